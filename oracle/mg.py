@@ -1,0 +1,284 @@
+"""Smoothers, eigenvalue estimate, hierarchy, V-cycle, multigrid solver and MG-preconditioned CG.
+
+Test infrastructure only (see the package docstring).
+
+* Jacobi: x <- x + omega D^{-1} (b - A x), omega = 2/3 (§3.2.2, §4.3).
+* Chebyshev-accelerated Jacobi targeting [lambda/4, lambda] of D^{-1} A (§3.2.1, §3.2.2,
+  §4.3). The paper gives no recurrence; this is the preconditioned Chebyshev iteration of
+  Saad, Iterative Methods for Sparse Linear Systems (2nd ed.), Alg. 12.1, with D^{-1} as the
+  preconditioner: after k steps the error is T_k((theta - lambda)/delta) / T_k(theta/delta)
+  times its initial value on every generalized eigenpair A v = lambda D v.
+* lambda_max of D^{-1} A from 10 Arnoldi steps in setup (§3.2.2, §4.3): Arnoldi on D^{-1} A in
+  the D inner product is Lanczos on the symmetric D^{-1/2} A D^{-1/2}; full
+  reorthogonalization, m = min(10, number of unknowns) steps, start vector from SplitMix64.
+* Hierarchy (§3.1, §4.3): h-multigrid keeps p and halves the elements per axis; p-multigrid
+  takes p -> ceil(p/2) down to 1 and then halves the elements; every level is rediscretized
+  with its own mesh, order and mu at its own quadrature points (§2.3). A coarser level is
+  added only while it keeps at least one interior unknown.
+* V-cycle with zero initial guess, nu pre- and post-smoothing steps per level, restriction
+  P^T, exact (dense Cholesky) solve on the coarsest level.
+* Multigrid as solver: x <- x + V(b - A x). PCG: Algorithm 1 with one V-cycle per iteration.
+  Both stop when ||r||_2 <= rtol ||r_0||_2 (§4.3: the discrete residual norm); the count is
+  the number of V-cycles applied to update x.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import scipy.linalg as sla
+
+from .fem import LevelOperator, Mesh, load_vector, nodal_field
+from .splitmix import start_vector
+from .transfer import Transfer
+
+
+def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0):
+    """List of (nelem, p) from fine to coarse."""
+    nelem = tuple(int(v) for v in nelem)
+
+    def interior(ne, q):
+        return int(np.prod([v * q - 1 for v in ne]))
+
+    levels = [(nelem, int(p))]
+    ne, q = nelem, int(p)
+    if hierarchy == "p":
+        while q > 1:
+            q = (q + 1) // 2
+            levels.append((ne, q))
+    elif hierarchy != "h":
+        raise ValueError("hierarchy must be 'h' or 'p'")
+    while all(v % 2 == 0 for v in ne) and interior(tuple(v // 2 for v in ne), q) >= 1:
+        ne = tuple(v // 2 for v in ne)
+        levels.append((ne, q))
+    if max_levels and max_levels > 0:
+        levels = levels[:max_levels]
+    return levels
+
+
+def jacobi(op: LevelOperator, dinv, b, x, nu, omega=2.0 / 3.0):
+    """nu damped-Jacobi sweeps; x = None means a zero initial guess."""
+    for _ in range(nu):
+        r = b.copy() if x is None else b - op.apply(x)
+        x = (np.zeros_like(b) if x is None else x) + omega * dinv * r
+    return x
+
+
+def chebyshev(op: LevelOperator, dinv, lmax, b, x, k, lo=0.25):
+    """Degree-k Chebyshev-Jacobi on [lo*lmax, lmax]; x = None means a zero initial guess."""
+    beta = lmax
+    alpha = lo * lmax
+    theta = 0.5 * (beta + alpha)
+    delta = 0.5 * (beta - alpha)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    if x is None:
+        r = b.copy()
+        x = np.zeros_like(b)
+    else:
+        r = b - op.apply(x)
+    d = dinv * r / theta
+    for i in range(1, k + 1):
+        x = x + d
+        if i < k:
+            r = r - op.apply(d)
+            rho_new = 1.0 / (2.0 * sigma - rho)
+            d = rho_new * rho * d + (2.0 * rho_new / delta) * dinv * r
+            rho = rho_new
+    return x
+
+
+def lanczos_lmax(op: LevelOperator, dinv, v0, steps=10, reorth_passes=2):
+    """Largest Ritz value of S = D^{-1/2} A D^{-1/2} after m = min(steps, n) Lanczos steps
+    with full reorthogonalization. Returns (lambda, alphas, betas)."""
+    s = np.sqrt(dinv)
+    nint = int(np.count_nonzero(dinv))
+    m = min(steps, nint)
+    v = v0 * (dinv != 0)
+    v = v / np.linalg.norm(v)
+    V = [v]
+    alphas, betas = [], []
+    tnorm = 0.0
+    for j in range(m):
+        w = s * op.apply(s * V[j])
+        a = float(V[j] @ w)
+        w = w - a * V[j]
+        if j > 0:
+            w = w - betas[-1] * V[j - 1]
+        for _ in range(reorth_passes):
+            for vi in V:
+                w = w - float(vi @ w) * vi
+        alphas.append(a)
+        bnext = float(np.linalg.norm(w))
+        tnorm = max(tnorm, abs(a) + (betas[-1] if betas else 0.0) + bnext)
+        if j == m - 1 or bnext <= 1e-14 * tnorm:
+            break
+        betas.append(bnext)
+        V.append(w / bnext)
+    T = np.diag(alphas)
+    for i, bt in enumerate(betas[:len(alphas) - 1]):
+        T[i, i + 1] = T[i + 1, i] = bt
+    lam = float(np.max(np.linalg.eigvalsh(T)))
+    return lam, alphas, betas[:len(alphas) - 1]
+
+
+@dataclass
+class Level:
+    mesh: Mesh
+    op: LevelOperator
+    dinv: np.ndarray
+    lmax: float = 0.0
+    to_coarse: Optional[Transfer] = None     # transfer between this level and the next coarser
+    chol: object = None                      # coarsest level: Cholesky factor of A_II
+    idx: Optional[np.ndarray] = None
+
+
+class Hierarchy:
+    def __init__(self, dim, nelem, p, map_desc, mu_desc, hierarchy="p", max_levels=0,
+                 smoother="chebyshev", nu=4, omega=2.0 / 3.0, cheb_lo=0.25, cheb_safety=1.0,
+                 eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False):
+        self.smoother, self.nu, self.omega = smoother, nu, omega
+        self.cheb_lo, self.cheb_safety = cheb_lo, cheb_safety
+        self.plan = plan_levels(dim, nelem, p, hierarchy, max_levels)
+        self.levels: List[Level] = []
+        for (ne, q) in self.plan:
+            mesh = Mesh(dim, ne, q, map_desc, mu_desc)
+            op = LevelOperator(mesh)
+            dg = op.diag()
+            dinv = np.zeros_like(dg)
+            dinv[mesh.interior] = 1.0 / dg[mesh.interior]
+            self.levels.append(Level(mesh=mesh, op=op, dinv=dinv))
+        for li in range(len(self.levels) - 1):
+            self.levels[li].to_coarse = Transfer(self.levels[li].mesh,
+                                                 self.levels[li + 1].mesh, direct_transfer)
+        for li, lv in enumerate(self.levels[:-1]):
+            if lmax_override is not None:
+                lv.lmax = float(lmax_override[li])
+            else:
+                v0 = start_vector(eig_seed, li, lv.mesh.N)
+                lam, _, _ = lanczos_lmax(lv.op, lv.dinv, v0, eig_steps)
+                lv.lmax = cheb_safety * lam
+        last = self.levels[-1]
+        Ad, idx = last.op.dense_interior()
+        last.idx = idx
+        last.chol = sla.cho_factor(Ad, lower=True) if len(idx) else None
+
+    @property
+    def fine(self) -> Level:
+        return self.levels[0]
+
+    def apply(self, li, x):
+        return self.levels[li].op.apply(x)
+
+    def smooth(self, li, b, x, steps=None):
+        lv = self.levels[li]
+        k = self.nu if steps is None else steps
+        if self.smoother == "jacobi":
+            return jacobi(lv.op, lv.dinv, b, x, k, self.omega)
+        return chebyshev(lv.op, lv.dinv, lv.lmax, b, x, k, self.cheb_lo)
+
+    def coarse_solve(self, b):
+        lv = self.levels[-1]
+        x = np.zeros_like(b)
+        if lv.chol is not None:
+            x[lv.idx] = sla.cho_solve(lv.chol, b[lv.idx])
+        return x
+
+    def vcycle(self, r, li=0):
+        """e = V r with zero initial guess on level li."""
+        if li == len(self.levels) - 1:
+            return self.coarse_solve(r)
+        lv = self.levels[li]
+        x = self.smooth(li, r, None)
+        res = r - lv.op.apply(x)
+        ec = self.vcycle(lv.to_coarse.restrict(res), li + 1)
+        x = x + lv.to_coarse.prolong(ec)
+        return self.smooth(li, r, x)
+
+    def applies(self):
+        return [lv.op.applies for lv in self.levels]
+
+
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    iters: int
+    converged: bool
+    history: List[float] = field(default_factory=list)
+    relres_true: float = float("nan")
+
+
+def mg_solve(H: Hierarchy, b, x0=None, rtol=1e-10, maxit=1000):
+    op = H.fine.op
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - op.apply(x) if x0 is not None else b.copy()
+    n0 = float(np.linalg.norm(r))
+    hist = [n0]
+    if n0 == 0.0:
+        return SolveResult(x, 0, True, hist, 0.0)
+    for it in range(1, maxit + 1):
+        x = x + H.vcycle(r)
+        r = b - op.apply(x)
+        nr = float(np.linalg.norm(r))
+        hist.append(nr)
+        if nr <= rtol * n0:
+            return SolveResult(x, it, True, hist, nr / n0)
+        if not math.isfinite(nr):
+            break
+    return SolveResult(x, len(hist) - 1, False, hist, hist[-1] / n0)
+
+
+def pcg(H: Hierarchy, b, x0=None, rtol=1e-10, maxit=500, precond=None):
+    """Algorithm 1: h = A p; alpha = (z, r) / (p, h); x += alpha p; r -= alpha h; test;
+    z = V r; beta = (z, r)_new / (z, r)_old; p = z + beta p."""
+    op = H.fine.op
+    M = H.vcycle if precond is None else precond
+    x = np.zeros_like(b) if x0 is None else x0.copy()
+    r = b - op.apply(x) if x0 is not None else b.copy()
+    n0 = float(np.linalg.norm(r))
+    hist = [n0]
+    if n0 == 0.0:
+        return SolveResult(x, 0, True, hist, 0.0)
+    z = M(r)
+    p = z.copy()
+    gamma = float(z @ r)
+    for it in range(1, maxit + 1):
+        h = op.apply(p)
+        alpha = gamma / float(p @ h)
+        x = x + alpha * p
+        r = r - alpha * h
+        nr = float(np.linalg.norm(r))
+        hist.append(nr)
+        if nr <= rtol * n0:
+            rt = float(np.linalg.norm(b - op.apply(x))) / n0
+            return SolveResult(x, it, True, hist, rt)
+        if not math.isfinite(nr):
+            break
+        z = M(r)
+        gnew = float(z @ r)
+        beta = gnew / gamma
+        gamma = gnew
+        p = z + beta * p
+    return SolveResult(x, len(hist) - 1, False, hist, hist[-1] / n0)
+
+
+def build_problem(prob, **kw):
+    """Hierarchy and right-hand side for a problem description from the seeded inputs."""
+    H = Hierarchy(prob.dim, prob.nelem, prob.order, prob.map, prob.mu,
+                  hierarchy=prob.hierarchy, max_levels=prob.max_levels,
+                  smoother=prob.smoother, nu=prob.nu, eig_seed=prob.eig_seed, **kw)
+    fn = prob.nodal_rhs()
+    if fn is None:
+        fn = nodal_field(H.fine.mesh, prob.f)
+    b = load_vector(H.fine.mesh, fn)
+    return H, b
+
+
+def solve(prob, **kw):
+    H, b = build_problem(prob, **kw)
+    if prob.mode == "mg":
+        return H, b, mg_solve(H, b, rtol=prob.rtol, maxit=prob.maxit)
+    return H, b, pcg(H, b, rtol=prob.rtol, maxit=prob.maxit)

@@ -1,0 +1,206 @@
+/*
+ * gllmg — matrix-free high-order continuous-FE multigrid on AMD MI355X (gfx950).
+ *
+ * The method is the one compared by Sundar, Stadler and Biros, "Comparison of Multigrid
+ * Algorithms for High-order Continuous Finite Element Discretizations": the Poisson problem
+ * -div(mu grad u) = f with u = 0 on the boundary (§2, Eq. (Poisson)), discretized with
+ * tensorized GLL nodal bases of order p <= 16 on a structured quad/hex mesh of the image of
+ * the unit square/cube under a smooth map (§2.3), solved with h- or p-multigrid V-cycles
+ * (§3.1) using Jacobi or Chebyshev-accelerated Jacobi smoothing (§3.2), as a solver or as
+ * the preconditioner of CG (Algorithm 1). The operator is never assembled: every product
+ * with A runs as a sum-factorized element kernel (§2.3, the O(p^4) tensorized matvec).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns a gllmg_status; no C++ exception crosses this interface. On any
+ *   status other than GLLMG_OK, gllmg_last_error() returns a message (thread-local, valid
+ *   until the next call on the same thread). On error, outputs are left untouched except
+ *   where a function says otherwise (GLLMG_ENOTCONV).
+ * - Vectors are DEVICE pointers owned by the caller (for example the data pointer of a
+ *   contiguous torch tensor), of the precision named by the gllmg_prec argument: double for
+ *   GLLMG_F64, float for GLLMG_F32. A level vector has nnodes entries (gllmg_level_info):
+ *   the nodes of the (n_x p + 1) x (n_y p + 1) [x (n_z p + 1)] grid, lexicographic with x
+ *   fastest, g = i_x + N_x (i_y + N_y i_z). Entries at boundary nodes are ignored on input
+ *   (treated as 0) and written as 0 on output (homogeneous Dirichlet data).
+ * - Pointers must be aligned to their element size; input and output vectors must not alias
+ *   unless a function says so.
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream). All device work
+ *   of a call is enqueued on it. Functions marked "asynchronous" return without waiting;
+ *   the others synchronize the stream before returning.
+ * - Levels are numbered 0 (finest) to nlevels-1 (coarsest).
+ * - A problem is not reentrant: calls on one problem must not overlap. Distinct problems may
+ *   be used concurrently from different threads on different streams.
+ */
+#ifndef GLLMG_H
+#define GLLMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GLLMG_OK = 0,
+  GLLMG_EINVAL = 1,       /* invalid argument, field or map (mu <= 0, detJ <= 0, ...)      */
+  GLLMG_ENOMEM = 2,       /* workspace too small, or device allocation failed              */
+  GLLMG_EDEVICE = 3,      /* a HIP runtime call failed                                     */
+  GLLMG_ENOTCONV = 4,     /* a solve reached maxit; x holds the last iterate, stats filled */
+  GLLMG_EBREAKDOWN = 5,   /* NaN/Inf residual or a non-positive curvature p^T A p          */
+  GLLMG_EUNSUPPORTED = 6  /* the request needs data the problem was not set up with        */
+} gllmg_status;
+
+typedef enum { GLLMG_F64 = 0, GLLMG_F32 = 1 } gllmg_prec;
+
+enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1 };
+enum { GLLMG_SMOOTH_JACOBI = 0, GLLMG_SMOOTH_CHEBYSHEV = 1 };
+enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1 };
+
+/* Field families, evaluated on the device at every level's nodes (physical coordinates
+ * x = Phi(X) for coefficients and right-hand sides, reference coordinates X for maps).
+ *   MAP_IDENTITY      Phi(X) = X
+ *   MAP_WARP_SINE     3D: Phi = (X + a sY sZ, Y + a sZ sX, Z + a sX sY), sW = sin(2 pi W);
+ *                     2D: Phi = (X + a sY, Y + a sX);            param[0] = a
+ *   MAP_AFFINE        Phi(X) = M X + c; param = M (d*d, row-major) then c (d)
+ *   CONST             param[0]
+ *   EXP_SINE_PRODUCT  exp(param[0] prod_i sin(2 pi (x_i + param[1+i])))
+ *   EXP_FOURIER       exp(sqrt(2/J) sum_j a_j cos(2 pi k_j.x + phi_j)); nmodes = J and
+ *                     modes = host array of J rows [k0, k1, k2, a, phi] (copied at setup)
+ *   SIN_PRODUCT       param[0] prod_i sin(param[1] pi x_i)
+ *   COS2_SUM          param[0] + param[1] sum_i cos^2(param[2] pi x_i)   (paper §4.1 form) */
+enum {
+  GLLMG_MAP_IDENTITY = 0, GLLMG_MAP_WARP_SINE = 1, GLLMG_MAP_AFFINE = 2,
+  GLLMG_FIELD_CONST = 10, GLLMG_FIELD_EXP_SINE_PRODUCT = 11, GLLMG_FIELD_EXP_FOURIER = 12,
+  GLLMG_FIELD_SIN_PRODUCT = 13, GLLMG_FIELD_COS2_SUM = 14
+};
+#define GLLMG_MAX_MODES 64
+
+typedef struct {
+  int32_t kind;
+  int32_t nmodes;
+  double param[12];
+  const double* modes;   /* host pointer, nmodes x 5 doubles, or NULL */
+} gllmg_field;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3                                                        */
+  int32_t nelem[3];       /* elements per axis (>= 1); nelem[2] ignored in 2D              */
+  int32_t order;          /* polynomial order p, 1..16                                     */
+  int32_t hierarchy;      /* GLLMG_HIER_H: fixed p, halve elements; GLLMG_HIER_P: p -> ceil(p/2)
+                             down to 1, then halve elements (§3.1.1, §3.1.2, §4.3)           */
+  int32_t max_levels;     /* 0: as many levels as the rule allows; else keep the finest k  */
+  int32_t smoother;       /* GLLMG_SMOOTH_JACOBI or GLLMG_SMOOTH_CHEBYSHEV                  */
+  int32_t nu_pre;         /* Jacobi sweeps / Chebyshev degree before the coarse correction  */
+  int32_t nu_post;        /* ... and after it                                              */
+  double omega;           /* Jacobi damping (the paper uses 2/3)                           */
+  double cheb_lo;         /* Chebyshev interval [cheb_lo * lambda, lambda] (paper: 1/4)    */
+  double cheb_safety;     /* lambda = cheb_safety x the Ritz estimate                      */
+  int32_t eig_steps;      /* Lanczos/Arnoldi steps for lambda_max (paper: 10)             */
+  int32_t vcycle_prec;    /* GLLMG_F64, or GLLMG_F32 for the mixed-precision V-cycle        */
+  uint64_t eig_seed;      /* seed of the SplitMix64 start vector                           */
+} gllmg_config;
+
+typedef struct gllmg_problem gllmg_problem;
+
+typedef struct {
+  int32_t iters;            /* V-cycles applied (= CG iterations in PCG mode)              */
+  int32_t converged;
+  double relres;            /* ||r_k|| / ||r_0|| of the iteration's own residual            */
+  double relres_true;       /* ||b - A x|| / ||r_0|| recomputed at the end (FP64)          */
+  double t_solve_s;         /* wall time from entry to return                              */
+  int64_t applies[16];      /* operator products per level during the solve                */
+  double* history;          /* optional caller array of maxit+1 residual norms (or NULL)   */
+} gllmg_solve_stats;
+
+/* Last error message of this thread. */
+const char* gllmg_last_error(void);
+
+/* Paper defaults: P-hierarchy, Chebyshev degree 4 pre/post, omega 2/3, [lambda/4, lambda],
+ * 10 eigen steps, FP64 V-cycle. dim/nelem/order are left for the caller. */
+void gllmg_config_default(gllmg_config* cfg);
+
+/* Number of levels and device bytes a setup of cfg needs (the whole footprint: no device
+ * memory is allocated by any later call). */
+gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* device_bytes);
+
+/* Build the hierarchy: per level the geometric factors G = w mu detJ J^{-1} J^{-T} at every
+ * GLL point (§2.3), the operator diagonal (§3.2.1), lambda_max of D^{-1} A (§3.2.2), the
+ * transfer tables (§2.2) and, on the coarsest level, the dense inverse for the exact coarse
+ * solve (only if that level has at most 4096 interior unknowns; otherwise the problem still
+ * supports products and smoothing, and gllmg_vcycle / gllmg_solve return EUNSUPPORTED). device_ws / ws_bytes: caller memory of at least gllmg_plan's size, kept until
+ * gllmg_destroy (or NULL / 0: the library allocates it). Synchronous.
+ * Errors: EINVAL for bad sizes, mu <= 0 or non-finite at a node, detJ <= 0 at a point;
+ * ENOMEM if ws_bytes is too small. */
+gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const gllmg_field* mu,
+                         void* device_ws, size_t ws_bytes, void* stream, gllmg_problem** out);
+
+gllmg_status gllmg_destroy(gllmg_problem* prob);
+
+gllmg_status gllmg_num_levels(const gllmg_problem* prob, int32_t* nlevels);
+
+/* Sizes and the Chebyshev bound of one level. Any output pointer may be NULL. */
+gllmg_status gllmg_level_info(const gllmg_problem* prob, int32_t level, int64_t* nnodes,
+                              int64_t* ninterior, int32_t* order, int32_t nelem[3],
+                              double* lmax);
+
+/* Replace a level's lambda_max (for example to use an externally computed bound). */
+gllmg_status gllmg_set_lmax(gllmg_problem* prob, int32_t level, double lmax);
+
+/* Physical node coordinates x = Phi(X) of a level: out[g * dim + a]. FP64. Asynchronous. */
+gllmg_status gllmg_node_coords(const gllmg_problem* prob, int32_t level, double* out, void* stream);
+
+/* A field at a level's physical node coordinates (all nodes). FP64. Asynchronous. */
+gllmg_status gllmg_eval_field(const gllmg_problem* prob, int32_t level, const gllmg_field* f,
+                              double* out, void* stream);
+
+/* Load vector on the finest level: b_j = (f, phi_j) under GLL quadrature = (lumped mass)_j
+ * f_j for interior nodes, 0 on the boundary (§2.1). f_nodal, b: FP64. Asynchronous. */
+gllmg_status gllmg_rhs(const gllmg_problem* prob, const double* f_nodal, double* b, void* stream);
+
+/* diag(A_level) at interior nodes, 0 on the boundary (§3.2.1). Asynchronous. */
+gllmg_status gllmg_diag(const gllmg_problem* prob, int32_t level, gllmg_prec prec, void* d,
+                        void* stream);
+
+/* y = A_level x (§2.3 matrix-free product). neumann = 1 skips the boundary condition on both
+ * input and output (the full stiffness, whose null space holds the constants). x and y must
+ * not alias. GLLMG_F32 needs a problem set up with vcycle_prec = GLLMG_F32. Asynchronous. */
+gllmg_status gllmg_apply(const gllmg_problem* prob, int32_t level, gllmg_prec prec, int32_t neumann,
+                         const void* x, void* y, void* stream);
+
+/* `steps` Jacobi sweeps (omega) or one Chebyshev polynomial of degree `steps` on
+ * [cheb_lo lambda, lambda] of D^{-1} A (§3.2), updating x in place. zero_guess = 1 treats x as
+ * 0 on entry (one product fewer). Uses the level's internal scratch. Asynchronous. */
+gllmg_status gllmg_smooth(const gllmg_problem* prob, int32_t level, gllmg_prec prec, const void* b,
+                          void* x, int32_t steps, int32_t zero_guess, void* stream);
+
+/* xf = P xc from level fine_level+1 to fine_level: P_ij = phi_j^{coarse}(p_i), the coarse
+ * basis at the fine nodes in reference coordinates (§2.2, Eq. (Pstencil)). Asynchronous. */
+gllmg_status gllmg_prolong(const gllmg_problem* prob, int32_t fine_level, gllmg_prec prec,
+                           const void* xc, void* xf, void* stream);
+
+/* rc = P^T rf (the restriction, §2.2). Asynchronous. */
+gllmg_status gllmg_restrict(const gllmg_problem* prob, int32_t fine_level, gllmg_prec prec,
+                            const void* rf, void* rc, void* stream);
+
+/* e = V r: one V-cycle on the finest level with zero initial guess (§3, §4.3): nu_pre
+ * smoothing steps, residual, restriction, recursive coarse correction (exact solve on the
+ * coarsest level), prolongation, nu_post smoothing steps. prec selects the V-cycle
+ * precision (GLLMG_F32 for a problem set up with vcycle_prec = GLLMG_F32). Asynchronous. */
+gllmg_status gllmg_vcycle(const gllmg_problem* prob, gllmg_prec prec, const void* r, void* e,
+                          void* stream);
+
+/* Solve A x = b on the finest level. mode GLLMG_MODE_PCG: CG preconditioned by one V-cycle
+ * per iteration (Algorithm 1); GLLMG_MODE_MG: x += V (b - A x). The V-cycle runs in the
+ * problem's vcycle_prec; the outer iteration, residuals and dot products are FP64. Stops
+ * when ||r|| <= rtol ||r_0|| (§4.3). b, x: FP64 device vectors; x is the initial guess on
+ * entry. stats may be NULL. Synchronous. ENOTCONV: maxit reached (x = last iterate, stats
+ * filled). EBREAKDOWN: non-finite residual or p^T A p <= 0. */
+gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* b, double* x,
+                         double rtol, int32_t maxit, gllmg_solve_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLLMG_H */

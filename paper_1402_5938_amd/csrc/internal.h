@@ -1,0 +1,182 @@
+// Internal declarations of the gllmg library: level data, kernel launchers, host helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/gllmg.h"
+
+namespace gllmg {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  gllmg_status status;
+  Error(gllmg_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define GLLMG_HIP(call)                                                                   \
+  do {                                                                                    \
+    hipError_t _e = (call);                                                               \
+    if (_e != hipSuccess)                                                                 \
+      throw ::gllmg::Error(GLLMG_EDEVICE, std::string(#call) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+#define GLLMG_CHECK(cond, status, msg)                        \
+  do {                                                        \
+    if (!(cond)) throw ::gllmg::Error((status), (msg));       \
+  } while (0)
+
+// ------------------------------------------------------------------ fields (device view)
+struct FieldDev {
+  int kind;
+  int nmodes;
+  double param[12];
+  const double* modes;   // device pointer, nmodes x 5
+};
+
+// ------------------------------------------------------------------ mesh geometry (device view)
+struct Grid {
+  int dim;
+  int p;             // order
+  int ne[3];         // elements per axis (ne[2] = 1 in 2D)
+  int nn[3];         // nodes per axis = ne * p + 1 (nn[2] = 1 in 2D)
+  int64_t E;         // elements
+  int64_t N;         // nodes
+};
+
+// 1D transfer table of one axis between a fine and a coarse level.
+//  prolong:  out[J] = sum_{m < nw} pw[J*nw + m] * in[pstart[J] + m]
+//  restrict: out[I] = sum_{t in [rptr[I], rptr[I+1])} rw[t] * in[ridx[t]]
+struct Transfer1D {
+  int nf, nc, nw;
+  int* pstart;       // device
+  double* pw64;
+  float* pw32;
+  int* rptr;
+  int* ridx;
+  double* rw64;
+  float* rw32;
+};
+
+struct Level {
+  Grid g;
+  int n;                  // p + 1
+  int64_t nint;           // interior nodes
+  int64_t npts;           // E * n^d quadrature points
+  int ncomp;              // unique G entries per point (3 in 2D, 6 in 3D)
+  double* G64 = nullptr;  // [E][ncomp][n^d]
+  float* G32 = nullptr;
+  double* D64 = nullptr;  // n x n derivative matrix, D[i*n + l] = l_l'(xi_i)
+  float* D32 = nullptr;
+  double* xi64 = nullptr; // GLL nodes and weights of the level's order
+  double* w64 = nullptr;
+  double* dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double lmax = 0.0;
+  // V-cycle scratch in the V-cycle precision (and an FP64 set for FP64 calls)
+  void* vb[2] = {nullptr, nullptr};
+  void* vx[2] = {nullptr, nullptr};
+  void* vr[2] = {nullptr, nullptr};
+  void* vd[2] = {nullptr, nullptr};
+  void* vt[2] = {nullptr, nullptr};
+  // transfer to the next coarser level (if any)
+  bool has_coarse = false;
+  Transfer1D tr[3];
+  // exact solve (coarsest level): dense inverse of the interior block
+  double* Ainv64 = nullptr;
+  float* Ainv32 = nullptr;
+  int64_t applies = 0;
+};
+
+// bump allocator over one device region
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  bool dry = false;   // only count
+  void* take(size_t bytes) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + bytes;
+    if (dry) return nullptr;
+    if (used > size) throw Error(GLLMG_ENOMEM, "device workspace too small");
+    return base + off;
+  }
+};
+
+// ------------------------------------------------------------------ host reference element (FP64)
+struct RefElem {
+  int p;
+  std::vector<double> xi, w, D;   // D[i*(p+1)+l] = l_l'(xi_i)
+};
+RefElem ref_element(int p);
+// Lagrange basis of the order-p GLL nodes evaluated at point y: out[j] = l_j(y).
+void lagrange_at(const RefElem& re, double y, double* out);
+// Largest eigenvalue of the symmetric tridiagonal matrix (diag a[0..m-1], offdiag b[0..m-2]).
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b);
+// In-place inverse of a dense SPD matrix (row-major n x n) via Cholesky; false if not SPD.
+bool spd_inverse(std::vector<double>& A, int n);
+
+// ------------------------------------------------------------------ kernel launchers
+// precision index: 0 = double, 1 = float
+void launch_geometry(const Level& L, const FieldDev& map, const FieldDev& mu, double* G64,
+                     float* G32, double* wdet, int* flag, hipStream_t s);
+void launch_gather_full(const Level& L, const double* elem_vals, double* out, hipStream_t s);
+void launch_node_coords(const Grid& g, const double* xi, const FieldDev& map, double* out,
+                        hipStream_t s);
+void launch_eval_field(const Grid& g, const double* xi, const FieldDev& map, const FieldDev& f,
+                       double* out, hipStream_t s);
+void launch_rhs(const Grid& g, const double* mass, const double* f, double* b, hipStream_t s);
+void launch_diag(const Level& L, double* diag, double* F, hipStream_t s);
+void launch_dinv(const Grid& g, const double* diag, double* dinv64, float* dinv32, int* flag,
+                 hipStream_t s);
+
+void launch_apply(const Level& L, int prec, int neumann, const void* x, void* y, void* F,
+                  hipStream_t s);
+size_t face_buffer_elems(const Level& L);
+
+void launch_prolong(const Level& fine, const Level& coarse, int prec, const void* xc, void* xf,
+                    bool add, void* t1, void* t2, hipStream_t s);
+void launch_restrict(const Level& fine, const Level& coarse, int prec, const void* rf, void* rc,
+                     void* t1, void* t2, hipStream_t s);
+size_t transfer_temp_elems(const Level& fine, const Level& coarse);
+
+void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s);
+
+// elementwise vector kernels (prec 0 = double, 1 = float); scalars are passed in FP64
+void vec_copy(int prec, int64_t n, const void* a, void* out, hipStream_t s);
+void vec_zero(int prec, int64_t n, void* out, hipStream_t s);
+void vec_sub(int prec, int64_t n, const void* a, const void* b, void* out, hipStream_t s);  // a - b
+void vec_axpy(int prec, int64_t n, double alpha, const void* x, void* y, hipStream_t s);   // y += a x
+void vec_scale_mul(int prec, int64_t n, double alpha, const void* a, const void* b, void* out,
+                   hipStream_t s);                                                          // alpha a*b
+void vec_div(int64_t n, const double* a, double den, double* out, hipStream_t s);       // a / den
+void vec_sqrt(int64_t n, const double* a, double* out, hipStream_t s);
+void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
+                  hipStream_t s);                                        // y += sign * (*coef) x
+void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s);     // v = v ? 1/v : 0
+void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s);        // v = e_idx
+void cast_64_32(int64_t n, const double* a, float* out, hipStream_t s);
+void cast_32_64(int64_t n, const float* a, double* out, hipStream_t s);
+// Chebyshev / Jacobi fused updates
+void cheb_start(int prec, int64_t n, const void* b, const void* t, const void* dinv,
+                double inv_theta, void* r, void* d, hipStream_t s);
+void cheb_step(int prec, int64_t n, int x_from_zero, void* x, const void* rin, void* r,
+               const void* t, void* d, const void* dinv, double c1, double c2, hipStream_t s);
+void jacobi_step(int prec, int64_t n, int x_from_zero, void* x, const void* b, const void* t,
+                 const void* dinv, double omega, hipStream_t s);
+// deterministic dot products (FP64 result written to a device scalar)
+constexpr int kDotBlocks = 1024;
+void dot(int prec, int64_t n, const void* a, const void* b, double* partials, double* result,
+         hipStream_t s);
+// scalar(s) in device memory for the PCG iteration
+void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* x, double* r,
+                   const double* p, const double* h, double* partials, double* rr, hipStream_t s);
+void pcg_update_p(int64_t n, const double* scal, int i_num, int i_den, double* p,
+                  const double* z, hipStream_t s);
+void start_vector(const Grid& g, uint64_t seed, int level, double* v, hipStream_t s);
+
+}  // namespace gllmg

@@ -1,0 +1,464 @@
+// Streaming kernels: h/p transfers as separable 1D passes, the coarsest-level dense solve,
+// the fused smoother updates, deterministic dot products and the PCG vector updates.
+#include "internal.h"
+
+namespace gllmg {
+
+namespace {
+
+constexpr int kT = 256;
+inline unsigned nb(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
+
+// ------------------------------------------------------------------ transfers
+// The prolongation P_ij = phi_j^{coarse}(p_i) (paper §2.2, Eq. (Pstencil)) of a tensorized
+// basis on a structured mesh is the Kronecker product of 1D matrices, so x_f = P x_c runs as
+// one 1D pass per axis; the restriction P^T runs the transposed 1D passes. Each pass reads
+// `in` (dims = out dims except along `axis`, where it has `ilen` entries).
+template <typename T>
+__global__ void __launch_bounds__(kT)
+k_tpass(const T* __restrict__ in, T* __restrict__ out, int dim, int axis, int o0, int o1, int o2,
+        int ilen, int restrict_mode, const int* __restrict__ pstart, const T* __restrict__ pw,
+        int nw, const int* __restrict__ rptr, const int* __restrict__ ridx,
+        const T* __restrict__ rw, int in_mask, int out_mask, int add) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)o0 * o1 * o2;
+  if (t >= tot) return;
+  int c[3];
+  c[0] = (int)(t % o0);
+  c[1] = (int)((t / o0) % o1);
+  c[2] = (int)(t / ((int64_t)o0 * o1));
+  int idims[3] = {o0, o1, o2};
+  idims[axis] = ilen;
+  // input offset of the line through c along `axis`, and its stride
+  int cc[3] = {c[0], c[1], c[2]};
+  cc[axis] = 0;
+  const int64_t base = cc[0] + (int64_t)idims[0] * (cc[1] + (int64_t)idims[1] * cc[2]);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)idims[0] : (int64_t)idims[0] * idims[1]);
+  bool other_bnd = false;  // input boundary in the other axes (same coordinates as the output)
+  for (int a = 0; a < dim; ++a)
+    if (a != axis) other_bnd = other_bnd || c[a] == 0 || c[a] == idims[a] - 1;
+  const int J = c[axis];
+  T acc = T(0);
+  if (!(in_mask && other_bnd)) {
+    if (!restrict_mode) {
+      const int s0 = pstart[J];
+      for (int m = 0; m < nw; ++m) {
+        const int I = s0 + m;
+        if (in_mask && (I == 0 || I == ilen - 1)) continue;
+        acc += pw[J * nw + m] * in[base + stride * I];
+      }
+    } else {
+      for (int q = rptr[J]; q < rptr[J + 1]; ++q) {
+        const int I = ridx[q];
+        if (in_mask && (I == 0 || I == ilen - 1)) continue;
+        acc += rw[q] * in[base + stride * I];
+      }
+    }
+  }
+  if (out_mask) {
+    bool ob = false;
+    for (int a = 0; a < dim; ++a) {
+      const int od = a == 0 ? o0 : (a == 1 ? o1 : o2);
+      ob = ob || c[a] == 0 || c[a] == od - 1;
+    }
+    if (ob) acc = T(0);
+  }
+  out[t] = add ? out[t] + acc : acc;
+}
+
+template <typename T>
+void tpass(const Transfer1D& tb, int prec, const void* in, void* out, int dim, int axis,
+           int o0, int o1, int o2, int ilen, int restrict_mode, int in_mask, int out_mask, int add,
+           hipStream_t s) {
+  const T* pw = prec == 0 ? (const T*)tb.pw64 : (const T*)tb.pw32;
+  const T* rw = prec == 0 ? (const T*)tb.rw64 : (const T*)tb.rw32;
+  const int64_t tot = (int64_t)o0 * o1 * o2;
+  hipLaunchKernelGGL(k_tpass<T>, dim3(nb(tot)), dim3(kT), 0, s, (const T*)in, (T*)out, dim, axis,
+                     o0, o1, o2, ilen, restrict_mode, tb.pstart, pw, tb.nw, tb.rptr, tb.ridx, rw,
+                     in_mask, out_mask, add);
+  GLLMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void prolong_t(const Level& F, const Level& C, int prec, const void* xc, void* xf, bool add,
+               void* t1, void* t2, hipStream_t s) {
+  const int* nf = F.g.nn;
+  const int* nc = C.g.nn;
+  if (F.g.dim == 2) {
+    tpass<T>(F.tr[0], prec, xc, t1, 2, 0, nf[0], nc[1], 1, nc[0], 0, 1, 0, 0, s);
+    tpass<T>(F.tr[1], prec, t1, xf, 2, 1, nf[0], nf[1], 1, nc[1], 0, 0, 1, add ? 1 : 0, s);
+  } else {
+    tpass<T>(F.tr[0], prec, xc, t1, 3, 0, nf[0], nc[1], nc[2], nc[0], 0, 1, 0, 0, s);
+    tpass<T>(F.tr[1], prec, t1, t2, 3, 1, nf[0], nf[1], nc[2], nc[1], 0, 0, 0, 0, s);
+    tpass<T>(F.tr[2], prec, t2, xf, 3, 2, nf[0], nf[1], nf[2], nc[2], 0, 0, 1, add ? 1 : 0, s);
+  }
+}
+
+template <typename T>
+void restrict_t(const Level& F, const Level& C, int prec, const void* rf, void* rc, void* t1,
+                void* t2, hipStream_t s) {
+  const int* nf = F.g.nn;
+  const int* nc = C.g.nn;
+  if (F.g.dim == 2) {
+    tpass<T>(F.tr[0], prec, rf, t1, 2, 0, nc[0], nf[1], 1, nf[0], 1, 1, 0, 0, s);
+    tpass<T>(F.tr[1], prec, t1, rc, 2, 1, nc[0], nc[1], 1, nf[1], 1, 0, 1, 0, s);
+  } else {
+    tpass<T>(F.tr[0], prec, rf, t1, 3, 0, nc[0], nf[1], nf[2], nf[0], 1, 1, 0, 0, s);
+    tpass<T>(F.tr[1], prec, t1, t2, 3, 1, nc[0], nc[1], nf[2], nf[1], 1, 0, 0, 0, s);
+    tpass<T>(F.tr[2], prec, t2, rc, 3, 2, nc[0], nc[1], nc[2], nf[2], 1, 0, 1, 0, s);
+  }
+}
+
+// ------------------------------------------------------------------ coarsest level
+// x = A_II^{-1} b on the interior nodes (dense inverse, rows in lexicographic interior order),
+// 0 on the boundary.
+template <typename T>
+__global__ void __launch_bounds__(kT)
+k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* __restrict__ x,
+         Grid g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
+  const int gx = (int)(t % nx), gy = (int)((t / nx) % ny), gz = (int)(t / ((int64_t)nx * ny));
+  bool bnd = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1;
+  if (g.dim == 3) bnd = bnd || gz == 0 || gz == nz - 1;
+  if (bnd) {
+    x[t] = T(0);
+    return;
+  }
+  const int mx = nx - 2, my = ny - 2;
+  const int64_t row = (gx - 1) + (int64_t)mx * ((gy - 1) + (int64_t)my * (g.dim == 3 ? gz - 1 : 0));
+  T acc = T(0);
+  for (int64_t j = 0; j < nint; ++j) {
+    const int jx = (int)(j % mx), jy = (int)((j / mx) % my), jz = (int)(j / ((int64_t)mx * my));
+    const int64_t node = (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (g.dim == 3 ? jz + 1 : 0));
+    acc += Ainv[row * nint + j] * b[node];
+  }
+  x[t] = acc;
+}
+
+// ------------------------------------------------------------------ elementwise
+template <typename T> __global__ void k_copy(int64_t n, const T* a, T* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i];
+}
+template <typename T> __global__ void k_zero(int64_t n, T* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = T(0);
+}
+template <typename T> __global__ void k_sub(int64_t n, const T* a, const T* b, T* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] - b[i];
+}
+template <typename T> __global__ void k_axpy(int64_t n, T al, const T* x, T* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = y[i] + al * x[i];
+}
+template <typename T> __global__ void k_scale_mul(int64_t n, T al, const T* a, const T* b, T* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = al * a[i] * b[i];
+}
+__global__ void k_c6432(int64_t n, const double* a, float* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (float)a[i];
+}
+__global__ void k_c3264(int64_t n, const float* a, double* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = (double)a[i];
+}
+
+__global__ void k_div(int64_t n, const double* a, double den, double* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] / den;
+}
+__global__ void k_sqrt(int64_t n, const double* a, double* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = sqrt(a[i]);
+}
+__global__ void k_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = y[i] + (sign * coef[0]) * x[i];
+}
+template <typename T> __global__ void k_recip_masked(int64_t n, T* v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = v[i] != T(0) ? T(1) / v[i] : T(0);
+}
+__global__ void k_set_unit(int64_t n, int64_t idx, double* v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = i == idx ? 1.0 : 0.0;
+}
+
+// Chebyshev start: r = b - t (t = A x; t == nullptr means x = 0 and r = b), d = dinv r / theta.
+template <typename T>
+__global__ void k_cheb_start(int64_t n, const T* b, const T* t, const T* dinv, T theta, T* r, T* d) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T ri = b[i];
+  if (t) {
+    ri = ri - t[i];
+    r[i] = ri;
+  }
+  d[i] = dinv[i] * ri / theta;
+}
+
+// One Chebyshev step after t = A d: x += d; r = rin - t; d = c1 d + (c2 dinv) r.
+template <typename T>
+__global__ void k_cheb_step(int64_t n, int from_zero, T* x, const T* rin, T* r, const T* t, T* d,
+                            const T* dinv, T c1, T c2) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T di = d[i];
+  x[i] = from_zero ? di : x[i] + di;
+  const T ri = rin[i] - t[i];
+  r[i] = ri;
+  d[i] = c1 * di + (c2 * dinv[i]) * ri;
+}
+
+// Damped Jacobi: x += (omega dinv) (b - t), or x = (omega dinv) b from a zero guess.
+template <typename T>
+__global__ void k_jacobi(int64_t n, int from_zero, T* x, const T* b, const T* t, const T* dinv, T om) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (from_zero)
+    x[i] = (om * dinv[i]) * b[i];
+  else
+    x[i] = x[i] + (om * dinv[i]) * (b[i] - t[i]);
+}
+
+// ------------------------------------------------------------------ deterministic reductions
+// Each block accumulates a fixed strided subset in FP64 and reduces it by a fixed tree; a
+// single block then sums the partials in a fixed tree. Same inputs and sizes give bitwise
+// identical results.
+__device__ inline double block_sum(double v) {
+  __shared__ double sh[kT];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kT / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const T* b, double* part) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
+    acc += (double)a[i] * (double)b[i];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kT) acc += part[i];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) *out = s;
+}
+
+inline int dot_grid(int64_t n) {
+  int64_t g = (n + kT - 1) / kT;
+  return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
+}
+
+// alpha = scal[num] / scal[den]; x += alpha p; r -= alpha h; partial sums of r.r
+__global__ void __launch_bounds__(kT)
+k_pcg_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r, const double* p,
+         const double* h, double* part) {
+  const double al = scal[inum] / scal[iden];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    x[i] = x[i] + al * p[i];
+    const double ri = r[i] - al * h[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// beta = scal[num] / scal[den]; p = z + beta p
+__global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double be = scal[inum] / scal[iden];
+  p[i] = z[i] + be * p[i];
+}
+
+}  // namespace
+
+size_t transfer_temp_elems(const Level& F, const Level& C) {
+  const int* nf = F.g.nn;
+  const int* nc = C.g.nn;
+  size_t a, b;
+  if (F.g.dim == 2) {
+    a = (size_t)nf[0] * nc[1];
+    b = (size_t)nc[0] * nf[1];
+    return a > b ? a : b;
+  }
+  const size_t p1 = (size_t)nf[0] * nc[1] * nc[2], p2 = (size_t)nf[0] * nf[1] * nc[2];
+  const size_t r1 = (size_t)nc[0] * nf[1] * nf[2], r2 = (size_t)nc[0] * nc[1] * nf[2];
+  a = p1 > p2 ? p1 : p2;
+  b = r1 > r2 ? r1 : r2;
+  return a > b ? a : b;
+}
+
+void launch_prolong(const Level& F, const Level& C, int prec, const void* xc, void* xf, bool add,
+                    void* t1, void* t2, hipStream_t s) {
+  if (prec == 0)
+    prolong_t<double>(F, C, prec, xc, xf, add, t1, t2, s);
+  else
+    prolong_t<float>(F, C, prec, xc, xf, add, t1, t2, s);
+}
+
+void launch_restrict(const Level& F, const Level& C, int prec, const void* rf, void* rc, void* t1,
+                     void* t2, hipStream_t s) {
+  if (prec == 0)
+    restrict_t<double>(F, C, prec, rf, rc, t1, t2, s);
+  else
+    restrict_t<float>(F, C, prec, rf, rc, t1, t2, s);
+}
+
+void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_coarse<double>, dim3(nb(L.g.N)), dim3(kT), 0, s, L.Ainv64, L.nint,
+                       (const double*)b, (double*)x, L.g);
+  else
+    hipLaunchKernelGGL(k_coarse<float>, dim3(nb(L.g.N)), dim3(kT), 0, s, L.Ainv32, L.nint,
+                       (const float*)b, (float*)x, L.g);
+  GLLMG_HIP(hipGetLastError());
+}
+
+void vec_copy(int prec, int64_t n, const void* a, void* o, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_copy<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)a, (double*)o);
+  else
+    hipLaunchKernelGGL(k_copy<float>, dim3(nb(n)), dim3(kT), 0, s, n, (const float*)a, (float*)o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_zero(int prec, int64_t n, void* o, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_zero<double>, dim3(nb(n)), dim3(kT), 0, s, n, (double*)o);
+  else
+    hipLaunchKernelGGL(k_zero<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float*)o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_sub(int prec, int64_t n, const void* a, const void* b, void* o, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_sub<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)a,
+                       (const double*)b, (double*)o);
+  else
+    hipLaunchKernelGGL(k_sub<float>, dim3(nb(n)), dim3(kT), 0, s, n, (const float*)a,
+                       (const float*)b, (float*)o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_axpy(int prec, int64_t n, double al, const void* x, void* y, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_axpy<double>, dim3(nb(n)), dim3(kT), 0, s, n, al, (const double*)x, (double*)y);
+  else
+    hipLaunchKernelGGL(k_axpy<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float)al, (const float*)x,
+                       (float*)y);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_scale_mul(int prec, int64_t n, double al, const void* a, const void* b, void* o,
+                   hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_scale_mul<double>, dim3(nb(n)), dim3(kT), 0, s, n, al, (const double*)a,
+                       (const double*)b, (double*)o);
+  else
+    hipLaunchKernelGGL(k_scale_mul<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float)al,
+                       (const float*)a, (const float*)b, (float*)o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_div(int64_t n, const double* a, double den, double* o, hipStream_t s) {
+  hipLaunchKernelGGL(k_div, dim3(nb(n)), dim3(kT), 0, s, n, a, den, o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_sqrt(int64_t n, const double* a, double* o, hipStream_t s) {
+  hipLaunchKernelGGL(k_sqrt, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_dev, dim3(nb(n)), dim3(kT), 0, s, n, coef, sign, x, y);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_recip_masked<double>, dim3(nb(n)), dim3(kT), 0, s, n, (double*)v);
+  else
+    hipLaunchKernelGGL(k_recip_masked<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float*)v);
+  GLLMG_HIP(hipGetLastError());
+}
+void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_unit, dim3(nb(n)), dim3(kT), 0, s, n, idx, v);
+  GLLMG_HIP(hipGetLastError());
+}
+void cast_64_32(int64_t n, const double* a, float* o, hipStream_t s) {
+  hipLaunchKernelGGL(k_c6432, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
+  GLLMG_HIP(hipGetLastError());
+}
+void cast_32_64(int64_t n, const float* a, double* o, hipStream_t s) {
+  hipLaunchKernelGGL(k_c3264, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
+  GLLMG_HIP(hipGetLastError());
+}
+void cheb_start(int prec, int64_t n, const void* b, const void* t, const void* dinv, double theta,
+                void* r, void* d, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_cheb_start<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)b,
+                       (const double*)t, (const double*)dinv, theta, (double*)r, (double*)d);
+  else
+    hipLaunchKernelGGL(k_cheb_start<float>, dim3(nb(n)), dim3(kT), 0, s, n, (const float*)b,
+                       (const float*)t, (const float*)dinv, (float)theta, (float*)r, (float*)d);
+  GLLMG_HIP(hipGetLastError());
+}
+void cheb_step(int prec, int64_t n, int from_zero, void* x, const void* rin, void* r, const void* t,
+               void* d, const void* dinv, double c1, double c2, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_cheb_step<double>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (double*)x,
+                       (const double*)rin, (double*)r, (const double*)t, (double*)d,
+                       (const double*)dinv, c1, c2);
+  else
+    hipLaunchKernelGGL(k_cheb_step<float>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (float*)x,
+                       (const float*)rin, (float*)r, (const float*)t, (float*)d,
+                       (const float*)dinv, (float)c1, (float)c2);
+  GLLMG_HIP(hipGetLastError());
+}
+void jacobi_step(int prec, int64_t n, int from_zero, void* x, const void* b, const void* t,
+                 const void* dinv, double om, hipStream_t s) {
+  if (prec == 0)
+    hipLaunchKernelGGL(k_jacobi<double>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (double*)x,
+                       (const double*)b, (const double*)t, (const double*)dinv, om);
+  else
+    hipLaunchKernelGGL(k_jacobi<float>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (float*)x,
+                       (const float*)b, (const float*)t, (const float*)dinv, (float)om);
+  GLLMG_HIP(hipGetLastError());
+}
+void dot(int prec, int64_t n, const void* a, const void* b, double* part, double* res,
+         hipStream_t s) {
+  const int g = dot_grid(n);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_dot_partial<double>, dim3(g), dim3(kT), 0, s, n, (const double*)a,
+                       (const double*)b, part);
+  else
+    hipLaunchKernelGGL(k_dot_partial<float>, dim3(g), dim3(kT), 0, s, n, (const float*)a,
+                       (const float*)b, part);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kT), 0, s, (const double*)part, g, res);
+  GLLMG_HIP(hipGetLastError());
+}
+void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r,
+                   const double* p, const double* h, double* part, double* rr, hipStream_t s) {
+  const int g = dot_grid(n);
+  hipLaunchKernelGGL(k_pcg_xr, dim3(g), dim3(kT), 0, s, n, scal, inum, iden, x, r, p, h, part);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kT), 0, s, (const double*)part, g, rr);
+  GLLMG_HIP(hipGetLastError());
+}
+void pcg_update_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_p, dim3(nb(n)), dim3(kT), 0, s, n, scal, inum, iden, p, z);
+  GLLMG_HIP(hipGetLastError());
+}
+
+}  // namespace gllmg

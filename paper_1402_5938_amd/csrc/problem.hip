@@ -1,0 +1,927 @@
+// Host side of the library: hierarchy planning, workspace layout, setup, smoothers, V-cycle,
+// solvers and the C ABI declared in include/gllmg.h.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "internal.h"
+
+namespace gllmg {
+
+namespace {
+
+struct LevelSpec {
+  int ne[3];
+  int p;
+};
+
+int64_t interior_count(int dim, const int ne[3], int p) {
+  int64_t c = 1;
+  for (int a = 0; a < dim; ++a) c *= (int64_t)ne[a] * p - 1;
+  return c;
+}
+
+void validate(const gllmg_config& c) {
+  GLLMG_CHECK(c.dim == 2 || c.dim == 3, GLLMG_EINVAL, "dim must be 2 or 3");
+  GLLMG_CHECK(c.order >= 1 && c.order <= 16, GLLMG_EINVAL, "order must be in [1, 16]");
+  for (int a = 0; a < c.dim; ++a)
+    GLLMG_CHECK(c.nelem[a] >= 1 && (int64_t)c.nelem[a] * c.order + 1 < (1 << 30), GLLMG_EINVAL,
+                "nelem out of range");
+  GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P, GLLMG_EINVAL,
+              "hierarchy must be GLLMG_HIER_H or GLLMG_HIER_P");
+  GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV,
+              GLLMG_EINVAL, "unknown smoother");
+  GLLMG_CHECK(c.nu_pre >= 0 && c.nu_post >= 0 && c.nu_pre <= 64 && c.nu_post <= 64, GLLMG_EINVAL,
+              "smoothing steps out of range");
+  GLLMG_CHECK(c.omega > 0.0 && c.omega < 2.0, GLLMG_EINVAL, "omega out of range");
+  GLLMG_CHECK(c.cheb_lo > 0.0 && c.cheb_lo < 1.0, GLLMG_EINVAL, "cheb_lo must be in (0, 1)");
+  GLLMG_CHECK(c.cheb_safety > 0.0, GLLMG_EINVAL, "cheb_safety must be positive");
+  GLLMG_CHECK(c.eig_steps >= 1 && c.eig_steps <= 64, GLLMG_EINVAL, "eig_steps out of range");
+  GLLMG_CHECK(c.vcycle_prec == GLLMG_F64 || c.vcycle_prec == GLLMG_F32, GLLMG_EINVAL,
+              "vcycle_prec must be GLLMG_F64 or GLLMG_F32");
+  GLLMG_CHECK(c.max_levels >= 0, GLLMG_EINVAL, "max_levels must be >= 0");
+  int ne[3] = {c.nelem[0], c.nelem[1], c.dim == 3 ? c.nelem[2] : 1};
+  GLLMG_CHECK(interior_count(c.dim, ne, c.order) >= 1, GLLMG_EINVAL,
+              "the mesh has no interior node");
+}
+
+// Levels from fine to coarse (§3.1, §4.3): h-hierarchy keeps p; p-hierarchy takes
+// p -> ceil(p/2) down to 1; then elements are halved while every axis is even and the coarser
+// mesh keeps an interior node.
+std::vector<LevelSpec> plan_levels(const gllmg_config& c) {
+  std::vector<LevelSpec> L;
+  LevelSpec s{{c.nelem[0], c.nelem[1], c.dim == 3 ? c.nelem[2] : 1}, c.order};
+  L.push_back(s);
+  if (c.hierarchy == GLLMG_HIER_P)
+    while (s.p > 1) {
+      s.p = (s.p + 1) / 2;
+      L.push_back(s);
+    }
+  for (;;) {
+    bool even = true;
+    for (int a = 0; a < c.dim; ++a) even = even && (s.ne[a] % 2 == 0);
+    if (!even) break;
+    LevelSpec t = s;
+    for (int a = 0; a < c.dim; ++a) t.ne[a] /= 2;
+    if (interior_count(c.dim, t.ne, t.p) < 1) break;
+    s = t;
+    L.push_back(s);
+  }
+  if (c.max_levels > 0 && (int)L.size() > c.max_levels) L.resize(c.max_levels);
+  return L;
+}
+
+Grid make_grid(int dim, const LevelSpec& s) {
+  Grid g{};
+  g.dim = dim;
+  g.p = s.p;
+  g.E = 1;
+  g.N = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.ne[a] = a < dim ? s.ne[a] : 1;
+    g.nn[a] = a < dim ? s.ne[a] * s.p + 1 : 1;
+    g.E *= g.ne[a];
+    g.N *= g.nn[a];
+  }
+  return g;
+}
+
+constexpr int64_t kMaxCoarse = 4096;
+
+}  // namespace
+
+}  // namespace gllmg
+
+using namespace gllmg;
+
+struct gllmg_problem {
+  gllmg_config cfg;
+  std::vector<Level> L;
+  std::vector<RefElem> re;
+  FieldDev map{}, mu{};
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool owns_ws = false;
+  double* mass = nullptr;
+  void* F = nullptr;
+  void* T1 = nullptr;
+  void* T2 = nullptr;
+  double* scal = nullptr;
+  double* part = nullptr;
+  int* flag = nullptr;
+  double* map_modes = nullptr;
+  double* mu_modes = nullptr;
+  double* pr = nullptr;  // FP64 fine-level solve vectors
+  double* pz = nullptr;
+  double* pp = nullptr;
+  double* ph = nullptr;
+  double* pt = nullptr;
+  char* scratch = nullptr;   // start of the region shared by setup temporaries and solve vectors
+  size_t scratch_bytes = 0;
+  double* hbuf = nullptr;    // pinned host scalars
+  int vprec = 0;             // V-cycle precision index
+};
+
+namespace gllmg {
+namespace {
+
+// Lay out (or only size) the whole device footprint.
+size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
+  const gllmg_config& c = P->cfg;
+  const bool f32 = c.vcycle_prec == GLLMG_F32;
+  P->L.resize(specs.size());
+  size_t face = 0, ttmp = 0;
+  for (size_t l = 0; l < specs.size(); ++l) {
+    Level& L = P->L[l];
+    L.g = make_grid(c.dim, specs[l]);
+    L.n = specs[l].p + 1;
+    L.nint = interior_count(c.dim, L.g.ne, L.g.p);
+    L.ncomp = c.dim == 3 ? 6 : 3;
+    L.npts = L.g.E * (c.dim == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n);
+    L.has_coarse = l + 1 < specs.size();
+    const int n = L.n;
+    L.D64 = (double*)A.take(sizeof(double) * n * n);
+    L.D32 = (float*)A.take(sizeof(float) * n * n);
+    L.xi64 = (double*)A.take(sizeof(double) * n);
+    L.w64 = (double*)A.take(sizeof(double) * n);
+    L.G64 = (double*)A.take(sizeof(double) * L.npts * L.ncomp);
+    L.G32 = f32 ? (float*)A.take(sizeof(float) * L.npts * L.ncomp) : nullptr;
+    L.dinv64 = (double*)A.take(sizeof(double) * L.g.N);
+    L.dinv32 = f32 ? (float*)A.take(sizeof(float) * L.g.N) : nullptr;
+    face = std::max(face, face_buffer_elems(L));
+    if (!L.has_coarse && L.nint <= kMaxCoarse) {
+      // the exact coarse solve exists only up to kMaxCoarse unknowns; a larger coarsest level
+      // still supports products and smoothing, and vcycle/solve report EUNSUPPORTED
+      L.Ainv64 = (double*)A.take(sizeof(double) * L.nint * L.nint);
+      L.Ainv32 = f32 ? (float*)A.take(sizeof(float) * L.nint * L.nint) : nullptr;
+    }
+  }
+  for (size_t l = 0; l + 1 < specs.size(); ++l) {
+    Level& F = P->L[l];
+    Level& C = P->L[l + 1];
+    ttmp = std::max(ttmp, transfer_temp_elems(F, C));
+    for (int a = 0; a < c.dim; ++a) {
+      Transfer1D& t = F.tr[a];
+      t.nf = F.g.nn[a];
+      t.nc = C.g.nn[a];
+      t.nw = C.n;
+      t.pstart = (int*)A.take(sizeof(int) * t.nf);
+      t.pw64 = (double*)A.take(sizeof(double) * t.nf * t.nw);
+      t.pw32 = (float*)A.take(sizeof(float) * t.nf * t.nw);
+      t.rptr = (int*)A.take(sizeof(int) * (t.nc + 1));
+      t.ridx = (int*)A.take(sizeof(int) * t.nf * t.nw);
+      t.rw64 = (double*)A.take(sizeof(double) * t.nf * t.nw);
+      t.rw32 = (float*)A.take(sizeof(float) * t.nf * t.nw);
+    }
+  }
+  const int64_t N0 = P->L[0].g.N;
+  P->mass = (double*)A.take(sizeof(double) * N0);
+  P->F = A.take(sizeof(double) * std::max<size_t>(face, 1));
+  P->T1 = A.take(sizeof(double) * std::max<size_t>(ttmp, 1));
+  P->T2 = A.take(sizeof(double) * std::max<size_t>(ttmp, 1));
+  P->scal = (double*)A.take(sizeof(double) * 64);
+  P->part = (double*)A.take(sizeof(double) * kDotBlocks);
+  P->flag = (int*)A.take(sizeof(int) * 4);
+  P->map_modes = (double*)A.take(sizeof(double) * 5 * GLLMG_MAX_MODES);
+  P->mu_modes = (double*)A.take(sizeof(double) * 5 * GLLMG_MAX_MODES);
+  // scratch: solve vectors in steady state, setup temporaries during setup
+  const size_t before = A.used;
+  P->scratch = (char*)A.take(0);
+  P->pr = (double*)A.take(sizeof(double) * N0);
+  P->pz = (double*)A.take(sizeof(double) * N0);
+  P->pp = (double*)A.take(sizeof(double) * N0);
+  P->ph = (double*)A.take(sizeof(double) * N0);
+  P->pt = (double*)A.take(sizeof(double) * N0);
+  for (auto& L : P->L) {
+    const int64_t N = L.g.N;
+    for (int pr = 0; pr < (f32 ? 2 : 1); ++pr) {
+      const size_t es = pr == 0 ? sizeof(double) : sizeof(float);
+      L.vb[pr] = A.take(es * N);
+      L.vx[pr] = A.take(es * N);
+      L.vr[pr] = A.take(es * N);
+      L.vd[pr] = A.take(es * N);
+      L.vt[pr] = A.take(es * N);
+    }
+  }
+  const size_t steady = A.used - before;
+  int64_t maxN = 0;
+  for (auto& L : P->L) maxN = std::max(maxN, L.g.N);
+  const size_t setup = sizeof(double) * (size_t)std::max<int64_t>(
+                                            (int64_t)c.eig_steps * maxN + 4 * maxN,
+                                            P->L[0].npts + maxN) + 4096;
+  if (setup > steady) A.take(setup - steady);
+  P->scratch_bytes = A.used - before;
+  return A.used + 256;
+}
+
+FieldDev to_dev(const gllmg_field* f, double* dev_modes, hipStream_t s, bool is_map) {
+  FieldDev d{};
+  GLLMG_CHECK(f != nullptr, GLLMG_EINVAL, "field is NULL");
+  d.kind = f->kind;
+  if (is_map)
+    GLLMG_CHECK(f->kind == GLLMG_MAP_IDENTITY || f->kind == GLLMG_MAP_WARP_SINE ||
+                    f->kind == GLLMG_MAP_AFFINE,
+                GLLMG_EINVAL, "unknown map kind");
+  else
+    GLLMG_CHECK(f->kind >= GLLMG_FIELD_CONST && f->kind <= GLLMG_FIELD_COS2_SUM, GLLMG_EINVAL,
+                "unknown field kind");
+  for (int i = 0; i < 12; ++i) d.param[i] = f->param[i];
+  d.nmodes = 0;
+  d.modes = dev_modes;
+  if (!is_map && f->kind == GLLMG_FIELD_EXP_FOURIER) {
+    GLLMG_CHECK(f->nmodes >= 1 && f->nmodes <= GLLMG_MAX_MODES && f->modes, GLLMG_EINVAL,
+                "EXP_FOURIER needs 1..64 modes");
+    d.nmodes = f->nmodes;
+    GLLMG_HIP(hipMemcpyAsync(dev_modes, f->modes, sizeof(double) * 5 * f->nmodes,
+                             hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+  }
+  return d;
+}
+
+double read_scalar(gllmg_problem* P, int idx, hipStream_t s) {
+  GLLMG_HIP(hipMemcpyAsync(P->hbuf, P->scal + idx, sizeof(double), hipMemcpyDeviceToHost, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+  return P->hbuf[0];
+}
+
+void read_scalars(gllmg_problem* P, int idx, int cnt, double* out, hipStream_t s) {
+  GLLMG_HIP(hipMemcpyAsync(P->hbuf, P->scal + idx, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < cnt; ++i) out[i] = P->hbuf[i];
+}
+
+void apply_level(gllmg_problem* P, int l, int pr, int neumann, const void* x, void* y, hipStream_t s) {
+  Level& L = P->L[l];
+  launch_apply(L, pr, neumann, x, y, P->F, s);
+  ++L.applies;
+}
+
+void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
+  Level& F = P->L[l];
+  Level& C = P->L[l + 1];
+  const RefElem& rf = P->re[l];
+  const RefElem& rc = P->re[l + 1];
+  const bool ptype = F.g.p != C.g.p;
+  for (int a = 0; a < F.g.dim; ++a) {
+    Transfer1D& t = F.tr[a];
+    const int nef = F.g.ne[a], pf = F.g.p, pc = C.g.p, nw = t.nw;
+    std::vector<int> pstart(t.nf);
+    std::vector<double> pw((size_t)t.nf * nw);
+    for (int J = 0; J < t.nf; ++J) {
+      int ef = std::min(J / pf, nef - 1);
+      const int i = J - ef * pf;
+      int ec;
+      double xc;
+      if (ptype) {
+        ec = ef;
+        xc = rf.xi[i];
+      } else {
+        ec = ef / 2;
+        const int ch = ef % 2;
+        xc = (rf.xi[i] + 2.0 * ch - 1.0) / 2.0;
+      }
+      pstart[J] = ec * pc;
+      lagrange_at(rc, xc, &pw[(size_t)J * nw]);
+    }
+    // transpose: for each coarse index the (fine index, weight) pairs, fine index ascending
+    std::vector<std::vector<std::pair<int, double>>> cols(t.nc);
+    for (int J = 0; J < t.nf; ++J)
+      for (int m = 0; m < nw; ++m) {
+        const double v = pw[(size_t)J * nw + m];
+        if (v != 0.0) cols[pstart[J] + m].push_back({J, v});
+      }
+    std::vector<int> rptr(t.nc + 1, 0), ridx;
+    std::vector<double> rw;
+    for (int I = 0; I < t.nc; ++I) {
+      for (auto& pr : cols[I]) {
+        ridx.push_back(pr.first);
+        rw.push_back(pr.second);
+      }
+      rptr[I + 1] = (int)ridx.size();
+    }
+    GLLMG_CHECK(ridx.size() <= (size_t)t.nf * nw, GLLMG_EINVAL, "transfer table overflow");
+    std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
+    GLLMG_HIP(hipMemcpy(t.pstart, pstart.data(), sizeof(int) * t.nf, hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(t.pw64, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(t.pw32, pw32.data(), sizeof(float) * pw32.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(t.rptr, rptr.data(), sizeof(int) * rptr.size(), hipMemcpyHostToDevice));
+    if (!ridx.empty()) {
+      GLLMG_HIP(hipMemcpy(t.ridx, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice));
+      GLLMG_HIP(hipMemcpy(t.rw64, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice));
+      GLLMG_HIP(hipMemcpy(t.rw32, rw32.data(), sizeof(float) * rw32.size(), hipMemcpyHostToDevice));
+    }
+  }
+  (void)s;
+}
+
+// lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
+// S = D^{-1/2} A D^{-1/2} with full reorthogonalization (two modified Gram-Schmidt passes),
+// m = min(eig_steps, interior unknowns) steps, SplitMix64 start vector; breakdown when
+// beta <= 1e-14 ||T||. Returns the largest eigenvalue of the tridiagonal T_m.
+double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
+  Level& L = P->L[l];
+  const int64_t N = L.g.N;
+  const int m = (int)std::min<int64_t>(P->cfg.eig_steps, L.nint);
+  double* base = (double*)P->scratch;
+  std::vector<double*> V(m + 1);
+  for (int i = 0; i <= m; ++i) V[i] = base + (size_t)i * N;
+  // m+1 basis vectors, w, t and sqrt(dinv): (m + 4) N doubles <= the setup scratch
+  double* w = base + (size_t)(m + 1) * N;
+  double* t = w + N;
+  double* sqd = t + N;
+  vec_sqrt(N, L.dinv64, sqd, s);
+  start_vector(L.g, P->cfg.eig_seed, l, V[0], s);
+  dot(0, N, V[0], V[0], P->part, P->scal + 8, s);
+  const double nrm0 = std::sqrt(read_scalar(P, 8, s));
+  vec_div(N, V[0], nrm0, V[0], s);
+  std::vector<double> al, be;
+  double tnorm = 0.0;
+  for (int j = 0; j < m; ++j) {
+    vec_scale_mul(0, N, 1.0, sqd, V[j], t, s);
+    apply_level(P, l, 0, 0, t, w, s);
+    vec_scale_mul(0, N, 1.0, sqd, w, w, s);
+    dot(0, N, V[j], w, P->part, P->scal + 9, s);
+    vec_axpy_dev(N, P->scal + 9, -1.0, V[j], w, s);
+    if (j > 0) vec_axpy(0, N, -be.back(), V[j - 1], w, s);
+    for (int pass = 0; pass < 2; ++pass)
+      for (int i = 0; i <= j; ++i) {
+        dot(0, N, V[i], w, P->part, P->scal + 10, s);
+        vec_axpy_dev(N, P->scal + 10, -1.0, V[i], w, s);
+      }
+    dot(0, N, w, w, P->part, P->scal + 11, s);
+    double sc[3];
+    read_scalars(P, 9, 3, sc, s);
+    const double a = sc[0];
+    const double bn = std::sqrt(sc[2]);
+    al.push_back(a);
+    tnorm = std::max(tnorm, std::fabs(a) + (be.empty() ? 0.0 : be.back()) + bn);
+    if (j == m - 1 || bn <= 1e-14 * tnorm) break;
+    be.push_back(bn);
+    vec_div(N, w, bn, V[j + 1], s);
+  }
+  be.resize(al.size() - 1);
+  return tridiag_max_eig(al, be);
+}
+
+void build_coarse_inverse(gllmg_problem* P, hipStream_t s) {
+  Level& L = P->L.back();
+  const int64_t N = L.g.N, ni = L.nint;
+  double* e = (double*)P->scratch;
+  double* y = e + N;
+  std::vector<double> A((size_t)ni * ni), col(N);
+  const int mx = L.g.nn[0] - 2, my = L.g.nn[1] - 2;
+  auto node_of = [&](int64_t j) {
+    const int jx = (int)(j % mx), jy = (int)((j / mx) % my), jz = (int)(j / ((int64_t)mx * my));
+    return (jx + 1) + (int64_t)L.g.nn[0] * ((jy + 1) + (int64_t)L.g.nn[1] * (L.g.dim == 3 ? jz + 1 : 0));
+  };
+  for (int64_t j = 0; j < ni; ++j) {
+    set_unit(N, node_of(j), e, s);
+    apply_level(P, (int)P->L.size() - 1, 0, 0, e, y, s);
+    GLLMG_HIP(hipMemcpyAsync(col.data(), y, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < ni; ++i) A[(size_t)i * ni + j] = col[node_of(i)];
+  }
+  // symmetrize the rounding of the matrix-free products
+  for (int64_t i = 0; i < ni; ++i)
+    for (int64_t j = 0; j < i; ++j) {
+      const double v = 0.5 * (A[(size_t)i * ni + j] + A[(size_t)j * ni + i]);
+      A[(size_t)i * ni + j] = A[(size_t)j * ni + i] = v;
+    }
+  GLLMG_CHECK(spd_inverse(A, (int)ni), GLLMG_EINVAL, "coarsest operator is not SPD");
+  std::vector<float> A32(A.begin(), A.end());
+  GLLMG_HIP(hipMemcpy(L.Ainv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice));
+  if (L.Ainv32)
+    GLLMG_HIP(hipMemcpy(L.Ainv32, A32.data(), sizeof(float) * A32.size(), hipMemcpyHostToDevice));
+  L.applies = 0;
+}
+
+void check_flag(gllmg_problem* P, hipStream_t s) {
+  int f = 0;
+  GLLMG_HIP(hipMemcpyAsync(&f, P->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+  GLLMG_CHECK(!(f & 1), GLLMG_EINVAL, "detJ <= 0 at a quadrature point: the map is not a diffeomorphism");
+  GLLMG_CHECK(!(f & 2), GLLMG_EINVAL, "mu is not positive and finite at a quadrature point");
+  GLLMG_CHECK(!(f & 4), GLLMG_EINVAL, "the operator diagonal is not positive");
+}
+
+void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu, hipStream_t s) {
+  const gllmg_config& c = P->cfg;
+  const bool f32 = c.vcycle_prec == GLLMG_F32;
+  P->map = to_dev(map, P->map_modes, s, true);
+  P->mu = to_dev(mu, P->mu_modes, s, false);
+  GLLMG_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
+  P->re.clear();
+  for (auto& L : P->L) {
+    P->re.push_back(ref_element(L.g.p));
+    const RefElem& r = P->re.back();
+    std::vector<float> D32(r.D.begin(), r.D.end());
+    GLLMG_HIP(hipMemcpy(L.D64, r.D.data(), sizeof(double) * r.D.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(L.xi64, r.xi.data(), sizeof(double) * r.xi.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpy(L.w64, r.w.data(), sizeof(double) * r.w.size(), hipMemcpyHostToDevice));
+  }
+  for (size_t l = 0; l < P->L.size(); ++l) {
+    Level& L = P->L[l];
+    double* wdet = l == 0 ? (double*)P->scratch : nullptr;
+    launch_geometry(L, P->map, P->mu, L.G64, f32 ? L.G32 : nullptr, wdet, P->flag, s);
+    if (l == 0) launch_gather_full(L, wdet, P->mass, s);
+    check_flag(P, s);
+    double* diag = (double*)P->scratch;
+    launch_diag(L, diag, (double*)P->F, s);
+    launch_dinv(L.g, diag, L.dinv64, f32 ? L.dinv32 : nullptr, P->flag, s);
+    check_flag(P, s);
+  }
+  for (size_t l = 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
+  for (size_t l = 0; l < P->L.size(); ++l)
+    if (P->L[l].has_coarse || !P->L[l].Ainv64)
+      P->L[l].lmax = c.cheb_safety * lanczos_lmax(P, (int)l, s);
+  if (P->L.back().Ainv64) build_coarse_inverse(P, s);
+  for (auto& L : P->L) L.applies = 0;
+  GLLMG_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ smoothers and cycles
+const void* dinv_of(const Level& L, int pr) { return pr == 0 ? (const void*)L.dinv64 : (const void*)L.dinv32; }
+
+void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k, bool zero,
+                 hipStream_t s) {
+  Level& L = P->L[l];
+  const int64_t N = L.g.N;
+  if (k <= 0) {
+    if (zero) vec_zero(pr, N, x, s);
+    return;
+  }
+  void* r = L.vr[pr];
+  void* d = L.vd[pr];
+  void* t = L.vt[pr];
+  const void* dinv = dinv_of(L, pr);
+  if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
+    for (int it = 0; it < k; ++it) {
+      if (it == 0 && zero) {
+        jacobi_step(pr, N, 1, x, b, nullptr, dinv, P->cfg.omega, s);
+      } else {
+        apply_level(P, l, pr, 0, x, t, s);
+        jacobi_step(pr, N, 0, x, b, t, dinv, P->cfg.omega, s);
+      }
+    }
+    return;
+  }
+  const double lam = L.lmax, alpha = P->cfg.cheb_lo * lam;
+  const double theta = 0.5 * (lam + alpha), delta = 0.5 * (lam - alpha);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  const void* rin;
+  if (zero) {
+    cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);
+    rin = b;
+  } else {
+    apply_level(P, l, pr, 0, x, t, s);
+    cheb_start(pr, N, b, t, dinv, theta, r, d, s);
+    rin = r;
+  }
+  for (int i = 1; i <= k; ++i) {
+    const bool first_zero = zero && i == 1;
+    if (i < k) {
+      apply_level(P, l, pr, 0, d, t, s);
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      cheb_step(pr, N, first_zero ? 1 : 0, x, rin, r, t, d, dinv, rn * rho, 2.0 * rn / delta, s);
+      rin = r;
+      rho = rn;
+    } else {
+      if (first_zero)
+        vec_copy(pr, N, d, x, s);
+      else
+        vec_axpy(pr, N, 1.0, d, x, s);
+    }
+  }
+}
+
+void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipStream_t s) {
+  Level& L = P->L[l];
+  if (!L.has_coarse) {
+    GLLMG_CHECK(L.Ainv64 != nullptr, GLLMG_EUNSUPPORTED,
+                "the coarsest level is too large for the dense exact solve; allow more levels");
+    launch_coarse_solve(L, pr, b, x, s);
+    return;
+  }
+  Level& C = P->L[l + 1];
+  smooth_impl(P, l, pr, b, x, P->cfg.nu_pre, true, s);
+  apply_level(P, l, pr, 0, x, L.vt[pr], s);
+  vec_sub(pr, L.g.N, b, L.vt[pr], L.vr[pr], s);
+  launch_restrict(L, C, pr, L.vr[pr], C.vb[pr], P->T1, P->T2, s);
+  vcycle_level(P, l + 1, pr, C.vb[pr], C.vx[pr], s);
+  launch_prolong(L, C, pr, C.vx[pr], x, true, P->T1, P->T2, s);
+  smooth_impl(P, l, pr, b, x, P->cfg.nu_post, false, s);
+}
+
+// z = V r for FP64 vectors r, z on the finest level, in the problem's V-cycle precision
+void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
+  Level& L = P->L[0];
+  if (P->vprec == 0) {
+    vcycle_level(P, 0, 0, r, z, s);
+  } else {
+    cast_64_32(L.g.N, r, (float*)L.vb[1], s);
+    vcycle_level(P, 0, 1, L.vb[1], L.vx[1], s);
+    cast_32_64(L.g.N, (const float*)L.vx[1], z, s);
+  }
+}
+
+enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
+
+gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, double rtol,
+                        int maxit, gllmg_solve_stats* st, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  Level& L = P->L[0];
+  const int64_t N = L.g.N;
+  std::vector<int64_t> a0;
+  for (auto& lv : P->L) a0.push_back(lv.applies);
+  double *r = P->pr, *z = P->pz, *p = P->pp, *h = P->ph;
+  apply_level(P, 0, 0, 0, x, h, s);
+  vec_sub(0, N, b, h, r, s);
+  dot(0, N, r, r, P->part, P->scal + S_RR, s);
+  const double n0 = std::sqrt(read_scalar(P, S_RR, s));
+  std::vector<double> hist{n0};
+  int iters = 0;
+  bool conv = n0 == 0.0;
+  bool breakdown = !std::isfinite(n0);
+  double nr = n0;
+  if (!conv && !breakdown) {
+    if (mode == GLLMG_MODE_PCG) {
+      precond(P, r, z, s);
+      dot(0, N, z, r, P->part, P->scal + S_G0, s);
+      vec_copy(0, N, z, p, s);
+      int g = S_G0;
+      for (int it = 1; it <= maxit; ++it) {
+        apply_level(P, 0, 0, 0, p, h, s);
+        dot(0, N, p, h, P->part, P->scal + S_PH, s);
+        pcg_update_xr(N, P->scal, g, S_PH, x, r, p, h, P->part, P->scal + S_RR, s);
+        double sc[2];
+        read_scalars(P, S_RR, 2, sc, s);
+        iters = it;
+        nr = std::sqrt(sc[0]);
+        hist.push_back(nr);
+        if (!(sc[1] > 0.0) || !std::isfinite(nr)) {
+          breakdown = true;
+          break;
+        }
+        if (nr <= rtol * n0) {
+          conv = true;
+          break;
+        }
+        precond(P, r, z, s);
+        const int gn = g == S_G0 ? S_G1 : S_G0;
+        dot(0, N, z, r, P->part, P->scal + gn, s);
+        pcg_update_p(N, P->scal, gn, g, p, z, s);
+        g = gn;
+      }
+    } else {
+      for (int it = 1; it <= maxit; ++it) {
+        precond(P, r, z, s);
+        vec_axpy(0, N, 1.0, z, x, s);
+        apply_level(P, 0, 0, 0, x, h, s);
+        vec_sub(0, N, b, h, r, s);
+        dot(0, N, r, r, P->part, P->scal + S_RR, s);
+        nr = std::sqrt(read_scalar(P, S_RR, s));
+        iters = it;
+        hist.push_back(nr);
+        if (!std::isfinite(nr)) {
+          breakdown = true;
+          break;
+        }
+        if (nr <= rtol * n0) {
+          conv = true;
+          break;
+        }
+      }
+    }
+  }
+  // true residual in FP64
+  double rt = 0.0;
+  if (n0 > 0.0 && std::isfinite(n0)) {
+    apply_level(P, 0, 0, 0, x, h, s);
+    vec_sub(0, N, b, h, P->pt, s);
+    dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, s);
+    rt = std::sqrt(read_scalar(P, S_B, s)) / n0;
+  }
+  GLLMG_HIP(hipStreamSynchronize(s));
+  if (st) {
+    st->iters = iters;
+    st->converged = conv ? 1 : 0;
+    st->relres = n0 > 0.0 ? nr / n0 : 0.0;
+    st->relres_true = rt;
+    for (int i = 0; i < 16; ++i) st->applies[i] = 0;
+    for (size_t i = 0; i < P->L.size() && i < 16; ++i) st->applies[i] = P->L[i].applies - a0[i];
+    if (st->history)
+      for (size_t i = 0; i < hist.size() && i <= (size_t)maxit; ++i) st->history[i] = hist[i];
+    st->t_solve_s =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (breakdown) throw Error(GLLMG_EBREAKDOWN, "breakdown: non-finite residual or p^T A p <= 0");
+  if (!conv) return GLLMG_ENOTCONV;
+  return GLLMG_OK;
+}
+
+thread_local std::string g_err;
+
+template <class Fn>
+gllmg_status guard(Fn&& fn) {
+  try {
+    return fn();
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    g_err = "host allocation failed";
+    return GLLMG_ENOMEM;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return GLLMG_EINVAL;
+  }
+}
+
+const Level& level_of(const gllmg_problem* P, int l) {
+  GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+  GLLMG_CHECK(l >= 0 && l < (int)P->L.size(), GLLMG_EINVAL, "level out of range");
+  return P->L[l];
+}
+
+int prec_index(const gllmg_problem* P, int prec) {
+  GLLMG_CHECK(prec == GLLMG_F64 || prec == GLLMG_F32, GLLMG_EINVAL, "bad precision");
+  if (prec == GLLMG_F32)
+    GLLMG_CHECK(P->cfg.vcycle_prec == GLLMG_F32, GLLMG_EUNSUPPORTED,
+                "FP32 data needs a problem set up with vcycle_prec = GLLMG_F32");
+  return prec == GLLMG_F64 ? 0 : 1;
+}
+
+void check_ptr(const void* p, size_t align, const char* what) {
+  GLLMG_CHECK(p != nullptr, GLLMG_EINVAL, std::string(what) + " is NULL");
+  GLLMG_CHECK(((uintptr_t)p % align) == 0, GLLMG_EINVAL, std::string(what) + " is misaligned");
+}
+
+}  // namespace
+}  // namespace gllmg
+
+extern "C" {
+
+const char* gllmg_last_error(void) { return gllmg::g_err.c_str(); }
+
+void gllmg_config_default(gllmg_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->dim = 3;
+  c->nelem[0] = c->nelem[1] = c->nelem[2] = 1;
+  c->order = 1;
+  c->hierarchy = GLLMG_HIER_P;
+  c->max_levels = 0;
+  c->smoother = GLLMG_SMOOTH_CHEBYSHEV;
+  c->nu_pre = 4;
+  c->nu_post = 4;
+  c->omega = 2.0 / 3.0;
+  c->cheb_lo = 0.25;
+  c->cheb_safety = 1.0;
+  c->eig_steps = 10;
+  c->vcycle_prec = GLLMG_F64;
+  c->eig_seed = 0;
+}
+
+gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* bytes) {
+  return guard([&]() {
+    GLLMG_CHECK(cfg != nullptr, GLLMG_EINVAL, "config is NULL");
+    validate(*cfg);
+    gllmg_problem tmp;
+    tmp.cfg = *cfg;
+    auto specs = plan_levels(*cfg);
+    Arena A;
+    A.dry = true;
+    const size_t tot = layout(&tmp, specs, A);
+    if (nlevels) *nlevels = (int32_t)specs.size();
+    if (bytes) *bytes = tot;
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const gllmg_field* mu,
+                         void* ws, size_t ws_bytes, void* stream, gllmg_problem** out) {
+  return guard([&]() {
+    GLLMG_CHECK(cfg != nullptr && out != nullptr, GLLMG_EINVAL, "NULL argument");
+    validate(*cfg);
+    hipStream_t s = (hipStream_t)stream;
+    std::unique_ptr<gllmg_problem> P(new gllmg_problem());
+    P->cfg = *cfg;
+    P->vprec = cfg->vcycle_prec == GLLMG_F32 ? 1 : 0;
+    auto specs = plan_levels(*cfg);
+    Arena dry;
+    dry.dry = true;
+    const size_t need = layout(P.get(), specs, dry);
+    if (ws) {
+      GLLMG_CHECK(ws_bytes >= need, GLLMG_ENOMEM, "workspace smaller than gllmg_plan's size");
+      GLLMG_CHECK(((uintptr_t)ws % 256) == 0, GLLMG_EINVAL, "workspace must be 256-byte aligned");
+      P->ws = (char*)ws;
+      P->ws_bytes = ws_bytes;
+    } else {
+      void* m = nullptr;
+      if (hipMalloc(&m, need) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(GLLMG_ENOMEM, "device allocation of the workspace failed");
+      }
+      P->ws = (char*)m;
+      P->ws_bytes = need;
+      P->owns_ws = true;
+    }
+    struct Free {
+      gllmg_problem* p;
+      bool armed = true;
+      ~Free() {
+        if (armed && p->owns_ws) (void)hipFree(p->ws);
+        if (armed && p->hbuf) (void)hipHostFree(p->hbuf);
+      }
+    } guard_free{P.get()};
+    Arena A;
+    A.base = P->ws;
+    A.size = P->ws_bytes;
+    layout(P.get(), specs, A);
+    GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
+    setup_impl(P.get(), map, mu, s);
+    guard_free.armed = false;
+    *out = P.release();
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_destroy(gllmg_problem* P) {
+  return guard([&]() {
+    if (!P) return GLLMG_OK;
+    if (P->owns_ws) (void)hipFree(P->ws);
+    if (P->hbuf) (void)hipHostFree(P->hbuf);
+    delete P;
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_num_levels(const gllmg_problem* P, int32_t* n) {
+  return guard([&]() {
+    GLLMG_CHECK(P && n, GLLMG_EINVAL, "NULL argument");
+    *n = (int32_t)P->L.size();
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_level_info(const gllmg_problem* P, int32_t level, int64_t* nnodes,
+                              int64_t* ninterior, int32_t* order, int32_t nelem[3], double* lmax) {
+  return guard([&]() {
+    const Level& L = level_of(P, level);
+    if (nnodes) *nnodes = L.g.N;
+    if (ninterior) *ninterior = L.nint;
+    if (order) *order = L.g.p;
+    if (nelem)
+      for (int a = 0; a < 3; ++a) nelem[a] = a < L.g.dim ? L.g.ne[a] : 0;
+    if (lmax) *lmax = L.lmax;
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_set_lmax(gllmg_problem* P, int32_t level, double lmax) {
+  return guard([&]() {
+    level_of(P, level);
+    GLLMG_CHECK(lmax > 0.0 && std::isfinite(lmax), GLLMG_EINVAL, "lmax must be positive");
+    P->L[level].lmax = lmax;
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_node_coords(const gllmg_problem* P, int32_t level, double* out, void* stream) {
+  return guard([&]() {
+    const Level& L = level_of(P, level);
+    check_ptr(out, 8, "out");
+    launch_node_coords(L.g, L.xi64, P->map, out, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_eval_field(const gllmg_problem* P, int32_t level, const gllmg_field* f,
+                              double* out, void* stream) {
+  return guard([&]() {
+    const Level& L = level_of(P, level);
+    check_ptr(out, 8, "out");
+    GLLMG_CHECK(f != nullptr, GLLMG_EINVAL, "field is NULL");
+    GLLMG_CHECK(f->kind != GLLMG_FIELD_EXP_FOURIER, GLLMG_EUNSUPPORTED,
+                "EXP_FOURIER fields are evaluated only as the coefficient");
+    FieldDev d{};
+    d.kind = f->kind;
+    for (int i = 0; i < 12; ++i) d.param[i] = f->param[i];
+    GLLMG_CHECK(f->kind >= GLLMG_FIELD_CONST && f->kind <= GLLMG_FIELD_COS2_SUM, GLLMG_EINVAL,
+                "unknown field kind");
+    launch_eval_field(L.g, L.xi64, P->map, d, out, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_rhs(const gllmg_problem* P, const double* f, double* b, void* stream) {
+  return guard([&]() {
+    const Level& L = level_of(P, 0);
+    check_ptr(f, 8, "f_nodal");
+    check_ptr(b, 8, "b");
+    launch_rhs(L.g, P->mass, f, b, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_diag(const gllmg_problem* P, int32_t level, gllmg_prec prec, void* d, void* stream) {
+  return guard([&]() {
+    const Level& L = level_of(P, level);
+    const int pr = prec_index(P, prec);
+    check_ptr(d, pr == 0 ? 8 : 4, "d");
+    hipStream_t s = (hipStream_t)stream;
+    // diag = 1 / dinv on the interior
+    vec_copy(pr, L.g.N, dinv_of(L, pr), d, s);
+    vec_recip_masked(pr, L.g.N, d, s);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_apply(const gllmg_problem* P, int32_t level, gllmg_prec prec, int32_t neumann,
+                         const void* x, void* y, void* stream) {
+  return guard([&]() {
+    level_of(P, level);
+    const int pr = prec_index(P, prec);
+    check_ptr(x, pr == 0 ? 8 : 4, "x");
+    check_ptr(y, pr == 0 ? 8 : 4, "y");
+    GLLMG_CHECK(x != y, GLLMG_EINVAL, "x and y must not alias");
+    apply_level(const_cast<gllmg_problem*>(P), level, pr, neumann ? 1 : 0, x, y, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_smooth(const gllmg_problem* P, int32_t level, gllmg_prec prec, const void* b,
+                          void* x, int32_t steps, int32_t zero_guess, void* stream) {
+  return guard([&]() {
+    level_of(P, level);
+    const int pr = prec_index(P, prec);
+    check_ptr(b, pr == 0 ? 8 : 4, "b");
+    check_ptr(x, pr == 0 ? 8 : 4, "x");
+    GLLMG_CHECK(steps >= 0 && steps <= 64, GLLMG_EINVAL, "steps out of range");
+    GLLMG_CHECK(P->cfg.smoother == GLLMG_SMOOTH_JACOBI || P->L[level].lmax > 0.0,
+                GLLMG_EUNSUPPORTED, "no Chebyshev bound on this level (coarsest level)");
+    smooth_impl(const_cast<gllmg_problem*>(P), level, pr, b, x, steps, zero_guess != 0,
+                (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_prolong(const gllmg_problem* P, int32_t fl, gllmg_prec prec, const void* xc,
+                           void* xf, void* stream) {
+  return guard([&]() {
+    level_of(P, fl);
+    level_of(P, fl + 1);
+    const int pr = prec_index(P, prec);
+    check_ptr(xc, pr == 0 ? 8 : 4, "xc");
+    check_ptr(xf, pr == 0 ? 8 : 4, "xf");
+    launch_prolong(P->L[fl], P->L[fl + 1], pr, xc, xf, false, P->T1, P->T2, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_restrict(const gllmg_problem* P, int32_t fl, gllmg_prec prec, const void* rf,
+                            void* rc, void* stream) {
+  return guard([&]() {
+    level_of(P, fl);
+    level_of(P, fl + 1);
+    const int pr = prec_index(P, prec);
+    check_ptr(rf, pr == 0 ? 8 : 4, "rf");
+    check_ptr(rc, pr == 0 ? 8 : 4, "rc");
+    launch_restrict(P->L[fl], P->L[fl + 1], pr, rf, rc, P->T1, P->T2, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_vcycle(const gllmg_problem* P, gllmg_prec prec, const void* r, void* e, void* stream) {
+  return guard([&]() {
+    level_of(P, 0);
+    const int pr = prec_index(P, prec);
+    check_ptr(r, pr == 0 ? 8 : 4, "r");
+    check_ptr(e, pr == 0 ? 8 : 4, "e");
+    GLLMG_CHECK(r != e, GLLMG_EINVAL, "r and e must not alias");
+    vcycle_level(const_cast<gllmg_problem*>(P), 0, pr, r, e, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_solve(const gllmg_problem* P, int32_t mode, const double* b, double* x,
+                         double rtol, int32_t maxit, gllmg_solve_stats* st, void* stream) {
+  return guard([&]() {
+    level_of(P, 0);
+    GLLMG_CHECK(mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG, GLLMG_EINVAL, "unknown mode");
+    check_ptr(b, 8, "b");
+    check_ptr(x, 8, "x");
+    GLLMG_CHECK(rtol > 0.0 && maxit >= 1, GLLMG_EINVAL, "rtol must be > 0 and maxit >= 1");
+    gllmg_status r = solve_impl(const_cast<gllmg_problem*>(P), mode, b, x, rtol, maxit, st,
+                                (hipStream_t)stream);
+    if (r == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached";
+    return r;
+  });
+}
+
+}  // extern "C"

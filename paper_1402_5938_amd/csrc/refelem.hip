@@ -1,0 +1,172 @@
+// Host reference element in FP64: GLL nodes and weights, the 1D derivative matrix, Lagrange
+// evaluation; plus the small dense/tridiagonal helpers of the setup phase.
+//
+// GLL points of order p (paper §1, §2.3, Fig. 1): -1, 1 and the p-1 zeros of P_p', which are
+// the zeros of the Jacobi polynomial P^{(1,1)}_{p-1}. Those are the eigenvalues of the
+// symmetric tridiagonal Jacobi matrix of P^{(1,1)} (Golub-Welsch): zero diagonal and
+// off-diagonal b_k = sqrt(k (k+2) / ((2k+1)(2k+3))), k = 1..p-2. They are found by Sturm
+// bisection and polished by Newton's method on P_{p-1} - x P_p. Weights: 2 / (p (p+1) P_p^2).
+// Derivative matrix (Deville, Fischer and Mund, cited in §1): D_ij = P_p(x_i) / (P_p(x_j)
+// (x_i - x_j)) for i != j, D_00 = -p(p+1)/4, D_pp = p(p+1)/4, D_ii = 0 otherwise.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace gllmg {
+
+static void legendre_pp(int p, double x, double* Pp, double* Pm1) {
+  double a = 1.0, b = x;  // P_0, P_1
+  for (int k = 1; k < p; ++k) {
+    double c = ((2.0 * k + 1.0) * x * b - k * a) / (k + 1.0);
+    a = b;
+    b = c;
+  }
+  *Pp = b;
+  *Pm1 = a;
+}
+
+// Number of eigenvalues < x of the symmetric tridiagonal (a, b) by the Sturm sequence.
+static int sturm_count(const std::vector<double>& a, const std::vector<double>& b, double x) {
+  int cnt = 0;
+  double q = 1.0;
+  const size_t m = a.size();
+  for (size_t i = 0; i < m; ++i) {
+    double bb = (i == 0) ? 0.0 : b[i - 1] * b[i - 1];
+    q = (a[i] - x) - (i == 0 ? 0.0 : bb / q);
+    if (q == 0.0) q = -1e-300;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+// k-th smallest eigenvalue (0-based) by bisection on [lo, hi].
+static double tridiag_eig_k(const std::vector<double>& a, const std::vector<double>& b, int k,
+                            double lo, double hi) {
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (sturm_count(a, b, mid) > k)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int m = (int)a.size();
+  if (m == 0) return 0.0;
+  double r = 0.0;  // Gershgorin bound
+  for (int i = 0; i < m; ++i) {
+    double s = std::fabs(a[i]);
+    if (i > 0) s += std::fabs(b[i - 1]);
+    if (i < m - 1) s += std::fabs(b[i]);
+    r = std::max(r, s);
+  }
+  r = r * (1.0 + 1e-12) + 1e-300;
+  return tridiag_eig_k(a, b, m - 1, -r, r);
+}
+
+RefElem ref_element(int p) {
+  GLLMG_CHECK(p >= 1 && p <= 32, GLLMG_EINVAL, "order out of range");
+  RefElem re;
+  re.p = p;
+  const int n = p + 1;
+  re.xi.assign(n, 0.0);
+  re.xi[0] = -1.0;
+  re.xi[p] = 1.0;
+  if (p >= 2) {
+    const int m = p - 1;
+    std::vector<double> a(m, 0.0), b(std::max(m - 1, 0));
+    for (int k = 1; k <= m - 1; ++k)
+      b[k - 1] = std::sqrt((double)k * (k + 2) / ((2.0 * k + 1.0) * (2.0 * k + 3.0)));
+    for (int k = 0; k < m; ++k) {
+      double x = tridiag_eig_k(a, b, k, -1.0, 1.0);
+      for (int it = 0; it < 3; ++it) {  // Newton on q(x) = P_{p-1} - x P_p, q' = -(p+1) P_p
+        double P, Pm1;
+        legendre_pp(p, x, &P, &Pm1);
+        x += (Pm1 - x * P) / ((p + 1.0) * P);
+      }
+      re.xi[k + 1] = x;
+    }
+    for (int k = 0; k < n / 2; ++k) {  // the rule is symmetric
+      double s = 0.5 * (re.xi[p - k] - re.xi[k]);
+      re.xi[k] = -s;
+      re.xi[p - k] = s;
+    }
+    if (p % 2 == 0) re.xi[p / 2] = 0.0;
+  }
+  std::vector<double> Pv(n);
+  re.w.resize(n);
+  for (int i = 0; i < n; ++i) {
+    double P, Pm1;
+    legendre_pp(p, re.xi[i], &P, &Pm1);
+    Pv[i] = P;
+    re.w[i] = 2.0 / (p * (p + 1.0) * P * P);
+  }
+  re.D.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (i != j) re.D[i * n + j] = Pv[i] / (Pv[j] * (re.xi[i] - re.xi[j]));
+  re.D[0] = -p * (p + 1.0) / 4.0;
+  re.D[n * n - 1] = p * (p + 1.0) / 4.0;
+  return re;
+}
+
+// Barycentric Lagrange evaluation (Berrut and Trefethen, SIAM Review 2004, "second form").
+void lagrange_at(const RefElem& re, double y, double* out) {
+  const int n = re.p + 1;
+  for (int j = 0; j < n; ++j)
+    if (y == re.xi[j]) {
+      for (int k = 0; k < n; ++k) out[k] = (k == j) ? 1.0 : 0.0;
+      return;
+    }
+  std::vector<double> lam(n);
+  for (int j = 0; j < n; ++j) {
+    double prod = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != j) prod *= (re.xi[j] - re.xi[k]);
+    lam[j] = 1.0 / prod;
+  }
+  double den = 0.0;
+  for (int j = 0; j < n; ++j) den += lam[j] / (y - re.xi[j]);
+  for (int j = 0; j < n; ++j) out[j] = (lam[j] / (y - re.xi[j])) / den;
+}
+
+bool spd_inverse(std::vector<double>& A, int n) {
+  // Cholesky A = L L^T (lower, in place)
+  for (int j = 0; j < n; ++j) {
+    double s = A[(size_t)j * n + j];
+    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
+    if (!(s > 0.0)) return false;
+    double ljj = std::sqrt(s);
+    A[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
+      A[(size_t)i * n + j] = t / ljj;
+    }
+  }
+  // invert L (lower) in place into Linv
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Li[(size_t)j * n + j] = 1.0 / A[(size_t)j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double t = 0.0;
+      for (int k = j; k < i; ++k) t += A[(size_t)i * n + k] * Li[(size_t)k * n + j];
+      Li[(size_t)i * n + j] = -t / A[(size_t)i * n + i];
+    }
+  }
+  // A^{-1} = L^{-T} L^{-1}
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double t = 0.0;
+      for (int k = i; k < n; ++k) t += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+      A[(size_t)i * n + j] = t;
+      A[(size_t)j * n + i] = t;
+    }
+  return true;
+}
+
+}  // namespace gllmg

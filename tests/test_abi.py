@@ -1,0 +1,61 @@
+"""The C-ABI library loads on the CPU host and exports every function include/gllmg.h declares;
+host-side argument checking is exercised without touching a GPU."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gllmg.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gllmg_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    from paper_1402_5938_amd import gllmg
+    lib = gllmg.lib()
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(gllmg.EXPORTS)
+
+
+def test_plan_and_validation_on_host():
+    from paper_1402_5938_amd import gllmg
+    cfg = gllmg.make_config(3, (16, 16, 16), 8, "p")
+    nl, nbytes = gllmg.plan(cfg)
+    assert nl == 7
+    # G in FP64 dominates: 6 words per GLL point of the finest level
+    assert nbytes > 6 * 8 * 4096 * 729
+    cfg2 = gllmg.make_config(2, (4, 4), 4, "h")
+    assert gllmg.plan(cfg2)[0] == 3
+    bad = gllmg.make_config(3, (2, 2, 2), 17, "p")
+    with pytest.raises(gllmg.GllmgError) as e:
+        gllmg.plan(bad)
+    assert e.value.status == gllmg.EINVAL
+    bad = gllmg.make_config(4, (2, 2, 2), 4, "p")
+    with pytest.raises(gllmg.GllmgError):
+        gllmg.plan(bad)
+    bad = gllmg.make_config(3, (1, 1, 1), 1, "p")       # no interior node
+    with pytest.raises(gllmg.GllmgError):
+        gllmg.plan(bad)
+    # literal reading of the 16^3 p=8 hierarchy: stop at p = 1 on 16^3 (3375 coarse unknowns)
+    assert gllmg.plan(gllmg.make_config(3, (16,) * 3, 8, "p", max_levels=4))[0] == 4
+    # a single level beyond the dense-solve limit is allowed (products and smoothing only)
+    assert gllmg.plan(gllmg.make_config(3, (16,) * 3, 8, "p", max_levels=1))[0] == 1
+
+
+def test_null_arguments_rejected():
+    from paper_1402_5938_amd import gllmg
+    lib = gllmg.lib()
+    assert lib.gllmg_plan(None, None, None) == gllmg.EINVAL
+    assert b"NULL" in lib.gllmg_last_error()
+    assert lib.gllmg_apply(None, 0, 0, 0, None, None, None) == gllmg.EINVAL
+    assert lib.gllmg_destroy(None) == gllmg.OK

@@ -147,6 +147,12 @@ gllmg_status gllmg_level_info(const gllmg_problem* prob, int32_t level, int64_t*
 /* Replace a level's lambda_max (for example to use an externally computed bound). */
 gllmg_status gllmg_set_lmax(gllmg_problem* prob, int32_t level, double lmax);
 
+/* Replay the solve's V-cycle from a HIP graph captured on first use (enable = 1, the
+ * default) or launch its kernels one by one (enable = 0). Both execute the same kernels in
+ * the same order and give bitwise identical results; the graph removes host launch gaps.
+ * The graph is rebuilt after gllmg_set_lmax. */
+gllmg_status gllmg_set_graphs(gllmg_problem* prob, int32_t enable);
+
 /* Physical node coordinates x = Phi(X) of a level: out[g * dim + a]. FP64. Asynchronous. */
 gllmg_status gllmg_node_coords(const gllmg_problem* prob, int32_t level, double* out, void* stream);
 

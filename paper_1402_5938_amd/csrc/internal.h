@@ -134,7 +134,28 @@ void launch_diag(const Level& L, double* diag, double* F, hipStream_t s);
 void launch_dinv(const Grid& g, const double* diag, double* dinv64, float* dinv32, int* flag,
                  hipStream_t s);
 
-void launch_apply(const Level& L, int prec, int neumann, const void* x, void* y, void* F,
+// What a product y = A x does with each output value (the update is fused into the product):
+//  STORE:    y = A x
+//  RESIDUAL: r = b - A x
+//  JACOBI:   x = x + (omega dinv) (b - A x)                    (in place; the input is x)
+//  CHEB_START: r = b - A x, d = dinv r / c1                    (c1 = theta)
+//  CHEB:     with t = A d: x = x + d (or x = d), r = rin - t,
+//            d = c1 d + (c2 dinv) r                             (in place; the input is d)
+// At Dirichlet boundary nodes every output is 0.
+enum EpiMode { EPI_STORE = 0, EPI_RESIDUAL = 1, EPI_JACOBI = 2, EPI_CHEB = 3, EPI_CHEB_START = 4 };
+struct Epi {
+  int mode = EPI_STORE;
+  int from_zero = 0;
+  void* y = nullptr;
+  const void* b = nullptr;
+  void* x = nullptr;
+  const void* rin = nullptr;
+  void* r = nullptr;
+  void* d = nullptr;
+  const void* dinv = nullptr;
+  double c1 = 0, c2 = 0, om = 0;
+};
+void launch_apply(const Level& L, int prec, int neumann, const void* x, const Epi& ep, void* F,
                   hipStream_t s);
 size_t face_buffer_elems(const Level& L);
 

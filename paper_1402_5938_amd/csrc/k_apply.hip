@@ -5,33 +5,92 @@
 //   u_b(q) = sum_l D[q_b, l] x_e(q with coordinate b -> l)          (d forward contractions)
 //   w_a(q) = sum_b G_ab(q) u_b(q)                                    (pointwise, G symmetric)
 //   y_e(i) = sum_a sum_m D[m, i_a] w_a(i with coordinate a -> m)     (d transposed contractions)
-// and y = sum_e Q_e^T y_e. The sum over elements is deterministic and atomic-free: a node in
-// the interior of an element has exactly one contribution, written directly; contributions
-// to nodes on element faces/edges/vertices go to a face buffer (compact per-element slots)
-// and a second kernel adds, for every such node, the 2, 4 or 8 slots in a fixed order.
-// Dirichlet data: boundary entries of x are read as 0 and boundary entries of y are set to 0.
+// and y = sum_e Q_e^T y_e. The sum over elements is deterministic and atomic-free: the element
+// kernel writes y_e contiguously into an element-vector buffer F[e][k][j][i]; a gather kernel
+// walks the nodes in vector order (x fastest) and adds the 1, 2, 4 or 8 element copies of
+// each node in a fixed order (lower element first per axis, x innermost). Every access of
+// the gather is coalesced for every order p. The gather ends with a per-node epilogue
+// (store, residual, Jacobi or Chebyshev update), so a smoothing step is two kernels and
+// never materializes A x.
+// Dirichlet data: boundary entries of x are read as 0 and A x is 0 at boundary nodes.
 #include "internal.h"
 
 namespace gllmg {
 
 namespace {
 
-// Compact slot of an element-boundary local node (i, j, k) of an n^3 element: the k = 0
-// plane (n^2), then for each 0 < k < n-1 the ring of the (i, j) plane (4(n-1)), then the
-// k = n-1 plane. 2D uses the ring alone.
-__host__ __device__ inline int slot_ring(int n, int i, int j) {
-  if (j == 0) return i;
-  if (j == n - 1) return n + 2 * (n - 2) + i;
-  return n + 2 * (j - 1) + (i == 0 ? 0 : 1);
+__host__ __device__ inline int nloc_of(int n, int dim) { return dim == 3 ? n * n * n : n * n; }
+
+// Typed view of the epilogue.
+template <typename T>
+struct EpiT {
+  int mode, from_zero;
+  T* y;
+  const T* b;
+  T* x;
+  const T* rin;
+  T* r;
+  T* d;
+  const T* dinv;
+  T c1, c2, om;
+};
+
+template <typename T>
+EpiT<T> typed(const Epi& e) {
+  return EpiT<T>{e.mode, e.from_zero, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
+                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
 }
-__host__ __device__ inline int slot3(int n, int i, int j, int k) {
-  const int R = 4 * (n - 1);
-  if (k == 0) return j * n + i;
-  if (k == n - 1) return n * n + (n - 2) * R + j * n + i;
-  return n * n + (k - 1) * R + slot_ring(n, i, j);
+
+// acc = (A xin)_g, xin = the input vector's value at g
+template <typename T>
+__device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
+  switch (ep.mode) {
+    case EPI_STORE:
+      ep.y[g] = acc;
+      break;
+    case EPI_RESIDUAL:
+      ep.r[g] = ep.b[g] - acc;
+      break;
+    case EPI_JACOBI:
+      ep.x[g] = xin + (ep.om * ep.dinv[g]) * (ep.b[g] - acc);
+      break;
+    case EPI_CHEB_START: {  // r = b - A x, d = dinv r / theta (theta in c1)
+      const T ri = ep.b[g] - acc;
+      ep.r[g] = ri;
+      ep.d[g] = ep.dinv[g] * ri / ep.c1;
+      break;
+    }
+    default: {  // EPI_CHEB, input vector is d
+      ep.x[g] = ep.from_zero ? xin : ep.x[g] + xin;
+      const T ri = ep.rin[g] - acc;
+      ep.r[g] = ri;
+      ep.d[g] = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
+    }
+  }
 }
-__host__ __device__ inline int nbnd(int n, int dim) {
-  return dim == 3 ? n * n * n - (n - 2) * (n - 2) * (n - 2) : n * n - (n - 2) * (n - 2);
+
+// Dirichlet boundary node: every output of the epilogue is 0 there.
+template <typename T>
+__device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
+  switch (ep.mode) {
+    case EPI_STORE:
+      ep.y[g] = T(0);
+      break;
+    case EPI_RESIDUAL:
+      ep.r[g] = T(0);
+      break;
+    case EPI_JACOBI:
+      ep.x[g] = T(0);
+      break;
+    case EPI_CHEB_START:
+      ep.r[g] = T(0);
+      ep.d[g] = T(0);
+      break;
+    default:
+      ep.x[g] = T(0);
+      ep.r[g] = T(0);
+      ep.d[g] = T(0);
+  }
 }
 
 // Elements per workgroup so that a workgroup has about 256 threads (n^2 threads per element).
@@ -41,24 +100,27 @@ struct Epb {
 };
 
 // ------------------------------------------------------------------ 3D element kernel
+// Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
+// y-contractions read the element tile from LDS, the z-contraction works in registers.
 template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB * N * N)
-k_apply3d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
-          const T* __restrict__ G, const T* __restrict__ Dm, Grid g, int neumann) {
+k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
+          const T* __restrict__ Dm, Grid g, int neumann) {
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
-  constexpr int NB = NNN - (N - 2) * (N - 2) * (N - 2);
   __shared__ T sA[EPB * NNN];
   __shared__ T sB[EPB * NNN];
   const int t = threadIdx.x;
   const int le = t / NN;
   const int ij = t - le * NN;
   const int i = ij % N, j = ij / N;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
-  const bool valid = e < g.E;
-  const int64_t ee = valid ? e : 0;
-  const int ex = (int)(ee % g.ne[0]);
-  const int ey = (int)((ee / g.ne[0]) % g.ne[1]);
-  const int ez = (int)(ee / ((int64_t)g.ne[0] * g.ne[1]));
+  const uint32_t e = blockIdx.x * EPB + le;
+  const bool valid = e < (uint32_t)g.E;
+  const uint32_t ee = valid ? e : 0u;
+  const uint32_t nexy = (uint32_t)g.ne[0] * (uint32_t)g.ne[1];
+  const int ez = (int)(ee / nexy);
+  const uint32_t rxy = ee - (uint32_t)ez * nexy;
+  const int ey = (int)(rxy / (uint32_t)g.ne[0]);
+  const int ex = (int)(rxy - (uint32_t)ey * g.ne[0]);
   const int gx = ex * P + i, gy = ey * P + j;
   const bool bxy = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
   const int64_t sxy = (int64_t)g.nn[0] * g.nn[1];
@@ -85,7 +147,7 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
   __syncthreads();
 
   T wx[N], wy[N], wz[N];
-  const T* Ge = G + ee * (6 * NNN) + ij;
+  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T ux = T(0), uy = T(0), uz = T(0);
@@ -115,7 +177,7 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
   }
   __syncthreads();
   if (!valid) return;
-  const bool inner_ij = i > 0 && i < N - 1 && j > 0 && j < N - 1;
+  T* Fe = F + (int64_t)e * NNN + ij;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T acc = T(0);
@@ -125,31 +187,27 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
       acc += DjT[l] * B[k * NN + l * N + i];
       acc += Dm[l * N + k] * wz[l];
     }
-    if (inner_ij && k > 0 && k < N - 1)
-      y[gb + sxy * k] = acc;
-    else
-      F[e * NB + slot3(N, i, j, k)] = acc;
+    Fe[k * NN] = acc;
   }
 }
 
 // ------------------------------------------------------------------ 2D element kernel
 template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB * N * N)
-k_apply2d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
-          const T* __restrict__ G, const T* __restrict__ Dm, Grid g, int neumann) {
+k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
+          const T* __restrict__ Dm, Grid g, int neumann) {
   constexpr int NN = N * N, P = N - 1;
-  constexpr int NB = 4 * (N - 1);
   __shared__ T sA[EPB * NN];
   __shared__ T sB[EPB * NN];
   const int t = threadIdx.x;
   const int le = t / NN;
   const int ij = t - le * NN;
   const int i = ij % N, j = ij / N;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
-  const bool valid = e < g.E;
-  const int64_t ee = valid ? e : 0;
-  const int ex = (int)(ee % g.ne[0]);
-  const int ey = (int)(ee / g.ne[0]);
+  const uint32_t e = blockIdx.x * EPB + le;
+  const bool valid = e < (uint32_t)g.E;
+  const uint32_t ee = valid ? e : 0u;
+  const int ey = (int)(ee / (uint32_t)g.ne[0]);
+  const int ex = (int)(ee - (uint32_t)ey * g.ne[0]);
   const int gx = ex * P + i, gy = ey * P + j;
   const bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
   const int64_t gi = gx + (int64_t)g.nn[0] * gy;
@@ -165,7 +223,7 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
     ux += Dm[i * N + l] * A[j * N + l];
     uy += Dm[j * N + l] * A[l * N + i];
   }
-  const T* Ge = G + ee * (3 * NN) + ij;
+  const T* Ge = G + (int64_t)ee * (3 * NN) + ij;
   const T g0 = Ge[0], g1 = Ge[NN], g2 = Ge[2 * NN];
   const T wx = g0 * ux + g1 * uy;
   const T wy = g1 * ux + g2 * uy;
@@ -180,75 +238,84 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ y, T* __restrict__ F,
     acc += Dm[l * N + i] * A[j * N + l];
     acc += Dm[l * N + j] * B[l * N + i];
   }
-  if (i > 0 && i < N - 1 && j > 0 && j < N - 1)
-    y[gi] = acc;
-  else
-    F[e * NB + slot_ring(N, i, j)] = acc;
+  F[(int64_t)e * NN + ij] = acc;
 }
 
-// ------------------------------------------------------------------ face sums
-// For every node on an element boundary: y[g] = sum of the face-buffer slots of the
-// elements containing it (lower element first along each axis, z outermost); 0 on the
-// domain boundary unless neumann.
+// ------------------------------------------------------------------ gather
+// containing elements of grid coordinate c along one axis: (element, local index), lower first
+__device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
+  const int e = c / p, r = c - e * p;
+  if (r != 0) {
+    ce[0] = e;
+    cl[0] = r;
+    return 1;
+  }
+  int k = 0;
+  if (e > 0) {
+    ce[k] = e - 1;
+    cl[k] = p;
+    ++k;
+  }
+  if (e < ne) {
+    ce[k] = e;
+    cl[k] = 0;
+    ++k;
+  }
+  return k;
+}
+
+// acc = sum over the elements containing node g of F[e][local index of g], then the epilogue;
+// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_facesum(const T* __restrict__ F, T* __restrict__ y, Grid g, int neumann) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
+k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep) {
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= (uint32_t)g.N) return;
   const int p = g.p, n = p + 1, dim = g.dim;
-  int gc[3];
-  gc[0] = (int)(t % g.nn[0]);
-  gc[1] = (int)((t / g.nn[0]) % g.nn[1]);
-  gc[2] = (dim == 3) ? (int)(t / ((int64_t)g.nn[0] * g.nn[1])) : 0;
-  const int rx = gc[0] % p, ry = gc[1] % p, rz = (dim == 3) ? gc[2] % p : 1;
-  if (rx != 0 && ry != 0 && rz != 0) return;  // element-interior node: written by the element kernel
-  bool bnd = gc[0] == 0 || gc[0] == g.nn[0] - 1 || gc[1] == 0 || gc[1] == g.nn[1] - 1;
-  if (dim == 3) bnd = bnd || gc[2] == 0 || gc[2] == g.nn[2] - 1;
+  const uint32_t nx = (uint32_t)g.nn[0], ny = (uint32_t)g.nn[1];
+  const int gx = (int)(t % nx);
+  const uint32_t r = t / nx;
+  const int gy = (int)(r % ny);
+  const int gz = (int)(r / ny);
+  bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
+  if (dim == 3) bnd = bnd || gz == 0 || gz == g.nn[2] - 1;
   if (bnd && !neumann) {
-    y[t] = T(0);
+    epilogue_zero(ep, (int64_t)t);
     return;
   }
-  int ce[3][2], cl[3][2], cnt[3];
-  for (int a = 0; a < 3; ++a) {
-    if (a >= dim) {
-      cnt[a] = 1;
-      ce[a][0] = 0;
-      cl[a][0] = 0;
-      continue;
-    }
-    const int r = gc[a] % p, e = gc[a] / p;
-    if (r != 0) {
-      cnt[a] = 1;
-      ce[a][0] = e;
-      cl[a][0] = r;
-    } else {
-      cnt[a] = 0;
-      if (e > 0) { ce[a][cnt[a]] = e - 1; cl[a][cnt[a]] = p; ++cnt[a]; }
-      if (e < g.ne[a]) { ce[a][cnt[a]] = e; cl[a][cnt[a]] = 0; ++cnt[a]; }
-    }
-  }
-  const int NB = nbnd(n, dim);
+  int cex[2], clx[2], cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
+  const int cx = axis_cands(gx, p, g.ne[0], cex, clx);
+  const int cy = axis_cands(gy, p, g.ne[1], cey, cly);
+  const int cz = dim == 3 ? axis_cands(gz, p, g.ne[2], cez, clz) : 1;
+  const int nl = nloc_of(n, dim);
   T acc = T(0);
-  for (int kz = 0; kz < cnt[2]; ++kz)
-    for (int ky = 0; ky < cnt[1]; ++ky)
-      for (int kx = 0; kx < cnt[0]; ++kx) {
-        const int64_t e = ce[0][kx] + (int64_t)g.ne[0] * (ce[1][ky] + (int64_t)g.ne[1] * ce[2][kz]);
-        const int s = (dim == 3) ? slot3(n, cl[0][kx], cl[1][ky], cl[2][kz])
-                                 : slot_ring(n, cl[0][kx], cl[1][ky]);
-        acc += F[e * NB + s];
+  for (int kz = 0; kz < cz; ++kz)
+    for (int ky = 0; ky < cy; ++ky)
+      for (int kx = 0; kx < cx; ++kx) {
+        const int64_t e = cex[kx] + (int64_t)g.ne[0] * (cey[ky] + (int64_t)g.ne[1] * cez[kz]);
+        const int l = clx[kx] + n * (cly[ky] + n * clz[kz]);
+        acc += F[e * nl + l];
       }
-  y[t] = acc;
+  const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
+  epilogue(ep, (int64_t)t, acc, xv);
+}
+
+template <typename T>
+void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, s, F, xin, g,
+                     neumann, ep);
+  GLLMG_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ diagonal
 // diag_e(i) = sum_a sum_m D[m, i_a]^2 G_aa(i with a -> m) + sum_{a != b} D[i_a, i_a] D[i_b, i_b] G_ab(i)
 // (the cross terms survive only where both D diagonal entries are nonzero: the element's
-// boundary nodes). One thread per element point; FP64.
+// boundary nodes). One thread per element point, written to the element-vector buffer; FP64.
 __global__ void __launch_bounds__(256)
-k_diag(const double* __restrict__ G, const double* __restrict__ Dm, Grid g, double* __restrict__ y,
-       double* __restrict__ F) {
+k_diag(const double* __restrict__ G, const double* __restrict__ Dm, Grid g, double* __restrict__ F) {
   const int n = g.p + 1, dim = g.dim;
-  const int nloc = dim == 3 ? n * n * n : n * n;
+  const int nloc = nloc_of(n, dim);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.E * nloc) return;
   const int64_t e = t / nloc;
@@ -276,45 +343,31 @@ k_diag(const double* __restrict__ G, const double* __restrict__ Dm, Grid g, doub
   for (int a = 0; a < dim; ++a)
     for (int b = a + 1; b < dim; ++b)
       d += 2.0 * Dm[qc[a] * n + qc[a]] * Dm[qc[b] * n + qc[b]] * Ge[(int64_t)comp(a, b) * nloc + q];
-  const int ex = (int)(e % g.ne[0]);
-  const int ey = (int)((e / g.ne[0]) % g.ne[1]);
-  const int ez = dim == 3 ? (int)(e / ((int64_t)g.ne[0] * g.ne[1])) : 0;
-  bool inner = qc[0] > 0 && qc[0] < n - 1 && qc[1] > 0 && qc[1] < n - 1;
-  if (dim == 3) inner = inner && qc[2] > 0 && qc[2] < n - 1;
-  if (inner) {
-    const int64_t gi = (ex * g.p + qc[0]) + (int64_t)g.nn[0] *
-                       ((ey * g.p + qc[1]) + (int64_t)g.nn[1] * (ez * g.p + qc[2]));
-    y[gi] = d;
-  } else {
-    const int s = dim == 3 ? slot3(n, qc[0], qc[1], qc[2]) : slot_ring(n, qc[0], qc[1]);
-    F[e * nbnd(n, dim) + s] = d;
-  }
+  F[t] = d;
 }
 
 template <int N, typename T>
-void apply_n(const Level& L, int neumann, const void* x, void* y, void* F, hipStream_t s) {
+void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F, hipStream_t s) {
   const T* G = std::is_same<T, double>::value ? (const T*)L.G64 : (const T*)L.G32;
   const T* D = std::is_same<T, double>::value ? (const T*)L.D64 : (const T*)L.D32;
   constexpr int EPB = Epb<N>::v;
   const unsigned nb = (unsigned)((L.g.E + EPB - 1) / EPB);
   if (L.g.dim == 3)
     hipLaunchKernelGGL((k_apply3d<N, T, EPB>), dim3(nb), dim3(EPB * N * N), 0, s, (const T*)x,
-                       (T*)y, (T*)F, G, D, L.g, neumann);
+                       (T*)F, G, D, L.g, neumann);
   else
     hipLaunchKernelGGL((k_apply2d<N, T, EPB>), dim3(nb), dim3(EPB * N * N), 0, s, (const T*)x,
-                       (T*)y, (T*)F, G, D, L.g, neumann);
+                       (T*)F, G, D, L.g, neumann);
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_facesum<T>, dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, s,
-                     (const T*)F, (T*)y, L.g, neumann);
-  GLLMG_HIP(hipGetLastError());
+  launch_gather<T>((const T*)F, (const T*)x, L.g, neumann, typed<T>(epi), s);
 }
 
 template <typename T>
-void apply_t(const Level& L, int neumann, const void* x, void* y, void* F, hipStream_t s) {
+void apply_t(const Level& L, int neumann, const void* x, const Epi& ep, void* F, hipStream_t s) {
   switch (L.n) {
 #define GLLMG_CASE(NV) \
   case NV:             \
-    return apply_n<NV, T>(L, neumann, x, y, F, s);
+    return apply_n<NV, T>(L, neumann, x, ep, F, s);
     GLLMG_CASE(2) GLLMG_CASE(3) GLLMG_CASE(4) GLLMG_CASE(5) GLLMG_CASE(6) GLLMG_CASE(7)
     GLLMG_CASE(8) GLLMG_CASE(9) GLLMG_CASE(10) GLLMG_CASE(11) GLLMG_CASE(12) GLLMG_CASE(13)
     GLLMG_CASE(14) GLLMG_CASE(15) GLLMG_CASE(16) GLLMG_CASE(17)
@@ -326,24 +379,24 @@ void apply_t(const Level& L, int neumann, const void* x, void* y, void* F, hipSt
 
 }  // namespace
 
-size_t face_buffer_elems(const Level& L) { return (size_t)L.g.E * nbnd(L.n, L.g.dim); }
+size_t face_buffer_elems(const Level& L) { return (size_t)L.g.E * nloc_of(L.n, L.g.dim); }
 
-void launch_apply(const Level& L, int prec, int neumann, const void* x, void* y, void* F,
+void launch_apply(const Level& L, int prec, int neumann, const void* x, const Epi& ep, void* F,
                   hipStream_t s) {
   if (prec == 0)
-    apply_t<double>(L, neumann, x, y, F, s);
+    apply_t<double>(L, neumann, x, ep, F, s);
   else
-    apply_t<float>(L, neumann, x, y, F, s);
+    apply_t<float>(L, neumann, x, ep, F, s);
 }
 
 void launch_diag(const Level& L, double* diag, double* F, hipStream_t s) {
   const int64_t tot = L.npts;
   hipLaunchKernelGGL(k_diag, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.G64, L.D64,
-                     L.g, diag, F);
+                     L.g, F);
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_facesum<double>, dim3((unsigned)((L.g.N + 255) / 256)), dim3(256), 0, s,
-                     (const double*)F, diag, L.g, 0);
-  GLLMG_HIP(hipGetLastError());
+  Epi ep;
+  ep.y = diag;
+  launch_gather<double>((const double*)F, nullptr, L.g, 0, typed<double>(ep), s);
 }
 
 }  // namespace gllmg

@@ -42,6 +42,9 @@ void validate(const gllmg_config& c) {
   GLLMG_CHECK(c.vcycle_prec == GLLMG_F64 || c.vcycle_prec == GLLMG_F32, GLLMG_EINVAL,
               "vcycle_prec must be GLLMG_F64 or GLLMG_F32");
   GLLMG_CHECK(c.max_levels >= 0, GLLMG_EINVAL, "max_levels must be >= 0");
+  int64_t nodes = 1;
+  for (int a = 0; a < c.dim; ++a) nodes *= (int64_t)c.nelem[a] * c.order + 1;
+  GLLMG_CHECK(nodes < (int64_t(1) << 31), GLLMG_EINVAL, "more than 2^31 - 1 nodes");
   int ne[3] = {c.nelem[0], c.nelem[1], c.dim == 3 ? c.nelem[2] : 1};
   GLLMG_CHECK(interior_count(c.dim, ne, c.order) >= 1, GLLMG_EINVAL,
               "the mesh has no interior node");
@@ -122,6 +125,11 @@ struct gllmg_problem {
   size_t scratch_bytes = 0;
   double* hbuf = nullptr;    // pinned host scalars
   int vprec = 0;             // V-cycle precision index
+  // the solve's V-cycle (pr -> pz) captured once as a HIP graph and replayed per iteration
+  bool use_graph = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t vexec = nullptr;
+  std::vector<int64_t> vapplies;
 };
 
 namespace gllmg {
@@ -253,10 +261,26 @@ void read_scalars(gllmg_problem* P, int idx, int cnt, double* out, hipStream_t s
   for (int i = 0; i < cnt; ++i) out[i] = P->hbuf[i];
 }
 
-void apply_level(gllmg_problem* P, int l, int pr, int neumann, const void* x, void* y, hipStream_t s) {
+void apply_epi(gllmg_problem* P, int l, int pr, int neumann, const void* x, const Epi& ep,
+               hipStream_t s) {
   Level& L = P->L[l];
-  launch_apply(L, pr, neumann, x, y, P->F, s);
+  launch_apply(L, pr, neumann, x, ep, P->F, s);
   ++L.applies;
+}
+
+void apply_level(gllmg_problem* P, int l, int pr, int neumann, const void* x, void* y, hipStream_t s) {
+  Epi ep;
+  ep.y = y;
+  apply_epi(P, l, pr, neumann, x, ep, s);
+}
+
+// r = b - A_l x
+void residual(gllmg_problem* P, int l, int pr, const void* b, const void* x, void* r, hipStream_t s) {
+  Epi ep;
+  ep.mode = EPI_RESIDUAL;
+  ep.b = b;
+  ep.r = r;
+  apply_epi(P, l, pr, 0, x, ep, s);
 }
 
 void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
@@ -456,38 +480,58 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   }
   void* r = L.vr[pr];
   void* d = L.vd[pr];
-  void* t = L.vt[pr];
   const void* dinv = dinv_of(L, pr);
   if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
     for (int it = 0; it < k; ++it) {
       if (it == 0 && zero) {
         jacobi_step(pr, N, 1, x, b, nullptr, dinv, P->cfg.omega, s);
       } else {
-        apply_level(P, l, pr, 0, x, t, s);
-        jacobi_step(pr, N, 0, x, b, t, dinv, P->cfg.omega, s);
+        Epi ep;  // x = x + (omega dinv) (b - A x), fused into the product
+        ep.mode = EPI_JACOBI;
+        ep.x = x;
+        ep.b = b;
+        ep.dinv = dinv;
+        ep.om = P->cfg.omega;
+        apply_epi(P, l, pr, 0, x, ep, s);
       }
     }
     return;
   }
+  // Chebyshev acceleration of Jacobi on [cheb_lo lambda, lambda] (Saad, Alg. 12.1 with D^{-1})
   const double lam = L.lmax, alpha = P->cfg.cheb_lo * lam;
   const double theta = 0.5 * (lam + alpha), delta = 0.5 * (lam - alpha);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   const void* rin;
   if (zero) {
-    cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);
+    cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);  // r = b, d = dinv b / theta
     rin = b;
   } else {
-    apply_level(P, l, pr, 0, x, t, s);
-    cheb_start(pr, N, b, t, dinv, theta, r, d, s);
+    Epi ep;  // r = b - A x, d = dinv r / theta
+    ep.mode = EPI_CHEB_START;
+    ep.b = b;
+    ep.r = r;
+    ep.d = d;
+    ep.dinv = dinv;
+    ep.c1 = theta;
+    apply_epi(P, l, pr, 0, x, ep, s);
     rin = r;
   }
   for (int i = 1; i <= k; ++i) {
     const bool first_zero = zero && i == 1;
     if (i < k) {
-      apply_level(P, l, pr, 0, d, t, s);
       const double rn = 1.0 / (2.0 * sigma - rho);
-      cheb_step(pr, N, first_zero ? 1 : 0, x, rin, r, t, d, dinv, rn * rho, 2.0 * rn / delta, s);
+      Epi ep;  // with t = A d: x += d; r = rin - t; d = rn rho d + (2 rn / delta) dinv r
+      ep.mode = EPI_CHEB;
+      ep.from_zero = first_zero ? 1 : 0;
+      ep.x = x;
+      ep.rin = rin;
+      ep.r = r;
+      ep.d = d;
+      ep.dinv = dinv;
+      ep.c1 = rn * rho;
+      ep.c2 = 2.0 * rn / delta;
+      apply_epi(P, l, pr, 0, d, ep, s);
       rin = r;
       rho = rn;
     } else {
@@ -509,8 +553,7 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
   }
   Level& C = P->L[l + 1];
   smooth_impl(P, l, pr, b, x, P->cfg.nu_pre, true, s);
-  apply_level(P, l, pr, 0, x, L.vt[pr], s);
-  vec_sub(pr, L.g.N, b, L.vt[pr], L.vr[pr], s);
+  residual(P, l, pr, b, x, L.vr[pr], s);
   launch_restrict(L, C, pr, L.vr[pr], C.vb[pr], P->T1, P->T2, s);
   vcycle_level(P, l + 1, pr, C.vb[pr], C.vx[pr], s);
   launch_prolong(L, C, pr, C.vx[pr], x, true, P->T1, P->T2, s);
@@ -518,7 +561,7 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
 }
 
 // z = V r for FP64 vectors r, z on the finest level, in the problem's V-cycle precision
-void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
+void precond_eager(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
   Level& L = P->L[0];
   if (P->vprec == 0) {
     vcycle_level(P, 0, 0, r, z, s);
@@ -527,6 +570,49 @@ void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
     vcycle_level(P, 0, 1, L.vb[1], L.vx[1], s);
     cast_32_64(L.g.N, (const float*)L.vx[1], z, s);
   }
+}
+
+void drop_graph(gllmg_problem* P) {
+  if (P->vexec) (void)hipGraphExecDestroy(P->vexec);
+  P->vexec = nullptr;
+}
+
+// Capture the launch sequence of one V-cycle from P->pr to P->pz (kernels only: no copies,
+// memsets or synchronization) on a private stream of default priority.
+void capture_vcycle(gllmg_problem* P) {
+  if (!P->cap) GLLMG_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+  std::vector<int64_t> a0;
+  for (auto& L : P->L) a0.push_back(L.applies);
+  GLLMG_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t g = nullptr;
+  try {
+    precond_eager(P, P->pr, P->pz, P->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
+  }
+  GLLMG_HIP(hipStreamEndCapture(P->cap, &g));
+  hipGraphExec_t ex = nullptr;
+  const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw Error(GLLMG_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  P->vexec = ex;
+  P->vapplies.assign(P->L.size(), 0);
+  for (size_t l = 0; l < P->L.size(); ++l) {
+    P->vapplies[l] = P->L[l].applies - a0[l];
+    P->L[l].applies = a0[l];
+  }
+}
+
+void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
+  if (!P->use_graph || r != P->pr || z != P->pz) {
+    precond_eager(P, r, z, s);
+    return;
+  }
+  if (!P->vexec) capture_vcycle(P);
+  GLLMG_HIP(hipGraphLaunch(P->vexec, s));
+  for (size_t l = 0; l < P->L.size(); ++l) P->L[l].applies += P->vapplies[l];
 }
 
 enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
@@ -539,8 +625,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
   std::vector<int64_t> a0;
   for (auto& lv : P->L) a0.push_back(lv.applies);
   double *r = P->pr, *z = P->pz, *p = P->pp, *h = P->ph;
-  apply_level(P, 0, 0, 0, x, h, s);
-  vec_sub(0, N, b, h, r, s);
+  residual(P, 0, 0, b, x, r, s);
   dot(0, N, r, r, P->part, P->scal + S_RR, s);
   const double n0 = std::sqrt(read_scalar(P, S_RR, s));
   std::vector<double> hist{n0};
@@ -581,8 +666,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
       for (int it = 1; it <= maxit; ++it) {
         precond(P, r, z, s);
         vec_axpy(0, N, 1.0, z, x, s);
-        apply_level(P, 0, 0, 0, x, h, s);
-        vec_sub(0, N, b, h, r, s);
+        residual(P, 0, 0, b, x, r, s);
         dot(0, N, r, r, P->part, P->scal + S_RR, s);
         nr = std::sqrt(read_scalar(P, S_RR, s));
         iters = it;
@@ -601,8 +685,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
   // true residual in FP64
   double rt = 0.0;
   if (n0 > 0.0 && std::isfinite(n0)) {
-    apply_level(P, 0, 0, 0, x, h, s);
-    vec_sub(0, N, b, h, P->pt, s);
+    residual(P, 0, 0, b, x, P->pt, s);
     dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, s);
     rt = std::sqrt(read_scalar(P, S_B, s)) / n0;
   }
@@ -754,6 +837,8 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
 gllmg_status gllmg_destroy(gllmg_problem* P) {
   return guard([&]() {
     if (!P) return GLLMG_OK;
+    drop_graph(P);
+    if (P->cap) (void)hipStreamDestroy(P->cap);
     if (P->owns_ws) (void)hipFree(P->ws);
     if (P->hbuf) (void)hipHostFree(P->hbuf);
     delete P;
@@ -788,6 +873,16 @@ gllmg_status gllmg_set_lmax(gllmg_problem* P, int32_t level, double lmax) {
     level_of(P, level);
     GLLMG_CHECK(lmax > 0.0 && std::isfinite(lmax), GLLMG_EINVAL, "lmax must be positive");
     P->L[level].lmax = lmax;
+    drop_graph(P);  // the captured V-cycle holds the old Chebyshev coefficients
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_set_graphs(gllmg_problem* P, int32_t enable) {
+  return guard([&]() {
+    GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+    P->use_graph = enable != 0;
+    if (!P->use_graph) drop_graph(P);
     return GLLMG_OK;
   });
 }

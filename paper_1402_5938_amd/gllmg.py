@@ -59,6 +59,7 @@ _lib = None
 
 EXPORTS = ["gllmg_last_error", "gllmg_config_default", "gllmg_plan", "gllmg_setup",
            "gllmg_destroy", "gllmg_num_levels", "gllmg_level_info", "gllmg_set_lmax",
+           "gllmg_set_graphs",
            "gllmg_node_coords", "gllmg_eval_field", "gllmg_rhs", "gllmg_diag", "gllmg_apply",
            "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve"]
 
@@ -83,6 +84,7 @@ def lib():
     L.gllmg_level_info.argtypes = [vp, i32, C.POINTER(i64), C.POINTER(i64), C.POINTER(i32),
                                    C.POINTER(i32), C.POINTER(dbl)]
     L.gllmg_set_lmax.argtypes = [vp, i32, dbl]
+    L.gllmg_set_graphs.argtypes = [vp, i32]
     L.gllmg_node_coords.argtypes = [vp, i32, vp, vp]
     L.gllmg_eval_field.argtypes = [vp, i32, C.POINTER(Field), vp, vp]
     L.gllmg_rhs.argtypes = [vp, vp, vp, vp]
@@ -242,6 +244,9 @@ class Problem:
     def set_lmax(self, l, v):
         _check(lib().gllmg_set_lmax(self.h, l, float(v)))
         self.levels[l].lmax = float(v)
+
+    def set_graphs(self, enable: bool):
+        _check(lib().gllmg_set_graphs(self.h, 1 if enable else 0))
 
     def nnodes(self, l=0):
         return self.levels[l].nnodes

@@ -156,3 +156,27 @@ def test_pcg_iteration_counts_warped(dim, ne, p):
     assert rg.converged and rg.iters == ro.iters
     assert rel_err(rg.history, ro.history) <= 1e-8
     G.close()
+
+
+@pytest.mark.parametrize("vprec", ["f64", "f32"])
+def test_graph_replays_match_eager(vprec):
+    """The captured V-cycle graph, replayed in several solves with eager work and
+    synchronizations in between, gives bitwise the same iterates as eager launches."""
+    import torch
+    G, H = build_pair(3, (2, 2, 2), 4, hierarchy="p", vcycle_prec=vprec)
+    f = np.random.default_rng(8).uniform(-1, 1, H.fine.mesh.N)
+    b = G.rhs(to_dev(f))
+    G.set_graphs(False)
+    xe = torch.zeros_like(b)
+    re_ = G.solve(b, xe, rtol=1e-10)
+    G.set_graphs(True)
+    for rep in range(3):
+        xg = torch.zeros_like(b)
+        rg = G.solve(b, xg, rtol=1e-10)
+        torch.cuda.synchronize()
+        G.apply(to_dev(f))                      # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert rg.iters == re_.iters and rg.history == re_.history
+        assert torch.equal(xg, xe), rep
+        assert rg.applies == re_.applies
+    G.close()

@@ -94,9 +94,12 @@ __device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
 }
 
 // Elements per workgroup so that a workgroup has about 256 threads (n^2 threads per element).
+#ifndef GLLMG_EPB_THREADS
+#define GLLMG_EPB_THREADS 256
+#endif
 template <int N>
 struct Epb {
-  static constexpr int v = (N * N >= 128) ? 1 : (256 / (N * N));
+  static constexpr int v = (N * N >= GLLMG_EPB_THREADS / 2) ? 1 : (GLLMG_EPB_THREADS / (N * N));
 };
 
 // ------------------------------------------------------------------ 3D element kernel
@@ -109,10 +112,12 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
   __shared__ T sA[EPB * NNN];
   __shared__ T sB[EPB * NNN];
+  __shared__ T sD[NN];  // D, read with wave-uniform addresses by the z-contractions
   const int t = threadIdx.x;
   const int le = t / NN;
   const int ij = t - le * NN;
   const int i = ij % N, j = ij / N;
+  if (t < NN) sD[t] = Dm[t];
   const uint32_t e = blockIdx.x * EPB + le;
   const bool valid = e < (uint32_t)g.E;
   const uint32_t ee = valid ? e : 0u;
@@ -128,15 +133,17 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   T* A = sA + le * NNN;
   T* B = sB + le * NNN;
 
+  // all N loads are issued before any is used: the addresses are in bounds for every thread
+  // (an out-of-range element reads element 0), and masked values are replaced afterwards
   T xr[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const int gz = ez * P + k;
     const bool bnd = bxy || gz == 0 || gz == g.nn[2] - 1;
-    T v = T(0);
-    if (valid && (neumann || !bnd)) v = x[gb + sxy * k];
-    xr[k] = v;
-    A[k * NN + ij] = v;
+    if (!valid || (bnd && !neumann)) xr[k] = T(0);
+    A[k * NN + ij] = xr[k];
   }
   T Di[N], Dj[N];
 #pragma unroll
@@ -144,10 +151,18 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     Di[l] = Dm[i * N + l];
     Dj[l] = Dm[j * N + l];
   }
+  // the first PF planes of geometric factors are loaded before the barrier, so their latency
+  // overlaps the gather of x; PF is bounded by a register budget
+  constexpr int PF = (N * 6 * (int)sizeof(T) / 4 <= 112) ? N : (N <= 12 ? 4 : 2);
+  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
+  T gp[PF][6];
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
   __syncthreads();
 
   T wx[N], wy[N], wz[N];
-  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T ux = T(0), uy = T(0), uz = T(0);
@@ -155,10 +170,24 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     for (int l = 0; l < N; ++l) {
       ux += Di[l] * A[k * NN + j * N + l];
       uy += Dj[l] * A[k * NN + l * N + i];
-      uz += Dm[k * N + l] * xr[l];
+      uz += sD[k * N + l] * xr[l];
     }
-    const T g0 = Ge[0 * NNN + k * NN], g1 = Ge[1 * NNN + k * NN], g2 = Ge[2 * NNN + k * NN];
-    const T g3 = Ge[3 * NNN + k * NN], g4 = Ge[4 * NNN + k * NN], g5 = Ge[5 * NNN + k * NN];
+    T g0, g1, g2, g3, g4, g5;
+    if (k < PF) {
+      g0 = gp[k < PF ? k : 0][0];
+      g1 = gp[k < PF ? k : 0][1];
+      g2 = gp[k < PF ? k : 0][2];
+      g3 = gp[k < PF ? k : 0][3];
+      g4 = gp[k < PF ? k : 0][4];
+      g5 = gp[k < PF ? k : 0][5];
+    } else {
+      g0 = Ge[0 * NNN + k * NN];
+      g1 = Ge[1 * NNN + k * NN];
+      g2 = Ge[2 * NNN + k * NN];
+      g3 = Ge[3 * NNN + k * NN];
+      g4 = Ge[4 * NNN + k * NN];
+      g5 = Ge[5 * NNN + k * NN];
+    }
     wx[k] = g0 * ux + g1 * uy + g2 * uz;
     wy[k] = g1 * ux + g3 * uy + g4 * uz;
     wz[k] = g2 * ux + g4 * uy + g5 * uz;
@@ -185,7 +214,7 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     for (int l = 0; l < N; ++l) {
       acc += DiT[l] * A[k * NN + j * N + l];
       acc += DjT[l] * B[k * NN + l * N + i];
-      acc += Dm[l * N + k] * wz[l];
+      acc += sD[l * N + k] * wz[l];
     }
     Fe[k * NN] = acc;
   }
@@ -213,8 +242,10 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   const int64_t gi = gx + (int64_t)g.nn[0] * gy;
   T* A = sA + le * NN;
   T* B = sB + le * NN;
-  T xv = T(0);
-  if (valid && (neumann || !bnd)) xv = x[gi];
+  T xv = x[gi];
+  const T* Ge = G + (int64_t)ee * (3 * NN) + ij;
+  const T g0 = Ge[0], g1 = Ge[NN], g2 = Ge[2 * NN];
+  if (!valid || (bnd && !neumann)) xv = T(0);
   A[ij] = xv;
   __syncthreads();
   T ux = T(0), uy = T(0);
@@ -223,8 +254,6 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     ux += Dm[i * N + l] * A[j * N + l];
     uy += Dm[j * N + l] * A[l * N + i];
   }
-  const T* Ge = G + (int64_t)ee * (3 * NN) + ij;
-  const T g0 = Ge[0], g1 = Ge[NN], g2 = Ge[2 * NN];
   const T wx = g0 * ux + g1 * uy;
   const T wy = g1 * ux + g2 * uy;
   __syncthreads();
@@ -265,47 +294,82 @@ __device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
 }
 
 // acc = sum over the elements containing node g of F[e][local index of g], then the epilogue;
-// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann.
-template <typename T>
-__global__ void __launch_bounds__(256)
+// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann. One workgroup of
+// kGX threads covers kGX consecutive nodes of one grid row (fixed y, z), so the row's
+// element candidates along y and z are uniform across the workgroup.
+constexpr int kGX = 64;
+
+template <int N, int DIM, typename T>
+__global__ void __launch_bounds__(kGX)
 k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep) {
-  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-  if (t >= (uint32_t)g.N) return;
-  const int p = g.p, n = p + 1, dim = g.dim;
-  const uint32_t nx = (uint32_t)g.nn[0], ny = (uint32_t)g.nn[1];
-  const int gx = (int)(t % nx);
-  const uint32_t r = t / nx;
-  const int gy = (int)(r % ny);
-  const int gz = (int)(r / ny);
+  constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
+  const int nch = (g.nn[0] + kGX - 1) / kGX;  // workgroups per row (uniform)
+  const int row = (int)(blockIdx.x / (unsigned)nch);
+  const int gx = (int)(blockIdx.x - (unsigned)row * nch) * kGX + threadIdx.x;
+  if (gx >= g.nn[0]) return;
+  const int gy = DIM == 3 ? row % g.nn[1] : row;
+  const int gz = DIM == 3 ? row / g.nn[1] : 0;
+  const int64_t t = gx + (int64_t)g.nn[0] * row;
   bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
-  if (dim == 3) bnd = bnd || gz == 0 || gz == g.nn[2] - 1;
+  if (DIM == 3) bnd = bnd || gz == 0 || gz == g.nn[2] - 1;
   if (bnd && !neumann) {
-    epilogue_zero(ep, (int64_t)t);
+    epilogue_zero(ep, t);
     return;
   }
   int cex[2], clx[2], cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
-  const int cx = axis_cands(gx, p, g.ne[0], cex, clx);
-  const int cy = axis_cands(gy, p, g.ne[1], cey, cly);
-  const int cz = dim == 3 ? axis_cands(gz, p, g.ne[2], cez, clz) : 1;
-  const int nl = nloc_of(n, dim);
-  T acc = T(0);
-  for (int kz = 0; kz < cz; ++kz)
-    for (int ky = 0; ky < cy; ++ky)
-      for (int kx = 0; kx < cx; ++kx) {
-        const int64_t e = cex[kx] + (int64_t)g.ne[0] * (cey[ky] + (int64_t)g.ne[1] * cez[kz]);
-        const int l = clx[kx] + n * (cly[ky] + n * clz[kz]);
-        acc += F[e * nl + l];
+  const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+  const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
+  const int cz = DIM == 3 ? axis_cands(gz, P, g.ne[2], cez, clz) : 1;
+  // up to 8 loads, all issued before the sum: missing candidates re-read candidate 0 and
+  // contribute +0 (the sum order is z, y, x with the lower element first)
+  T v[2][2][2];
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx) {
+        const int az = kz < cz ? kz : 0, ay = ky < cy ? ky : 0, ax = kx < cx ? kx : 0;
+        const int64_t e = cex[ax] + (int64_t)g.ne[0] * (cey[ay] + (int64_t)g.ne[1] * cez[az]);
+        v[kz][ky][kx] = F[e * NL + clx[ax] + N * (cly[ay] + N * clz[az])];
       }
+  T acc = T(0);
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx)
+        if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
   const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
-  epilogue(ep, (int64_t)t, acc, xv);
+  epilogue(ep, t, acc, xv);
+}
+
+template <int N, typename T>
+void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
+                   hipStream_t s) {
+  const dim3 grid((unsigned)(((g.nn[0] + kGX - 1) / kGX) * (g.N / g.nn[0])));
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, dim3(kGX), 0, s, F, xin, g, neumann, ep);
+  else
+    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, dim3(kGX), 0, s, F, xin, g, neumann, ep);
+  GLLMG_HIP(hipGetLastError());
 }
 
 template <typename T>
-void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_gather<T>, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, s, F, xin, g,
-                     neumann, ep);
-  GLLMG_HIP(hipGetLastError());
+void launch_gather_rt(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
+                      hipStream_t s) {
+  switch (g.p + 1) {
+#define GLLMG_CASE(NV) \
+  case NV:             \
+    return launch_gather<NV, T>(F, xin, g, neumann, ep, s);
+    GLLMG_CASE(2) GLLMG_CASE(3) GLLMG_CASE(4) GLLMG_CASE(5) GLLMG_CASE(6) GLLMG_CASE(7)
+    GLLMG_CASE(8) GLLMG_CASE(9) GLLMG_CASE(10) GLLMG_CASE(11) GLLMG_CASE(12) GLLMG_CASE(13)
+    GLLMG_CASE(14) GLLMG_CASE(15) GLLMG_CASE(16) GLLMG_CASE(17)
+#undef GLLMG_CASE
+    default:
+      throw Error(GLLMG_EINVAL, "unsupported order");
+  }
 }
 
 // ------------------------------------------------------------------ diagonal
@@ -359,7 +423,7 @@ void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F
     hipLaunchKernelGGL((k_apply2d<N, T, EPB>), dim3(nb), dim3(EPB * N * N), 0, s, (const T*)x,
                        (T*)F, G, D, L.g, neumann);
   GLLMG_HIP(hipGetLastError());
-  launch_gather<T>((const T*)F, (const T*)x, L.g, neumann, typed<T>(epi), s);
+  launch_gather<N, T>((const T*)F, (const T*)x, L.g, neumann, typed<T>(epi), s);
 }
 
 template <typename T>
@@ -396,7 +460,7 @@ void launch_diag(const Level& L, double* diag, double* F, hipStream_t s) {
   GLLMG_HIP(hipGetLastError());
   Epi ep;
   ep.y = diag;
-  launch_gather<double>((const double*)F, nullptr, L.g, 0, typed<double>(ep), s);
+  launch_gather_rt<double>((const double*)F, nullptr, L.g, 0, typed<double>(ep), s);
 }
 
 }  // namespace gllmg

@@ -15,7 +15,7 @@ from typing import List, Optional
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgllmg.so")
+LIB_PATH = os.environ.get("GLLMG_LIB", os.path.join(HERE, "libgllmg.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EUNSUPPORTED = range(7)
 F64, F32 = 0, 1

@@ -205,6 +205,29 @@ gllmg_status gllmg_vcycle(const gllmg_problem* prob, gllmg_prec prec, const void
 gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* b, double* x,
                          double rtol, int32_t maxit, gllmg_solve_stats* stats, void* stream);
 
+/* The same solve split into non-blocking steps, so that one host thread can drive many
+ * problems on different streams and interleave them iteration by iteration (continuous
+ * batching). gllmg_solve_begin enqueues r = b - A x and its norm on `stream` and returns.
+ * gllmg_solve_poll never blocks: it consumes the iteration scalars that have arrived, enqueues
+ * the next iteration and sets *done = 1 once the solve (including the final true residual) has
+ * finished. gllmg_solve_end waits for completion if needed, fills stats and returns the status
+ * gllmg_solve would have returned. Iterates and counts are identical to gllmg_solve. One solve
+ * per problem at a time; b and x must stay valid until gllmg_solve_end. */
+gllmg_status gllmg_solve_begin(gllmg_problem* prob, int32_t mode, const double* b, double* x,
+                               double rtol, int32_t maxit, void* stream);
+gllmg_status gllmg_solve_poll(gllmg_problem* prob, int32_t* done);
+gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
+
+/* Solve `count` independent problems (any mix of dimension, mesh, order and precision), each
+ * on its own internal stream ordered after `stream`, advanced iteration by iteration from one
+ * host thread; `stream` waits for all of them before the call returns. stats and status may be
+ * NULL, else arrays of `count`. Returns GLLMG_OK if every solve converged, else the first
+ * error (status[i] holds each problem's own status). */
+gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const* b,
+                               double* const* x, int32_t count, int32_t mode, double rtol,
+                               int32_t maxit, gllmg_solve_stats* stats, gllmg_status* status,
+                               void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <thread>
 
 #include "internal.h"
 
@@ -130,6 +131,20 @@ struct gllmg_problem {
   hipStream_t cap = nullptr;
   hipGraphExec_t vexec = nullptr;
   std::vector<int64_t> vapplies;
+  // state of the solve in progress (gllmg_solve_begin / _poll / _end)
+  struct Solve {
+    bool active = false, done = false, conv = false, breakdown = false;
+    int mode = 0, maxit = 0, iters = 0, g = 0, phase = 0;
+    const double* b = nullptr;
+    double* x = nullptr;
+    double rtol = 0, n0 = 0, nr = 0, rt = 0;
+    hipStream_t s = nullptr;
+    hipEvent_t ev = nullptr;
+    std::vector<double> hist;
+    std::vector<int64_t> a0;
+    std::chrono::steady_clock::time_point t0;
+  } sv;
+  hipStream_t xs = nullptr;  // internal stream for batched solves (default priority)
 };
 
 namespace gllmg {
@@ -616,95 +631,154 @@ void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
 }
 
 enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
+enum { PH_INIT = 0, PH_ITER = 1, PH_FINAL = 2 };
+
+// Host-visible scalars of the solve arrive in the pinned buffer hbuf through stream-ordered
+// copies followed by an event; the state machine advances only when that event has completed,
+// so the host never blocks inside solve_poll.
+void post_scalars(gllmg_problem* P, int src, int cnt, int dst) {
+  auto& v = P->sv;
+  GLLMG_HIP(hipMemcpyAsync(P->hbuf + dst, P->scal + src, sizeof(double) * cnt,
+                           hipMemcpyDeviceToHost, v.s));
+  GLLMG_HIP(hipEventRecord(v.ev, v.s));
+}
+
+// One PCG iteration up to its convergence data: h = A p; (p, h); x += alpha p; r -= alpha h;
+// (r, r). One MG iteration: z = V r; x += z; r = b - A x; (r, r).
+void enqueue_iteration(gllmg_problem* P) {
+  auto& v = P->sv;
+  const int64_t N = P->L[0].g.N;
+  if (v.mode == GLLMG_MODE_PCG) {
+    apply_level(P, 0, 0, 0, P->pp, P->ph, v.s);
+    dot(0, N, P->pp, P->ph, P->part, P->scal + S_PH, v.s);
+    pcg_update_xr(N, P->scal, v.g, S_PH, v.x, P->pr, P->pp, P->ph, P->part, P->scal + S_RR, v.s);
+  } else {
+    precond(P, P->pr, P->pz, v.s);
+    vec_axpy(0, N, 1.0, P->pz, v.x, v.s);
+    residual(P, 0, 0, v.b, v.x, P->pr, v.s);
+    dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, v.s);
+  }
+  post_scalars(P, S_RR, 2, 0);
+  v.phase = PH_ITER;
+}
+
+void enqueue_final(gllmg_problem* P) {
+  auto& v = P->sv;
+  const int64_t N = P->L[0].g.N;
+  if (v.n0 > 0.0 && std::isfinite(v.n0)) {
+    residual(P, 0, 0, v.b, v.x, P->pt, v.s);
+    dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, v.s);
+  }
+  post_scalars(P, S_B, 1, 2);
+  v.phase = PH_FINAL;
+}
+
+void solve_begin(gllmg_problem* P, int mode, const double* b, double* x, double rtol, int maxit,
+                 hipStream_t s) {
+  auto& v = P->sv;
+  GLLMG_CHECK(!v.active, GLLMG_EINVAL, "a solve is already in progress on this problem");
+  hipEvent_t ev = v.ev;
+  if (!ev) GLLMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  v = gllmg_problem::Solve{};
+  v.ev = ev;
+  v.active = true;
+  v.mode = mode;
+  v.b = b;
+  v.x = x;
+  v.rtol = rtol;
+  v.maxit = maxit;
+  v.s = s;
+  v.t0 = std::chrono::steady_clock::now();
+  for (auto& lv : P->L) v.a0.push_back(lv.applies);
+  const int64_t N = P->L[0].g.N;
+  residual(P, 0, 0, b, x, P->pr, s);
+  dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, s);
+  post_scalars(P, S_RR, 1, 0);
+  v.phase = PH_INIT;
+}
+
+// Advance without blocking; returns true when the solve has finished.
+bool solve_poll(gllmg_problem* P) {
+  auto& v = P->sv;
+  GLLMG_CHECK(v.active, GLLMG_EINVAL, "no solve in progress");
+  while (!v.done) {
+    const hipError_t q = hipEventQuery(v.ev);
+    if (q == hipErrorNotReady) return false;
+    if (q != hipSuccess) throw Error(GLLMG_EDEVICE, std::string("hipEventQuery: ") + hipGetErrorString(q));
+    const int64_t N = P->L[0].g.N;
+    if (v.phase == PH_INIT) {
+      v.n0 = std::sqrt(P->hbuf[0]);
+      v.nr = v.n0;
+      v.hist.assign(1, v.n0);
+      v.conv = v.n0 == 0.0;
+      v.breakdown = !std::isfinite(v.n0);
+      if (v.conv || v.breakdown) {
+        enqueue_final(P);
+        continue;
+      }
+      if (v.mode == GLLMG_MODE_PCG) {
+        precond(P, P->pr, P->pz, v.s);
+        dot(0, N, P->pz, P->pr, P->part, P->scal + S_G0, v.s);
+        vec_copy(0, N, P->pz, P->pp, v.s);
+        v.g = S_G0;
+      }
+      enqueue_iteration(P);
+    } else if (v.phase == PH_ITER) {
+      const double rr = P->hbuf[0], ph = P->hbuf[1];
+      ++v.iters;
+      v.nr = std::sqrt(rr);
+      v.hist.push_back(v.nr);
+      if ((v.mode == GLLMG_MODE_PCG && !(ph > 0.0)) || !std::isfinite(v.nr)) {
+        v.breakdown = true;
+        enqueue_final(P);
+      } else if (v.nr <= v.rtol * v.n0) {
+        v.conv = true;
+        enqueue_final(P);
+      } else if (v.iters >= v.maxit) {
+        enqueue_final(P);
+      } else {
+        if (v.mode == GLLMG_MODE_PCG) {
+          precond(P, P->pr, P->pz, v.s);
+          const int gn = v.g == S_G0 ? S_G1 : S_G0;
+          dot(0, N, P->pz, P->pr, P->part, P->scal + gn, v.s);
+          pcg_update_p(N, P->scal, gn, v.g, P->pp, P->pz, v.s);
+          v.g = gn;
+        }
+        enqueue_iteration(P);
+      }
+    } else {
+      v.rt = (v.n0 > 0.0 && std::isfinite(v.n0)) ? std::sqrt(P->hbuf[2]) / v.n0 : 0.0;
+      v.done = true;
+    }
+  }
+  return true;
+}
+
+gllmg_status solve_end(gllmg_problem* P, gllmg_solve_stats* st) {
+  auto& v = P->sv;
+  GLLMG_CHECK(v.active, GLLMG_EINVAL, "no solve in progress");
+  while (!solve_poll(P)) GLLMG_HIP(hipEventSynchronize(v.ev));
+  v.active = false;
+  if (st) {
+    st->iters = v.iters;
+    st->converged = v.conv ? 1 : 0;
+    st->relres = v.n0 > 0.0 ? v.nr / v.n0 : 0.0;
+    st->relres_true = v.rt;
+    for (int i = 0; i < 16; ++i) st->applies[i] = 0;
+    for (size_t i = 0; i < P->L.size() && i < 16; ++i) st->applies[i] = P->L[i].applies - v.a0[i];
+    if (st->history)
+      for (size_t i = 0; i < v.hist.size() && i <= (size_t)v.maxit; ++i) st->history[i] = v.hist[i];
+    st->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - v.t0).count();
+  }
+  if (v.breakdown) throw Error(GLLMG_EBREAKDOWN, "breakdown: non-finite residual or p^T A p <= 0");
+  if (!v.conv) return GLLMG_ENOTCONV;
+  return GLLMG_OK;
+}
 
 gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, double rtol,
                         int maxit, gllmg_solve_stats* st, hipStream_t s) {
-  auto t0 = std::chrono::steady_clock::now();
-  Level& L = P->L[0];
-  const int64_t N = L.g.N;
-  std::vector<int64_t> a0;
-  for (auto& lv : P->L) a0.push_back(lv.applies);
-  double *r = P->pr, *z = P->pz, *p = P->pp, *h = P->ph;
-  residual(P, 0, 0, b, x, r, s);
-  dot(0, N, r, r, P->part, P->scal + S_RR, s);
-  const double n0 = std::sqrt(read_scalar(P, S_RR, s));
-  std::vector<double> hist{n0};
-  int iters = 0;
-  bool conv = n0 == 0.0;
-  bool breakdown = !std::isfinite(n0);
-  double nr = n0;
-  if (!conv && !breakdown) {
-    if (mode == GLLMG_MODE_PCG) {
-      precond(P, r, z, s);
-      dot(0, N, z, r, P->part, P->scal + S_G0, s);
-      vec_copy(0, N, z, p, s);
-      int g = S_G0;
-      for (int it = 1; it <= maxit; ++it) {
-        apply_level(P, 0, 0, 0, p, h, s);
-        dot(0, N, p, h, P->part, P->scal + S_PH, s);
-        pcg_update_xr(N, P->scal, g, S_PH, x, r, p, h, P->part, P->scal + S_RR, s);
-        double sc[2];
-        read_scalars(P, S_RR, 2, sc, s);
-        iters = it;
-        nr = std::sqrt(sc[0]);
-        hist.push_back(nr);
-        if (!(sc[1] > 0.0) || !std::isfinite(nr)) {
-          breakdown = true;
-          break;
-        }
-        if (nr <= rtol * n0) {
-          conv = true;
-          break;
-        }
-        precond(P, r, z, s);
-        const int gn = g == S_G0 ? S_G1 : S_G0;
-        dot(0, N, z, r, P->part, P->scal + gn, s);
-        pcg_update_p(N, P->scal, gn, g, p, z, s);
-        g = gn;
-      }
-    } else {
-      for (int it = 1; it <= maxit; ++it) {
-        precond(P, r, z, s);
-        vec_axpy(0, N, 1.0, z, x, s);
-        residual(P, 0, 0, b, x, r, s);
-        dot(0, N, r, r, P->part, P->scal + S_RR, s);
-        nr = std::sqrt(read_scalar(P, S_RR, s));
-        iters = it;
-        hist.push_back(nr);
-        if (!std::isfinite(nr)) {
-          breakdown = true;
-          break;
-        }
-        if (nr <= rtol * n0) {
-          conv = true;
-          break;
-        }
-      }
-    }
-  }
-  // true residual in FP64
-  double rt = 0.0;
-  if (n0 > 0.0 && std::isfinite(n0)) {
-    residual(P, 0, 0, b, x, P->pt, s);
-    dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, s);
-    rt = std::sqrt(read_scalar(P, S_B, s)) / n0;
-  }
-  GLLMG_HIP(hipStreamSynchronize(s));
-  if (st) {
-    st->iters = iters;
-    st->converged = conv ? 1 : 0;
-    st->relres = n0 > 0.0 ? nr / n0 : 0.0;
-    st->relres_true = rt;
-    for (int i = 0; i < 16; ++i) st->applies[i] = 0;
-    for (size_t i = 0; i < P->L.size() && i < 16; ++i) st->applies[i] = P->L[i].applies - a0[i];
-    if (st->history)
-      for (size_t i = 0; i < hist.size() && i <= (size_t)maxit; ++i) st->history[i] = hist[i];
-    st->t_solve_s =
-        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
-  if (breakdown) throw Error(GLLMG_EBREAKDOWN, "breakdown: non-finite residual or p^T A p <= 0");
-  if (!conv) return GLLMG_ENOTCONV;
-  return GLLMG_OK;
+  solve_begin(P, mode, b, x, rtol, maxit, s);
+  return solve_end(P, st);
 }
 
 thread_local std::string g_err;
@@ -839,6 +913,8 @@ gllmg_status gllmg_destroy(gllmg_problem* P) {
     if (!P) return GLLMG_OK;
     drop_graph(P);
     if (P->cap) (void)hipStreamDestroy(P->cap);
+    if (P->xs) (void)hipStreamDestroy(P->xs);
+    if (P->sv.ev) (void)hipEventDestroy(P->sv.ev);
     if (P->owns_ws) (void)hipFree(P->ws);
     if (P->hbuf) (void)hipHostFree(P->hbuf);
     delete P;
@@ -1016,6 +1092,95 @@ gllmg_status gllmg_solve(const gllmg_problem* P, int32_t mode, const double* b, 
                                 (hipStream_t)stream);
     if (r == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached";
     return r;
+  });
+}
+
+gllmg_status gllmg_solve_begin(gllmg_problem* P, int32_t mode, const double* b, double* x,
+                               double rtol, int32_t maxit, void* stream) {
+  return guard([&]() {
+    level_of(P, 0);
+    GLLMG_CHECK(mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG, GLLMG_EINVAL, "unknown mode");
+    check_ptr(b, 8, "b");
+    check_ptr(x, 8, "x");
+    GLLMG_CHECK(rtol > 0.0 && maxit >= 1, GLLMG_EINVAL, "rtol must be > 0 and maxit >= 1");
+    GLLMG_CHECK(P->L.back().Ainv64 != nullptr, GLLMG_EUNSUPPORTED,
+                "the coarsest level is too large for the dense exact solve");
+    solve_begin(P, mode, b, x, rtol, maxit, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_solve_poll(gllmg_problem* P, int32_t* done) {
+  return guard([&]() {
+    GLLMG_CHECK(P && done, GLLMG_EINVAL, "NULL argument");
+    *done = solve_poll(P) ? 1 : 0;
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_solve_end(gllmg_problem* P, gllmg_solve_stats* st) {
+  return guard([&]() {
+    GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+    gllmg_status r = solve_end(P, st);
+    if (r == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached";
+    return r;
+  });
+}
+
+gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const* b,
+                               double* const* x, int32_t count, int32_t mode, double rtol,
+                               int32_t maxit, gllmg_solve_stats* stats, gllmg_status* status,
+                               void* stream) {
+  return guard([&]() {
+    GLLMG_CHECK(count >= 0 && (count == 0 || (probs && b && x)), GLLMG_EINVAL, "NULL argument");
+    hipStream_t cs = (hipStream_t)stream;
+    hipEvent_t start = nullptr;
+    GLLMG_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
+    GLLMG_HIP(hipEventRecord(start, cs));
+    std::vector<int> live;
+    gllmg_status worst = GLLMG_OK;
+    auto fail = [&](int i, gllmg_status st) {
+      if (status) status[i] = st;
+      if (worst == GLLMG_OK || worst == GLLMG_ENOTCONV) worst = st;
+    };
+    for (int i = 0; i < count; ++i) {
+      gllmg_problem* P = probs[i];
+      GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+      if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
+      GLLMG_HIP(hipStreamWaitEvent(P->xs, start, 0));
+      const gllmg_status st = gllmg_solve_begin(P, mode, b[i], x[i], rtol, maxit, P->xs);
+      if (st != GLLMG_OK) {
+        fail(i, st);
+        continue;
+      }
+      live.push_back(i);
+    }
+    // iteration-level interleaving: every live problem advances as soon as its last
+    // iteration's scalars have arrived
+    std::vector<char> fin(count, 0);
+    size_t left = live.size();
+    while (left > 0) {
+      bool progressed = false;
+      for (int i : live) {
+        if (fin[i]) continue;
+        if (solve_poll(probs[i])) {
+          fin[i] = 1;
+          --left;
+          progressed = true;
+          const gllmg_status st = gllmg_solve_end(probs[i], stats ? &stats[i] : nullptr);
+          if (status) status[i] = st;
+          if (st != GLLMG_OK) fail(i, st);
+        }
+      }
+      if (!progressed && left > 0) std::this_thread::yield();
+    }
+    for (int i : live) {
+      GLLMG_HIP(hipEventRecord(probs[i]->sv.ev, probs[i]->xs));
+      GLLMG_HIP(hipStreamWaitEvent(cs, probs[i]->sv.ev, 0));
+    }
+    (void)hipEventDestroy(start);
+    if (worst == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached in a problem";
+    return worst;
   });
 }
 

@@ -61,7 +61,8 @@ EXPORTS = ["gllmg_last_error", "gllmg_config_default", "gllmg_plan", "gllmg_setu
            "gllmg_destroy", "gllmg_num_levels", "gllmg_level_info", "gllmg_set_lmax",
            "gllmg_set_graphs",
            "gllmg_node_coords", "gllmg_eval_field", "gllmg_rhs", "gllmg_diag", "gllmg_apply",
-           "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve"]
+           "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve",
+           "gllmg_solve_begin", "gllmg_solve_poll", "gllmg_solve_end", "gllmg_batch_solve"]
 
 
 def lib():
@@ -95,6 +96,11 @@ def lib():
     L.gllmg_restrict.argtypes = [vp, i32, i32, vp, vp, vp]
     L.gllmg_vcycle.argtypes = [vp, i32, vp, vp, vp]
     L.gllmg_solve.argtypes = [vp, i32, vp, vp, dbl, i32, C.POINTER(SolveStats), vp]
+    L.gllmg_solve_begin.argtypes = [vp, i32, vp, vp, dbl, i32, vp]
+    L.gllmg_solve_poll.argtypes = [vp, C.POINTER(i32)]
+    L.gllmg_solve_end.argtypes = [vp, C.POINTER(SolveStats)]
+    L.gllmg_batch_solve.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32, i32, dbl,
+                                    i32, C.POINTER(SolveStats), C.POINTER(C.c_int), vp]
     for name in EXPORTS[2:]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -323,10 +329,66 @@ class Problem:
                                    C.byref(st), _stream(stream))
         if status not in (OK, ENOTCONV) or (status == ENOTCONV and raise_on_notconv):
             _check(status)
-        return SolveResult(status=status, iters=st.iters, converged=bool(st.converged),
-                           relres=st.relres, relres_true=st.relres_true, t_solve_s=st.t_solve_s,
-                           applies=list(st.applies[:self.nlevels]),
-                           history=list(hist[:st.iters + 1]))
+        return _result(status, st, hist, self.nlevels)
+
+    def solve_async(self, b, x, mode="pcg", rtol=1e-10, maxit=500, stream=None) -> AsyncSolve:
+        return AsyncSolve(self, b, x, mode, rtol, maxit, stream)
+
+
+class AsyncSolve:
+    """A solve in progress (gllmg_solve_begin / _poll / _end)."""
+
+    def __init__(self, prob: "Problem", b, x, mode="pcg", rtol=1e-10, maxit=500, stream=None):
+        self.prob, self.b, self.x, self.maxit = prob, b, x, maxit
+        self.hist = (C.c_double * (maxit + 1))()
+        m = MODE_PCG if mode == "pcg" else MODE_MG
+        _check(lib().gllmg_solve_begin(prob.h, m, _ptr(b), _ptr(x), float(rtol), int(maxit),
+                                       _stream(stream)))
+        self.result = None
+
+    def poll(self) -> bool:
+        if self.result is not None:
+            return True
+        d = C.c_int32()
+        _check(lib().gllmg_solve_poll(self.prob.h, C.byref(d)))
+        if d.value:
+            self.finish()
+        return self.result is not None
+
+    def finish(self) -> "SolveResult":
+        if self.result is None:
+            st = SolveStats()
+            st.history = C.cast(self.hist, C.POINTER(C.c_double))
+            status = lib().gllmg_solve_end(self.prob.h, C.byref(st))
+            if status not in (OK, ENOTCONV):
+                _check(status)
+            self.result = _result(status, st, self.hist, self.prob.nlevels)
+        return self.result
+
+
+def _result(status, st, hist, nlevels):
+    return SolveResult(status=status, iters=st.iters, converged=bool(st.converged),
+                       relres=st.relres, relres_true=st.relres_true, t_solve_s=st.t_solve_s,
+                       applies=list(st.applies[:nlevels]), history=list(hist[:st.iters + 1]))
+
+
+def batch_solve(problems, bs, xs, mode="pcg", rtol=1e-10, maxit=500, stream=None):
+    """gllmg_batch_solve over Problem objects with per-problem FP64 vectors."""
+    n = len(problems)
+    P = (C.c_void_p * n)(*[p.h for p in problems])
+    B = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    stats = (SolveStats * n)()
+    hists = [(C.c_double * (maxit + 1))() for _ in range(n)]
+    for i in range(n):
+        stats[i].history = C.cast(hists[i], C.POINTER(C.c_double))
+    status = (C.c_int * n)()
+    m = MODE_PCG if mode == "pcg" else MODE_MG
+    st = lib().gllmg_batch_solve(P, B, X, n, m, float(rtol), int(maxit), stats, status,
+                                 _stream(stream))
+    if st not in (OK, ENOTCONV):
+        _check(st)
+    return [_result(status[i], stats[i], hists[i], problems[i].nlevels) for i in range(n)]
 
 
 def _prec_of(t):

@@ -69,8 +69,108 @@ def cpu_baseline():
                       f"{reps} solves in {el:.1f} s, setup excluded"}
 
 
+def _solve_timed(G, b, steps, warmup, rtol, maxit):
+    import torch
+    x = torch.zeros_like(b)
+    for _ in range(warmup):
+        x.zero_()
+        G.solve(b, x, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        x.zero_()
+        r = G.solve(b, x, rtol=rtol, maxit=maxit)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, r, x
+
+
+def workload_mixed(a):
+    """Mixed precision on the 3D warped problem with 8^3 hexes at p = 16 (2,146,689 nodes),
+    f ~ U[-1,1] (seed 0): FP32 V-cycle inside FP64 PCG versus the all-FP64 solve, both to
+    1e-10; the FP32 solution's error is measured against a tight (1e-13) FP64 solve."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    out = {}
+    sols = {}
+    for prec in ("f64", "f32"):
+        prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0)
+        G = gllmg.Problem.from_inputs(prob)
+        b = G.rhs(torch.from_numpy(prob.nodal_rhs()).cuda())
+        t, r, x = _solve_timed(G, b, a.steps, a.warmup, 1e-10, 500)
+        out[prec] = {"time_to_solution_ms": t * 1e3, "pcg_iterations": r.iters,
+                     "relres_true": r.relres_true}
+        sols[prec] = x.clone()
+        if prec == "f64":
+            xt = torch.zeros_like(b)
+            G.solve(b, xt, rtol=1e-13, maxit=500)
+            sols["tight"] = xt
+        G.close()
+    u = sols["tight"]
+    for prec in ("f64", "f32"):
+        out[prec]["rel_error_vs_fp64_tight"] = float(torch.linalg.norm(sols[prec] - u) /
+                                                     torch.linalg.norm(u))
+    out["speedup_mixed_over_fp64"] = out["f64"]["time_to_solution_ms"] / out["f32"]["time_to_solution_ms"]
+    return {"workload": "mixed: 3D warped var 8^3 p=16, N=2146689, PCG to 1e-10", **out}
+
+
+def workload_batch(a):
+    """256 independent 3D problems on 4^3 hexes, p uniform in {2,4,8,16}, mu = exp(random
+    Fourier field), f ~ U[-1,1], FP32 V-cycle + FP64 PCG, all solved by one batched call."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    probs = inputs.batched_problems(seed=0, count=a.batch_count)
+    t0 = time.perf_counter()
+    Gs, bs = [], []
+    for pr in probs:
+        G = gllmg.Problem.from_inputs(pr)
+        Gs.append(G)
+        bs.append(G.rhs(torch.from_numpy(pr.nodal_rhs()).cuda()))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    xs = [torch.zeros_like(b) for b in bs]
+    res = gllmg.batch_solve(Gs, bs, xs, rtol=1e-10)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(max(1, a.steps)):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = gllmg.batch_solve(Gs, bs, xs, rtol=1e-10)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    nodes = sum(G.nnodes(0) for G in Gs)
+    ok = sum(r.converged for r in res)
+    for G in Gs:
+        G.close()
+    return {"workload": f"batch: {len(probs)} x 3D 4^3 hexes, p in {{2,4,8,16}}, FP32 V-cycle + FP64 PCG to 1e-10",
+            "batch_time_ms": best * 1e3, "solves_per_s": len(probs) / best,
+            "gdof_solves_per_s": nodes / best / 1e9, "total_nodes": nodes, "converged": ok,
+            "setup_s": t_setup, "max_iters": max(r.iters for r in res)}
+
+
+def workload_serve(a):
+    """Poisson-arrival stream (mean 200 req/s) of mixed 2D/3D solves to 1e-8 under an HBM
+    budget; p50/p99 latency and solves/s over the first a.serve_s seconds of arrivals."""
+    from paper_1402_5938_amd import inputs
+    from paper_1402_5938_amd.serve import Server
+    trace = inputs.serving_trace(seed=0, rate=200.0, duration_s=a.serve_s)
+    srv = Server(hbm_budget=int(a.hbm_gb * 2 ** 30), max_active=64)
+    rep = srv.run(trace, time_scale=1.0, max_wall_s=a.serve_s * 20 + 60)
+    srv.close()
+    return {"workload": f"serve: {len(trace)} requests over {a.serve_s} s at 200 req/s, "
+                        f"budget {a.hbm_gb} GiB", **rep}
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve"])
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--serve-s", type=float, default=2.0)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
@@ -89,6 +189,10 @@ def main():
     from paper_1402_5938_amd import gllmg, inputs
 
     torch.cuda.set_device(0)
+    if a.workload != "config2":
+        fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve}[a.workload]
+        print(json.dumps(fn(a)))
+        return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
     cfg = gllmg.make_config(3, prob.nelem, prob.order, "p", "chebyshev", prob.nu)
     t_setup = time.perf_counter()

@@ -343,17 +343,17 @@ void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
     }
     GLLMG_CHECK(ridx.size() <= (size_t)t.nf * nw, GLLMG_EINVAL, "transfer table overflow");
     std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-    GLLMG_HIP(hipMemcpy(t.pstart, pstart.data(), sizeof(int) * t.nf, hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(t.pw64, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(t.pw32, pw32.data(), sizeof(float) * pw32.size(), hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(t.rptr, rptr.data(), sizeof(int) * rptr.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpyAsync(t.pstart, pstart.data(), sizeof(int) * t.nf, hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(t.pw64, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(t.pw32, pw32.data(), sizeof(float) * pw32.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(t.rptr, rptr.data(), sizeof(int) * rptr.size(), hipMemcpyHostToDevice, s));
     if (!ridx.empty()) {
-      GLLMG_HIP(hipMemcpy(t.ridx, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice));
-      GLLMG_HIP(hipMemcpy(t.rw64, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice));
-      GLLMG_HIP(hipMemcpy(t.rw32, rw32.data(), sizeof(float) * rw32.size(), hipMemcpyHostToDevice));
+      GLLMG_HIP(hipMemcpyAsync(t.ridx, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(t.rw64, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(t.rw32, rw32.data(), sizeof(float) * rw32.size(), hipMemcpyHostToDevice, s));
     }
+    GLLMG_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
   }
-  (void)s;
 }
 
 // lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
@@ -431,9 +431,10 @@ void build_coarse_inverse(gllmg_problem* P, hipStream_t s) {
     }
   GLLMG_CHECK(spd_inverse(A, (int)ni), GLLMG_EINVAL, "coarsest operator is not SPD");
   std::vector<float> A32(A.begin(), A.end());
-  GLLMG_HIP(hipMemcpy(L.Ainv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice));
+  GLLMG_HIP(hipMemcpyAsync(L.Ainv64, A.data(), sizeof(double) * A.size(), hipMemcpyHostToDevice, s));
   if (L.Ainv32)
-    GLLMG_HIP(hipMemcpy(L.Ainv32, A32.data(), sizeof(float) * A32.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpyAsync(L.Ainv32, A32.data(), sizeof(float) * A32.size(), hipMemcpyHostToDevice, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
   L.applies = 0;
 }
 
@@ -457,10 +458,11 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
     P->re.push_back(ref_element(L.g.p));
     const RefElem& r = P->re.back();
     std::vector<float> D32(r.D.begin(), r.D.end());
-    GLLMG_HIP(hipMemcpy(L.D64, r.D.data(), sizeof(double) * r.D.size(), hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(L.xi64, r.xi.data(), sizeof(double) * r.xi.size(), hipMemcpyHostToDevice));
-    GLLMG_HIP(hipMemcpy(L.w64, r.w.data(), sizeof(double) * r.w.size(), hipMemcpyHostToDevice));
+    GLLMG_HIP(hipMemcpyAsync(L.D64, r.D.data(), sizeof(double) * r.D.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(L.xi64, r.xi.data(), sizeof(double) * r.xi.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync(L.w64, r.w.data(), sizeof(double) * r.w.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipStreamSynchronize(s));  // D32 goes out of scope
   }
   for (size_t l = 0; l < P->L.size(); ++l) {
     Level& L = P->L[l];
@@ -593,12 +595,14 @@ void drop_graph(gllmg_problem* P) {
 }
 
 // Capture the launch sequence of one V-cycle from P->pr to P->pz (kernels only: no copies,
-// memsets or synchronization) on a private stream of default priority.
+// memsets or synchronization) on a private stream of default priority. Relaxed mode: other
+// threads of the process (a server's setup thread, say) may keep issuing synchronous HIP
+// calls while the capture is open.
 void capture_vcycle(gllmg_problem* P) {
   if (!P->cap) GLLMG_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
   std::vector<int64_t> a0;
   for (auto& L : P->L) a0.push_back(L.applies);
-  GLLMG_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  GLLMG_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
   hipGraph_t g = nullptr;
   try {
     precond_eager(P, P->pr, P->pz, P->cap);
@@ -625,7 +629,17 @@ void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
     precond_eager(P, r, z, s);
     return;
   }
-  if (!P->vexec) capture_vcycle(P);
+  if (!P->vexec) {
+    try {
+      capture_vcycle(P);
+    } catch (const Error&) {
+      // the same kernels are launched one by one instead
+      (void)hipGetLastError();
+      P->use_graph = false;
+      precond_eager(P, r, z, s);
+      return;
+    }
+  }
   GLLMG_HIP(hipGraphLaunch(P->vexec, s));
   for (size_t l = 0; l < P->L.size(); ++l) P->L[l].applies += P->vapplies[l];
 }
@@ -902,6 +916,15 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
     layout(P.get(), specs, A);
     GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
     setup_impl(P.get(), map, mu, s);
+    if (P->L.back().Ainv64) {
+      // capture the solve's V-cycle now, while nothing else of this problem is in flight
+      try {
+        capture_vcycle(P.get());
+      } catch (const Error&) {
+        (void)hipGetLastError();
+        P->use_graph = false;
+      }
+    }
     guard_free.armed = false;
     *out = P.release();
     return GLLMG_OK;

@@ -1,0 +1,230 @@
+"""Continuous-batching solve server on one GPU.
+
+Requests (problem descriptions with an arrival time) are admitted against an HBM budget by
+their exact device footprint (gllmg_plan's workspace plus the request's own vectors). A setup
+thread builds each admitted request's hierarchy, which then stays resident in HBM until its
+solve finishes. The serving loop keeps every active solve moving iteration by iteration
+(gllmg_solve_begin / _poll / _end): requests that arrive while others are on the GPU join as
+soon as memory and a slot are free, and their iterations overlap on the device's queues.
+Nothing here computes any part of the method: every step runs in libgllmg.
+"""
+
+from __future__ import annotations
+
+import collections
+import dataclasses
+import queue
+import threading
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import gllmg
+from .inputs import Problem, Request
+
+
+class HbmLedger:
+    """Bytes promised to admitted requests, against a fixed budget."""
+
+    def __init__(self, budget: int):
+        self.budget = int(budget)
+        self.used = 0
+        self.peak = 0
+        self._lock = threading.Lock()
+
+    def try_reserve(self, nbytes: int) -> bool:
+        with self._lock:
+            if self.used + nbytes > self.budget:
+                return False
+            self.used += nbytes
+            self.peak = max(self.peak, self.used)
+            return True
+
+    def release(self, nbytes: int):
+        with self._lock:
+            self.used -= nbytes
+            assert self.used >= 0
+
+
+def request_config(prob: Problem) -> gllmg.Config:
+    return gllmg.make_config(prob.dim, prob.nelem, prob.order, prob.hierarchy, prob.smoother,
+                             prob.nu, vcycle_prec=prob.vcycle_prec, max_levels=prob.max_levels,
+                             eig_seed=prob.eig_seed)
+
+
+def request_footprint(prob: Problem) -> int:
+    """Device bytes of one request: the library workspace plus f, b and x (FP64)."""
+    _, ws = gllmg.plan(request_config(prob))
+    return ws + 256 + 3 * 8 * prob.nnodes
+
+
+@dataclasses.dataclass
+class Record:
+    rid: int
+    name: str
+    nnodes: int
+    footprint: int
+    arrival: float
+    admitted: float = float("nan")
+    ready: float = float("nan")
+    started: float = float("nan")
+    finished: float = float("nan")
+    iters: int = -1
+    converged: bool = False
+    relres_true: float = float("nan")
+    status: int = -1
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Server:
+    def __init__(self, hbm_budget: int, max_active: int = 64, nstreams: int = 8,
+                 keep_solutions: bool = False):
+        import torch
+        self.ledger = HbmLedger(hbm_budget)
+        self.max_active = max_active
+        self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
+        self.keep = keep_solutions
+        self.solutions: Dict[int, object] = {}
+        self.records: Dict[int, Record] = {}
+        self._ready: "queue.Queue" = queue.Queue()
+        self._todo: "queue.Queue" = queue.Queue()
+        self._setup_thread = threading.Thread(target=self._setup_worker, daemon=True)
+        self._setup_thread.start()
+        self._t0 = 0.0
+
+    def now(self) -> float:
+        return time.perf_counter() - self._t0
+
+    # ----------------------------------------------------------------- setup thread
+    def _setup_worker(self):
+        import torch
+        s = torch.cuda.Stream()
+        while True:
+            item = self._todo.get()
+            if item is None:
+                return
+            req, rec = item
+            try:
+                with torch.cuda.stream(s):
+                    P = gllmg.Problem(request_config(req.problem), req.problem.map,
+                                      req.problem.mu, stream=s)
+                    fn = req.problem.nodal_rhs()
+                    if fn is None:
+                        f = P.eval_field(req.problem.f, stream=s)
+                    else:
+                        f = torch.from_numpy(fn).to("cuda", non_blocking=False)
+                    b = P.rhs(f, stream=s)
+                    x = torch.zeros_like(b)
+                    del f
+                s.synchronize()
+                rec.ready = self.now()
+                self._ready.put((req, rec, P, b, x))
+            except Exception as e:  # reported per request; the ledger is released by the loop
+                rec.error = str(e)
+                self._ready.put((req, rec, None, None, None))
+
+    # ----------------------------------------------------------------- serving loop
+    def run(self, trace: List[Request], time_scale: float = 1.0,
+            max_wall_s: Optional[float] = None) -> dict:
+        """Serve `trace` (arrival times multiplied by time_scale) until every request is done
+        or max_wall_s has passed. Returns the report."""
+        pending = collections.deque(sorted(trace, key=lambda r: r.arrival_s))
+        waiting: collections.deque = collections.deque()
+        active = []  # (req, rec, P, b, x, async)
+        in_setup = 0
+        rr = 0
+        self._t0 = time.perf_counter()
+        for req in trace:
+            self.records[req.rid] = Record(req.rid, req.problem.name, req.problem.nnodes,
+                                           request_footprint(req.problem),
+                                           req.arrival_s * time_scale)
+        while pending or waiting or active or in_setup:
+            now = self.now()
+            if max_wall_s is not None and now > max_wall_s:
+                break
+            progressed = False
+            while pending and pending[0].arrival_s * time_scale <= now:
+                waiting.append(pending.popleft())
+            # FIFO admission by footprint and slots
+            while waiting and len(active) + in_setup < self.max_active:
+                req = waiting[0]
+                rec = self.records[req.rid]
+                if rec.footprint > self.ledger.budget:
+                    rec.error = "request larger than the HBM budget"
+                    rec.finished = now
+                    waiting.popleft()
+                    continue
+                if not self.ledger.try_reserve(rec.footprint):
+                    break
+                waiting.popleft()
+                rec.admitted = now
+                in_setup += 1
+                self._todo.put((req, rec))
+                progressed = True
+            # hierarchies that finished setting up start solving
+            while True:
+                try:
+                    req, rec, P, b, x = self._ready.get_nowait()
+                except queue.Empty:
+                    break
+                in_setup -= 1
+                progressed = True
+                if P is None:
+                    rec.finished = self.now()
+                    self.ledger.release(rec.footprint)
+                    continue
+                st = self.streams[rr % len(self.streams)]  # setup already synchronized
+                rr += 1
+                a = P.solve_async(b, x, rtol=req.problem.rtol, maxit=req.problem.maxit, stream=st)
+                rec.started = self.now()
+                active.append((req, rec, P, b, x, a))
+            # advance every active solve without blocking
+            still = []
+            for item in active:
+                req, rec, P, b, x, a = item
+                if a.poll():
+                    res = a.result
+                    rec.finished = self.now()
+                    rec.iters, rec.converged = res.iters, res.converged
+                    rec.relres_true, rec.status = res.relres_true, res.status
+                    if self.keep:
+                        self.solutions[req.rid] = x.clone()
+                    P.close()
+                    del b
+                    self.ledger.release(rec.footprint)
+                    progressed = True
+                else:
+                    still.append(item)
+            active = still
+            if not progressed:
+                time.sleep(20e-6)
+        return self.report()
+
+    def close(self):
+        self._todo.put(None)
+        self._setup_thread.join(timeout=60)
+
+    def report(self) -> dict:
+        done = [r for r in self.records.values() if r.converged and np.isfinite(r.finished)]
+        failed = [r for r in self.records.values() if r.error or (np.isfinite(r.finished) and not r.converged)]
+        lat = np.array([r.latency for r in done]) if done else np.array([np.nan])
+        t_first = min((r.arrival for r in self.records.values()), default=0.0)
+        t_last = max((r.finished for r in done), default=0.0)
+        span = max(t_last - t_first, 1e-9)
+        dofs = sum(r.nnodes for r in done)
+        return {
+            "requests": len(self.records), "completed": len(done), "failed": len(failed),
+            "solves_per_s": len(done) / span, "gdof_solves_per_s": dofs / span / 1e9,
+            "p50_latency_s": float(np.nanpercentile(lat, 50)),
+            "p99_latency_s": float(np.nanpercentile(lat, 99)),
+            "mean_admission_wait_s": float(np.nanmean([r.admitted - r.arrival for r in done])) if done else float("nan"),
+            "mean_setup_s": float(np.nanmean([r.ready - r.admitted for r in done])) if done else float("nan"),
+            "mean_solve_s": float(np.nanmean([r.finished - r.started for r in done])) if done else float("nan"),
+            "hbm_budget": self.ledger.budget, "hbm_peak_reserved": self.ledger.peak,
+            "span_s": span,
+        }

@@ -201,7 +201,8 @@ gllmg_status gllmg_vcycle(const gllmg_problem* prob, gllmg_prec prec, const void
  * problem's vcycle_prec; the outer iteration, residuals and dot products are FP64. Stops
  * when ||r|| <= rtol ||r_0|| (§4.3). b, x: FP64 device vectors; x is the initial guess on
  * entry. stats may be NULL. Synchronous. ENOTCONV: maxit reached (x = last iterate, stats
- * filled). EBREAKDOWN: non-finite residual or p^T A p <= 0. */
+ * filled). EBREAKDOWN: non-finite residual or p^T A p <= 0. EUNSUPPORTED: the coarsest level
+ * has more than 4096 interior nodes, so no exact coarse solve was set up. */
 gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* b, double* x,
                          double rtol, int32_t maxit, gllmg_solve_stats* stats, void* stream);
 
@@ -212,7 +213,9 @@ gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* 
  * the next iteration and sets *done = 1 once the solve (including the final true residual) has
  * finished. gllmg_solve_end waits for completion if needed, fills stats and returns the status
  * gllmg_solve would have returned. Iterates and counts are identical to gllmg_solve. One solve
- * per problem at a time; b and x must stay valid until gllmg_solve_end. */
+ * per problem at a time; b and x must stay valid until gllmg_solve_end. An error returned by
+ * gllmg_solve_poll ends the solve (the stream is drained first; gllmg_solve_end is not called
+ * afterwards) and the problem accepts a new gllmg_solve_begin. */
 gllmg_status gllmg_solve_begin(gllmg_problem* prob, int32_t mode, const double* b, double* x,
                                double rtol, int32_t maxit, void* stream);
 gllmg_status gllmg_solve_poll(gllmg_problem* prob, int32_t* done);
@@ -221,8 +224,10 @@ gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
 /* Solve `count` independent problems (any mix of dimension, mesh, order and precision), each
  * on its own internal stream ordered after `stream`, advanced iteration by iteration from one
  * host thread; `stream` waits for all of them before the call returns. stats and status may be
- * NULL, else arrays of `count`. Returns GLLMG_OK if every solve converged, else the first
- * error (status[i] holds each problem's own status). */
+ * NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
+ * any solve starts: EINVAL). Returns GLLMG_OK if every solve converged, else the first error
+ * other than ENOTCONV if any, else ENOTCONV (status[i] holds each problem's own status; a
+ * problem that fails does not stop the others). */
 gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const* b,
                                double* const* x, int32_t count, int32_t mode, double rtol,
                                int32_t maxit, gllmg_solve_stats* stats, gllmg_status* status,

@@ -161,6 +161,21 @@ class Stiffness:
             y += self.B[a].T @ wa
         return y
 
+    def matvec_abs(self, x):
+        """|B|^T |G| |B| |x|: every product of the factored sum taken in absolute value. It
+        bounds |A x| entrywise and is the scale of the rounding error of any evaluation order
+        of A x; it is a yardstick for comparisons, not part of the method."""
+        d = self.mesh.dim
+        ax = np.abs(x)
+        u = [abs(self.B[b]) @ ax for b in range(d)]
+        y = np.zeros(self.mesh.N)
+        for a in range(d):
+            wa = np.zeros_like(u[0])
+            for b in range(d):
+                wa += np.abs(self.G[:, a, b]) * u[b]
+            y += abs(self.B[a]).T @ wa
+        return y
+
     def csr(self):
         """The assembled stiffness as a CSR matrix."""
         d = self.mesh.dim
@@ -197,6 +212,12 @@ class LevelOperator:
         if neumann:
             return self.K.matvec(x)
         return self.mask * self.K.matvec(self.mask * x)
+
+    def apply_abs(self, x, neumann=False):
+        """The rounding scale |B|^T |G| |B| |x| of apply(x) (see Stiffness.matvec_abs)."""
+        if neumann:
+            return self.K.matvec_abs(x)
+        return self.mask * self.K.matvec_abs(self.mask * x)
 
     def diag(self):
         return self.mask * self.K.diagonal()

@@ -111,6 +111,7 @@ struct Arena {
 struct RefElem {
   int p;
   std::vector<double> xi, w, D;   // D[i*(p+1)+l] = l_l'(xi_i)
+  std::vector<double> lam;        // barycentric weights of the nodes xi
 };
 RefElem ref_element(int p);
 // Lagrange basis of the order-p GLL nodes evaluated at point y: out[j] = l_j(y).
@@ -146,6 +147,7 @@ enum EpiMode { EPI_STORE = 0, EPI_RESIDUAL = 1, EPI_JACOBI = 2, EPI_CHEB = 3, EP
 struct Epi {
   int mode = EPI_STORE;
   int from_zero = 0;
+  int last = 0;  // CHEB: also add the next d into x; r and d are not written
   void* y = nullptr;
   const void* b = nullptr;
   void* x = nullptr;

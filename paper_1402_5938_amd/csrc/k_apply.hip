@@ -24,7 +24,7 @@ __host__ __device__ inline int nloc_of(int n, int dim) { return dim == 3 ? n * n
 // Typed view of the epilogue.
 template <typename T>
 struct EpiT {
-  int mode, from_zero;
+  int mode, from_zero, last;
   T* y;
   const T* b;
   T* x;
@@ -37,7 +37,7 @@ struct EpiT {
 
 template <typename T>
 EpiT<T> typed(const Epi& e) {
-  return EpiT<T>{e.mode, e.from_zero, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
+  return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
                  (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
 }
 
@@ -61,10 +61,16 @@ __device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
       break;
     }
     default: {  // EPI_CHEB, input vector is d
-      ep.x[g] = ep.from_zero ? xin : ep.x[g] + xin;
+      const T xo = ep.from_zero ? xin : ep.x[g] + xin;
       const T ri = ep.rin[g] - acc;
-      ep.r[g] = ri;
-      ep.d[g] = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
+      const T dn = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
+      if (ep.last) {  // the polynomial's final step: x = (x + d) + d_next, r and d not needed
+        ep.x[g] = xo + dn;
+      } else {
+        ep.x[g] = xo;
+        ep.r[g] = ri;
+        ep.d[g] = dn;
+      }
     }
   }
 }
@@ -88,8 +94,10 @@ __device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
       break;
     default:
       ep.x[g] = T(0);
-      ep.r[g] = T(0);
-      ep.d[g] = T(0);
+      if (!ep.last) {
+        ep.r[g] = T(0);
+        ep.d[g] = T(0);
+      }
   }
 }
 
@@ -105,19 +113,25 @@ struct Epb {
 // ------------------------------------------------------------------ 3D element kernel
 // Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
 // y-contractions read the element tile from LDS, the z-contraction works in registers.
+// High orders keep a long register column per thread: allow up to 256 VGPRs (at most two
+// waves per SIMD) instead of spilling to scratch.
+template <int N>
+struct Waves {
+  static constexpr int max = N >= 12 ? 2 : 8;
+};
+
 template <int N, typename T, int EPB>
-__global__ void __launch_bounds__(EPB * N * N)
+__global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(1, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann) {
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
   __shared__ T sA[EPB * NNN];
   __shared__ T sB[EPB * NNN];
-  __shared__ T sD[NN];  // D, read with wave-uniform addresses by the z-contractions
+  __shared__ T sD[NN];
   const int t = threadIdx.x;
   const int le = t / NN;
   const int ij = t - le * NN;
   const int i = ij % N, j = ij / N;
-  if (t < NN) sD[t] = Dm[t];
   const uint32_t e = blockIdx.x * EPB + le;
   const bool valid = e < (uint32_t)g.E;
   const uint32_t ee = valid ? e : 0u;
@@ -133,11 +147,21 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   T* A = sA + le * NNN;
   T* B = sB + le * NNN;
 
-  // all N loads are issued before any is used: the addresses are in bounds for every thread
-  // (an out-of-range element reads element 0), and masked values are replaced afterwards
+  // Every global load of the first phase is issued before any is consumed (all addresses are
+  // in bounds: an out-of-range element reads element 0, thread t reads D[t mod n^2]): the x
+  // column, the first PF planes of geometric factors (PF bounded by a register budget) and D.
+  constexpr int PF = (N * 6 * (int)sizeof(T) / 4 <= 112) ? N : (N <= 12 ? 4 : 2);
   T xr[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
+  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
+  T gp[PF][6];
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
+  const T dval = Dm[ij];
+  if (le == 0) sD[ij] = dval;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     const int gz = ez * P + k;
@@ -145,22 +169,13 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     if (!valid || (bnd && !neumann)) xr[k] = T(0);
     A[k * NN + ij] = xr[k];
   }
+  __syncthreads();
   T Di[N], Dj[N];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    Di[l] = Dm[i * N + l];
-    Dj[l] = Dm[j * N + l];
+    Di[l] = sD[i * N + l];
+    Dj[l] = sD[j * N + l];
   }
-  // the first PF planes of geometric factors are loaded before the barrier, so their latency
-  // overlaps the gather of x; PF is bounded by a register budget
-  constexpr int PF = (N * 6 * (int)sizeof(T) / 4 <= 112) ? N : (N <= 12 ? 4 : 2);
-  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
-  T gp[PF][6];
-#pragma unroll
-  for (int k = 0; k < PF; ++k)
-#pragma unroll
-    for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
-  __syncthreads();
 
   T wx[N], wy[N], wz[N];
 #pragma unroll
@@ -198,14 +213,14 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     A[k * NN + ij] = wx[k];
     B[k * NN + ij] = wy[k];
   }
+  __syncthreads();
+  if (!valid) return;
   T DiT[N], DjT[N];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
-    DiT[l] = Dm[l * N + i];
-    DjT[l] = Dm[l * N + j];
+    DiT[l] = sD[l * N + i];
+    DjT[l] = sD[l * N + j];
   }
-  __syncthreads();
-  if (!valid) return;
   T* Fe = F + (int64_t)e * NNN + ij;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -294,65 +309,69 @@ __device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
 }
 
 // acc = sum over the elements containing node g of F[e][local index of g], then the epilogue;
-// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann. One workgroup of
-// kGX threads covers kGX consecutive nodes of one grid row (fixed y, z), so the row's
-// element candidates along y and z are uniform across the workgroup.
+// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann. Each wave walks one
+// grid row (fixed y, z) in chunks of 64 nodes, a workgroup holds kGR rows, so the row's
+// element candidates along y and z are uniform across the wave.
 constexpr int kGX = 64;
+constexpr int kGR = 4;
 
 template <int N, int DIM, typename T>
-__global__ void __launch_bounds__(kGX)
-k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep) {
+__global__ void __launch_bounds__(kGX * kGR)
+k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int nrows, int neumann,
+         EpiT<T> ep) {
   constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
-  const int nch = (g.nn[0] + kGX - 1) / kGX;  // workgroups per row (uniform)
-  const int row = (int)(blockIdx.x / (unsigned)nch);
-  const int gx = (int)(blockIdx.x - (unsigned)row * nch) * kGX + threadIdx.x;
-  if (gx >= g.nn[0]) return;
+  const int row = (int)blockIdx.x * kGR + (int)threadIdx.y;
+  if (row >= nrows) return;
   const int gy = DIM == 3 ? row % g.nn[1] : row;
   const int gz = DIM == 3 ? row / g.nn[1] : 0;
-  const int64_t t = gx + (int64_t)g.nn[0] * row;
-  bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
-  if (DIM == 3) bnd = bnd || gz == 0 || gz == g.nn[2] - 1;
-  if (bnd && !neumann) {
-    epilogue_zero(ep, t);
-    return;
-  }
-  int cex[2], clx[2], cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
-  const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+  const bool bnd_yz = gy == 0 || gy == g.nn[1] - 1 || (DIM == 3 && (gz == 0 || gz == g.nn[2] - 1));
+  int cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
   const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
   const int cz = DIM == 3 ? axis_cands(gz, P, g.ne[2], cez, clz) : 1;
-  // up to 8 loads, all issued before the sum: missing candidates re-read candidate 0 and
-  // contribute +0 (the sum order is z, y, x with the lower element first)
-  T v[2][2][2];
+  const int64_t rbase = (int64_t)g.nn[0] * row;
+  for (int gx = threadIdx.x; gx < g.nn[0]; gx += kGX) {
+    const int64_t t = rbase + gx;
+    if ((bnd_yz || gx == 0 || gx == g.nn[0] - 1) && !neumann) {
+      epilogue_zero(ep, t);
+      continue;
+    }
+    int cex[2], clx[2];
+    const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+    // up to 8 loads, all issued before the sum: missing candidates re-read candidate 0 and
+    // are skipped in the sum (the sum order is z, y, x with the lower element first)
+    T v[2][2][2];
 #pragma unroll
-  for (int kz = 0; kz < 2; ++kz)
+    for (int kz = 0; kz < 2; ++kz)
 #pragma unroll
-    for (int ky = 0; ky < 2; ++ky)
+      for (int ky = 0; ky < 2; ++ky)
 #pragma unroll
-      for (int kx = 0; kx < 2; ++kx) {
-        const int az = kz < cz ? kz : 0, ay = ky < cy ? ky : 0, ax = kx < cx ? kx : 0;
-        const int64_t e = cex[ax] + (int64_t)g.ne[0] * (cey[ay] + (int64_t)g.ne[1] * cez[az]);
-        v[kz][ky][kx] = F[e * NL + clx[ax] + N * (cly[ay] + N * clz[az])];
-      }
-  T acc = T(0);
+        for (int kx = 0; kx < 2; ++kx) {
+          const int az = kz < cz ? kz : 0, ay = ky < cy ? ky : 0, ax = kx < cx ? kx : 0;
+          const int64_t e = cex[ax] + (int64_t)g.ne[0] * (cey[ay] + (int64_t)g.ne[1] * cez[az]);
+          v[kz][ky][kx] = F[e * NL + clx[ax] + N * (cly[ay] + N * clz[az])];
+        }
+    T acc = T(0);
 #pragma unroll
-  for (int kz = 0; kz < 2; ++kz)
+    for (int kz = 0; kz < 2; ++kz)
 #pragma unroll
-    for (int ky = 0; ky < 2; ++ky)
+      for (int ky = 0; ky < 2; ++ky)
 #pragma unroll
-      for (int kx = 0; kx < 2; ++kx)
-        if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
-  const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
-  epilogue(ep, t, acc, xv);
+        for (int kx = 0; kx < 2; ++kx)
+          if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
+    const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
+    epilogue(ep, t, acc, xv);
+  }
 }
 
 template <int N, typename T>
 void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
                    hipStream_t s) {
-  const dim3 grid((unsigned)(((g.nn[0] + kGX - 1) / kGX) * (g.N / g.nn[0])));
+  const int nrows = (int)(g.N / g.nn[0]);
+  const dim3 grid((unsigned)((nrows + kGR - 1) / kGR)), block(kGX, kGR);
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, dim3(kGX), 0, s, F, xin, g, neumann, ep);
+    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, block, 0, s, F, xin, g, nrows, neumann, ep);
   else
-    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, dim3(kGX), 0, s, F, xin, g, neumann, ep);
+    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, block, 0, s, F, xin, g, nrows, neumann, ep);
   GLLMG_HIP(hipGetLastError());
 }
 

@@ -541,6 +541,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
       Epi ep;  // with t = A d: x += d; r = rin - t; d = rn rho d + (2 rn / delta) dinv r
       ep.mode = EPI_CHEB;
       ep.from_zero = first_zero ? 1 : 0;
+      ep.last = i == k - 1 ? 1 : 0;  // ... and then x += d, the polynomial's final update
       ep.x = x;
       ep.rin = rin;
       ep.r = r;
@@ -551,7 +552,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
       apply_epi(P, l, pr, 0, d, ep, s);
       rin = r;
       rho = rn;
-    } else {
+    } else if (k == 1) {  // a degree-1 polynomial has no product to fuse the update into
       if (first_zero)
         vec_copy(pr, N, d, x, s);
       else
@@ -711,10 +712,26 @@ void solve_begin(gllmg_problem* P, int mode, const double* b, double* x, double 
   v.phase = PH_INIT;
 }
 
-// Advance without blocking; returns true when the solve has finished.
+bool solve_poll_impl(gllmg_problem* P);
+
+// Advance without blocking; returns true when the solve has finished. A failure while
+// advancing ends the solve: the stream is drained (so b, x and the internal vectors are no
+// longer in use) and the problem accepts a new solve.
 bool solve_poll(gllmg_problem* P) {
   auto& v = P->sv;
   GLLMG_CHECK(v.active, GLLMG_EINVAL, "no solve in progress");
+  try {
+    return solve_poll_impl(P);
+  } catch (...) {
+    (void)hipStreamSynchronize(v.s);
+    (void)hipGetLastError();
+    v.active = false;
+    throw;
+  }
+}
+
+bool solve_poll_impl(gllmg_problem* P) {
+  auto& v = P->sv;
   while (!v.done) {
     const hipError_t q = hipEventQuery(v.ev);
     if (q == hipErrorNotReady) return false;
@@ -1111,6 +1128,8 @@ gllmg_status gllmg_solve(const gllmg_problem* P, int32_t mode, const double* b, 
     check_ptr(b, 8, "b");
     check_ptr(x, 8, "x");
     GLLMG_CHECK(rtol > 0.0 && maxit >= 1, GLLMG_EINVAL, "rtol must be > 0 and maxit >= 1");
+    GLLMG_CHECK(P->L.back().Ainv64 != nullptr, GLLMG_EUNSUPPORTED,
+                "the coarsest level is too large for the dense exact solve");
     gllmg_status r = solve_impl(const_cast<gllmg_problem*>(P), mode, b, x, rtol, maxit, st,
                                 (hipStream_t)stream);
     if (r == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached";
@@ -1166,9 +1185,15 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       if (status) status[i] = st;
       if (worst == GLLMG_OK || worst == GLLMG_ENOTCONV) worst = st;
     };
+    {
+      std::vector<const gllmg_problem*> seen(probs, probs + count);
+      for (auto* P : seen) GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+      std::sort(seen.begin(), seen.end());
+      GLLMG_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), GLLMG_EINVAL,
+                  "a problem appears twice in the batch");
+    }
     for (int i = 0; i < count; ++i) {
       gllmg_problem* P = probs[i];
-      GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
       if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
       GLLMG_HIP(hipStreamWaitEvent(P->xs, start, 0));
       const gllmg_status st = gllmg_solve_begin(P, mode, b[i], x[i], rtol, maxit, P->xs);
@@ -1186,7 +1211,19 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       bool progressed = false;
       for (int i : live) {
         if (fin[i]) continue;
-        if (solve_poll(probs[i])) {
+        bool finished = false;
+        try {
+          finished = solve_poll(probs[i]);
+        } catch (const Error& e) {
+          // this problem's solve has ended with the error; the others go on
+          fin[i] = 1;
+          --left;
+          progressed = true;
+          g_err = e.what();
+          fail(i, e.status);
+          continue;
+        }
+        if (finished) {
           fin[i] = 1;
           --left;
           progressed = true;

@@ -97,20 +97,37 @@ RefElem ref_element(int p) {
     }
     if (p % 2 == 0) re.xi[p / 2] = 0.0;
   }
-  std::vector<double> Pv(n);
   re.w.resize(n);
   for (int i = 0; i < n; ++i) {
     double P, Pm1;
     legendre_pp(p, re.xi[i], &P, &Pm1);
-    Pv[i] = P;
     re.w[i] = 2.0 / (p * (p + 1.0) * P * P);
   }
+  // Barycentric weights of the computed (rounded) nodes, lam_j = 1 / prod_{k != j}(xi_j - xi_k).
+  // The derivative matrix is built from them rather than from the Legendre closed form
+  // P_p(xi_i) / (P_p(xi_j)(xi_i - xi_j)), which presumes exact nodes: with nodes off by an ulp
+  // it no longer differentiates linear functions exactly (at p = 16, D xi - 1 reaches 3e-13),
+  // and the isoparametric Jacobian D x amplifies that by |x| / |J|, i.e. by the element count.
+  re.lam.resize(n);
+  for (int j = 0; j < n; ++j) {
+    double prod = 1.0;
+    for (int k = 0; k < n; ++k)
+      if (k != j) prod *= (re.xi[j] - re.xi[k]);
+    re.lam[j] = 1.0 / prod;
+  }
+  // D_ij = (lam_j / lam_i) / (xi_i - xi_j) off the diagonal; each diagonal entry is minus the
+  // sum of its row's others, so that D annihilates constants to rounding (Baltensperger and
+  // Trummer, SIAM J. Sci. Comput. 2003).
   re.D.assign(n * n, 0.0);
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
+    double rs = 0.0;
     for (int j = 0; j < n; ++j)
-      if (i != j) re.D[i * n + j] = Pv[i] / (Pv[j] * (re.xi[i] - re.xi[j]));
-  re.D[0] = -p * (p + 1.0) / 4.0;
-  re.D[n * n - 1] = p * (p + 1.0) / 4.0;
+      if (i != j) {
+        re.D[i * n + j] = (re.lam[j] / re.lam[i]) / (re.xi[i] - re.xi[j]);
+        rs += re.D[i * n + j];
+      }
+    re.D[i * n + i] = -rs;
+  }
   return re;
 }
 
@@ -122,13 +139,7 @@ void lagrange_at(const RefElem& re, double y, double* out) {
       for (int k = 0; k < n; ++k) out[k] = (k == j) ? 1.0 : 0.0;
       return;
     }
-  std::vector<double> lam(n);
-  for (int j = 0; j < n; ++j) {
-    double prod = 1.0;
-    for (int k = 0; k < n; ++k)
-      if (k != j) prod *= (re.xi[j] - re.xi[k]);
-    lam[j] = 1.0 / prod;
-  }
+  const std::vector<double>& lam = re.lam;
   double den = 0.0;
   for (int j = 0; j < n; ++j) den += lam[j] / (y - re.xi[j]);
   for (int j = 0; j < n; ++j) out[j] = (lam[j] / (y - re.xi[j])) / den;

@@ -83,7 +83,7 @@ class Record:
 
 class Server:
     def __init__(self, hbm_budget: int, max_active: int = 64, nstreams: int = 8,
-                 keep_solutions: bool = False):
+                 keep_solutions: bool = False, setup_threads: int = 3):
         import torch
         self.ledger = HbmLedger(hbm_budget)
         self.max_active = max_active
@@ -93,8 +93,10 @@ class Server:
         self.records: Dict[int, Record] = {}
         self._ready: "queue.Queue" = queue.Queue()
         self._todo: "queue.Queue" = queue.Queue()
-        self._setup_thread = threading.Thread(target=self._setup_worker, daemon=True)
-        self._setup_thread.start()
+        self._setup_threads = [threading.Thread(target=self._setup_worker, daemon=True)
+                               for _ in range(setup_threads)]
+        for t in self._setup_threads:
+            t.start()
         self._t0 = 0.0
 
     def now(self) -> float:
@@ -206,8 +208,10 @@ class Server:
         return self.report()
 
     def close(self):
-        self._todo.put(None)
-        self._setup_thread.join(timeout=60)
+        for _ in self._setup_threads:
+            self._todo.put(None)
+        for t in self._setup_threads:
+            t.join(timeout=60)
 
     def report(self) -> dict:
         done = [r for r in self.records.values() if r.converged and np.isfinite(r.finished)]

@@ -1,0 +1,70 @@
+"""Write the full-size expected values in tests/golden/ from the CPU oracle only.
+
+python tests/golden/make_golden.py [config2|config3|all]
+
+For the 3D warped variable-coefficient problem at its two full sizes (16^3 hexes at p = 8 and
+8^3 hexes at p = 16, 2,146,689 nodes each), the oracle's FP64 p-multigrid PCG (Chebyshev
+degree 4, rtol 1e-10) gives: lambda_max per level, the iteration count, the residual history,
+the solution at seeded sample nodes and its norm; plus y = A x for a seeded x at sample nodes,
+with the rounding scale |B|^T|G||B||x| at the same nodes.
+Inputs come from paper_1402_5938_amd.inputs (seeded, no arithmetic of the method); nothing
+here calls the GPU library.
+"""
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import fem, mg  # noqa: E402
+from paper_1402_5938_amd import inputs  # noqa: E402
+
+NSAMPLE = 2048
+
+
+def sample_nodes(N, seed=1234):
+    return np.sort(np.random.default_rng(seed).choice(N, size=NSAMPLE, replace=False))
+
+
+def run(name, prob):
+    t0 = time.time()
+    H, b = mg.build_problem(prob)
+    t_setup = time.time() - t0
+    m = H.fine.mesh
+    idx = sample_nodes(m.N)
+    xs = inputs.uniform_nodal(99, m.N)
+    y = H.fine.op.apply(xs)
+    ya = H.fine.op.apply_abs(xs)
+    t1 = time.time()
+    res = mg.pcg(H, b, rtol=prob.rtol, maxit=prob.maxit)
+    t_solve = time.time() - t1
+    out = {
+        "problem": prob.name, "nnodes": int(m.N), "levels": [[list(lv.mesh.nelem), lv.mesh.p] for lv in H.levels],
+        "lmax": [lv.lmax for lv in H.levels[:-1]], "iters": res.iters, "converged": bool(res.converged),
+        "history": res.history, "relres_true": res.relres_true,
+        "sample_nodes": idx.tolist(), "x_sample": res.x[idx].tolist(),
+        "x_norm2": float(np.linalg.norm(res.x)), "b_norm2": float(np.linalg.norm(b)),
+        "apply_input_seed": 99, "apply_sample": y[idx].tolist(), "apply_norm2": float(np.linalg.norm(y)),
+        "apply_abs_sample": ya[idx].tolist(), "apply_abs_norm2": float(np.linalg.norm(ya)),
+        "oracle_setup_s": t_setup, "oracle_solve_s": t_solve,
+    }
+    with open(os.path.join(HERE, f"{name}.json"), "w") as f:
+        json.dump(out, f)
+    print(name, "iters", res.iters, "setup", round(t_setup, 1), "s solve", round(t_solve, 1), "s", flush=True)
+
+
+def main():
+    which = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if which in ("config2", "all"):
+        run("warped_16cubed_p8", inputs.warped_var3d(nelem=16, order=8))
+    if which in ("config3", "all"):
+        run("warped_8cubed_p16", inputs.warped_var3d(nelem=8, order=16, f_seed=0))
+
+
+if __name__ == "__main__":
+    main()

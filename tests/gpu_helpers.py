@@ -33,11 +33,18 @@ def rel2(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def fp64_close(a, b, tol=1e-12, tol_max=5e-12):
-    """The FP64 parity bar: 2-norm relative error <= 1e-12, and max-norm error relative to the
-    largest entry <= 5e-12 (rounding of the O(p) sums with |D| up to p(p+1)/4 grows with p)."""
-    e2, em = rel2(a, b), rel_err(a, b)
-    return e2 <= tol and em <= tol_max, (e2, em)
+def fp64_close(a, b, scale=None, tol=1e-12, tol_scale=1e-14):
+    """The FP64 parity bar: ||a - b||_2 <= 1e-12 ||b||_2 + 1e-14 ||scale||_2, where `scale` is the
+    oracle's |B|^T|G||B||x| (the magnitude of the terms whose rounding the two evaluation orders
+    differ by); without a scale, 1e-12 relative in the 2-norm and 5e-12 in the max-norm."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    d2 = np.linalg.norm(a - b)
+    if scale is None:
+        e2, em = rel2(a, b), rel_err(a, b)
+        return e2 <= tol and em <= 5 * tol, (e2, em)
+    bound = tol * np.linalg.norm(b) + tol_scale * np.linalg.norm(scale)
+    return d2 <= bound, (d2, bound)
 
 
 def build_pair(dim, nelem, p, map_desc=None, mu_desc=None, hierarchy="p", smoother="chebyshev",

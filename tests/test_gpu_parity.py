@@ -1,8 +1,9 @@
 """GPU (HIP, through the C ABI) versus the CPU FP64 oracle, element by element, on seeded
 inputs that span several elements per axis, ragged (non-cubic) element counts and all orders
-1..16. Tolerances: FP64 operator, diagonal, transfers, smoothing <= 1e-12 relative in the
-2-norm (and <= 5e-12 in the max-norm relative to the largest entry); V-cycle <= 1e-10;
-FP32 paths <= 2e-5 relative; iteration counts equal."""
+1..16. Tolerances: FP64 products ||dy||_2 <= 1e-12 ||y||_2 + 1e-14 || |B|^T|G||B||x| ||_2 (the
+second term is the scale of the rounding of the O(p)-term sums, which dominates for rough x at
+high p); diagonal, transfers, smoothing <= 1e-12 relative in the 2-norm and 5e-12 in the
+max-norm; V-cycle <= 1e-10; FP32 paths <= 2e-5 relative; iteration counts equal."""
 
 import numpy as np
 import pytest
@@ -30,10 +31,10 @@ def test_apply_diag_coords_fp64(dim, ne, p):
     np.testing.assert_allclose(to_np(G.node_coords(0)), m.x, rtol=0, atol=1e-14)
     x = random_vec(m.N, 11)
     y = to_np(G.apply(to_dev(x)))
-    ok, e = fp64_close(y, lv.op.apply(x))
+    ok, e = fp64_close(y, lv.op.apply(x), lv.op.apply_abs(x))
     assert ok, e
     yn = to_np(G.apply(to_dev(x), neumann=True))
-    ok, e = fp64_close(yn, lv.op.apply(x, neumann=True))
+    ok, e = fp64_close(yn, lv.op.apply(x, neumann=True), lv.op.apply_abs(x, neumann=True))
     assert ok, e
     d = to_np(G.diag(0))
     ok, e = fp64_close(d, lv.op.diag())

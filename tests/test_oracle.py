@@ -167,6 +167,21 @@ def test_stiffness_symmetric_nullspace_spd(dim, ne, p):
     np.testing.assert_allclose(K.diagonal(), np.diag(A), rtol=1e-13)
 
 
+def test_abs_product_bounds_product():
+    """|B|^T|G||B||x| >= |A x| entrywise, with equality for x >= 0 on a mesh where every
+    factor is nonnegative (unit box, mu = 1, p = 1: D has one negative column, so compare
+    with the dense absolute-value product instead)."""
+    m = _mesh(3, 2, 4)
+    op = fem.LevelOperator(m)
+    x = np.random.default_rng(3).standard_normal(m.N)
+    ya, y = op.apply_abs(x, neumann=True), op.apply(x, neumann=True)
+    assert np.all(ya >= np.abs(y) - 1e-12 * ya.max())
+    K = fem.Stiffness(m)
+    dense = sum(abs(K.B[a]).T.toarray() @ np.diag(np.abs(K.G[:, a, b])) @ abs(K.B[b]).toarray()
+                for a in range(3) for b in range(3))
+    np.testing.assert_allclose(ya, dense @ np.abs(x), rtol=1e-12)
+
+
 @pytest.mark.parametrize("dim,ne,p", [(2, 3, 3), (3, 2, 3)])
 def test_energy_of_linear_functions(dim, ne, p):
     """grad u = a exactly for u = a.x + c (linear functions lie in the isoparametric space),

@@ -12,6 +12,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 """
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,6 +22,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per operator product read by the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
+# plain copy kernel), with the hash of the apply kernels' source they were taken on
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_warped_16cubed_p8_hbm_traffic.txt")
+APPLY_SOURCE = os.path.join(ROOT, "paper_1402_5938_amd", "csrc", "k_apply.hip")
+CALIB_COPY_BYTES = 256 * 2 ** 20
+
+
+def measured_traffic(nelem, order):
+    """HBM bytes per product from the committed counter runs, or None when they were taken on
+    another problem size or the apply kernels' source has changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.lstrip().startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(APPLY_SOURCE, "rb").read()).hexdigest()
+    if kv.get("k_apply_sha256") != sha or kv.get("problem") != f"{nelem}^3 hexes p={order}":
+        return None
+    try:
+        return float(kv["hbm_bytes_per_apply"])
+    except (KeyError, ValueError):
+        return None
 
 
 def apply_bytes(dim, ne, p, N, s):
@@ -165,9 +190,43 @@ def workload_serve(a):
                         f"budget {a.hbm_gb} GiB", **rep}
 
 
+def workload_apply(a):
+    """Operator products alone on the benchmark problem, for counter runs: 5 untimed products,
+    a.apply_reps products timed with HIP events on the launch stream, then 3 plain device
+    copies of 256 MiB (the calibration kernel for the HBM byte counters)."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
+    G = gllmg.Problem.from_inputs(prob)
+    N = G.nnodes(0)
+    xr = torch.from_numpy(inputs.uniform_nodal(99, N)).cuda()
+    y = torch.empty_like(xr)
+    for _ in range(5):
+        G.apply(xr, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(a.apply_reps):
+        G.apply(xr, y)
+    e1.record()
+    torch.cuda.synchronize()
+    t_apply = e0.elapsed_time(e1) / a.apply_reps * 1e-3
+    src = torch.ones(CALIB_COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    nbytes = apply_bytes(3, prob.nelem, prob.order, N, 8)
+    G.close()
+    return {"workload": f"apply: 3D warped var {a.nelem}^3 hexes p={a.order}, N={N}, "
+                        f"{a.apply_reps} timed products, then 3 copies of {CALIB_COPY_BYTES} bytes",
+            "apply_us": t_apply * 1e6, "algorithmic_bytes": nbytes,
+            "achieved_gbs": nbytes / t_apply / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
@@ -190,7 +249,8 @@ def main():
 
     torch.cuda.set_device(0)
     if a.workload != "config2":
-        fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve}[a.workload]
+        fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
+              "apply": workload_apply}[a.workload]
         print(json.dumps(fn(a)))
         return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
@@ -220,7 +280,7 @@ def main():
     assert r.converged and r.relres_true < 1e-9, r
 
     # operator product on the finest level, HIP events on the launch stream
-    xr = torch.randn(N, dtype=torch.float64, device="cuda")
+    xr = torch.from_numpy(inputs.uniform_nodal(99, N)).cuda()
     y = torch.empty_like(xr)
     for _ in range(5):
         G.apply(xr, y)
@@ -254,7 +314,8 @@ def main():
                    "solves_per_s": 1e3 / ms, "setup_s": t_setup,
                    "apply_gdof_s": N / t_apply / 1e9, "apply_us": t_apply * 1e6},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(a.nelem, a.order),
                      "kernel": "operator apply (element kernel + face-sum kernel), finest level",
                      "algorithmic_bytes": nbytes, "flops": apply_flops(3, prob.nelem, prob.order)},
     }

@@ -48,18 +48,13 @@ struct Grid {
   int64_t N;         // nodes
 };
 
-// 1D transfer table of one axis between a fine and a coarse level.
-//  prolong:  out[J] = sum_{m < nw} pw[J*nw + m] * in[pstart[J] + m]
-//  restrict: out[I] = sum_{t in [rptr[I], rptr[I+1])} rw[t] * in[ridx[t]]
-struct Transfer1D {
-  int nf, nc, nw;
-  int* pstart;       // device
-  double* pw64;
-  float* pw32;
-  int* rptr;
-  int* ridx;
-  double* rw64;
-  float* rw32;
+// Transfer from a level to the next coarser one: the 1D matrix Pl[child][i][c] (child < nch;
+// nch = 1 under p-coarsening, 2 under h-coarsening) evaluating coarse element basis function c
+// at fine element node i, the same for every element and axis of the uniform mesh.
+struct Xfer {
+  int nch = 1;
+  double* P64 = nullptr;  // device, nch * n_fine * n_coarse
+  float* P32 = nullptr;
 };
 
 struct Level {
@@ -85,7 +80,7 @@ struct Level {
   void* vt[2] = {nullptr, nullptr};
   // transfer to the next coarser level (if any)
   bool has_coarse = false;
-  Transfer1D tr[3];
+  Xfer tp;  // to the next coarser level
   // exact solve (coarsest level): dense inverse of the interior block
   double* Ainv64 = nullptr;
   float* Ainv32 = nullptr;
@@ -142,8 +137,19 @@ void launch_dinv(const Grid& g, const double* diag, double* dinv64, float* dinv3
 //  CHEB_START: r = b - A x, d = dinv r / c1                    (c1 = theta)
 //  CHEB:     with t = A d: x = x + d (or x = d), r = rin - t,
 //            d = c1 d + (c2 dinv) r                             (in place; the input is d)
+// and, for sums that are not products (the restriction's gather, s = the summed value):
+//  STORE_CHEB0:   y = s, d = dinv s / c1      (first Chebyshev step from x = 0, c1 = theta)
+//  STORE_JACOBI0: y = s, x = (om dinv) s      (first Jacobi step from x = 0)
 // At Dirichlet boundary nodes every output is 0.
-enum EpiMode { EPI_STORE = 0, EPI_RESIDUAL = 1, EPI_JACOBI = 2, EPI_CHEB = 3, EPI_CHEB_START = 4 };
+enum EpiMode {
+  EPI_STORE = 0,
+  EPI_RESIDUAL = 1,
+  EPI_JACOBI = 2,
+  EPI_CHEB = 3,
+  EPI_CHEB_START = 4,
+  EPI_STORE_CHEB0 = 5,
+  EPI_STORE_JACOBI0 = 6
+};
 struct Epi {
   int mode = EPI_STORE;
   int from_zero = 0;
@@ -161,11 +167,17 @@ void launch_apply(const Level& L, int prec, int neumann, const void* x, const Ep
                   hipStream_t s);
 size_t face_buffer_elems(const Level& L);
 
+// Node-order sum of element vectors R (layout [e][k][j][i] on level L) followed by the epilogue.
+void launch_gather_epi(const Level& L, int prec, const void* R, const Epi& ep, hipStream_t s);
+
+// xf = P xc (or xf += P xc)
 void launch_prolong(const Level& fine, const Level& coarse, int prec, const void* xc, void* xf,
-                    bool add, void* t1, void* t2, hipStream_t s);
-void launch_restrict(const Level& fine, const Level& coarse, int prec, const void* rf, void* rc,
-                     void* t1, void* t2, hipStream_t s);
-size_t transfer_temp_elems(const Level& fine, const Level& coarse);
+                    bool add, hipStream_t s);
+// P^T rf summed into the coarse level's epilogue ep (EPI_STORE: ep.y = P^T rf); R is a buffer
+// of restrict_buffer_elems elements of the precision
+void launch_restrict(const Level& fine, const Level& coarse, int prec, const void* rf,
+                     const Epi& ep, void* R, hipStream_t s);
+size_t restrict_buffer_elems(const Level& fine, const Level& coarse);
 
 void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s);
 

@@ -60,6 +60,14 @@ __device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
       ep.d[g] = ep.dinv[g] * ri / ep.c1;
       break;
     }
+    case EPI_STORE_CHEB0:
+      ep.y[g] = acc;
+      ep.d[g] = ep.dinv[g] * acc / ep.c1;
+      break;
+    case EPI_STORE_JACOBI0:
+      ep.y[g] = acc;
+      ep.x[g] = (ep.om * ep.dinv[g]) * acc;
+      break;
     default: {  // EPI_CHEB, input vector is d
       const T xo = ep.from_zero ? xin : ep.x[g] + xin;
       const T ri = ep.rin[g] - acc;
@@ -91,6 +99,14 @@ __device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
     case EPI_CHEB_START:
       ep.r[g] = T(0);
       ep.d[g] = T(0);
+      break;
+    case EPI_STORE_CHEB0:
+      ep.y[g] = T(0);
+      ep.d[g] = T(0);
+      break;
+    case EPI_STORE_JACOBI0:
+      ep.y[g] = T(0);
+      ep.x[g] = T(0);
       break;
     default:
       ep.x[g] = T(0);
@@ -393,8 +409,9 @@ void launch_gather_rt(const T* F, const T* xin, const Grid& g, int neumann, cons
 
 // ------------------------------------------------------------------ diagonal
 // diag_e(i) = sum_a sum_m D[m, i_a]^2 G_aa(i with a -> m) + sum_{a != b} D[i_a, i_a] D[i_b, i_b] G_ab(i)
-// (the cross terms survive only where both D diagonal entries are nonzero: the element's
-// boundary nodes). One thread per element point, written to the element-vector buffer; FP64.
+// (for the GLL points D has a zero diagonal, up to rounding, except at the two end points, so
+// the cross terms matter on element boundaries only). One thread per element point, written
+// to the element-vector buffer; FP64.
 __global__ void __launch_bounds__(256)
 k_diag(const double* __restrict__ G, const double* __restrict__ Dm, Grid g, double* __restrict__ F) {
   const int n = g.p + 1, dim = g.dim;
@@ -470,6 +487,13 @@ void launch_apply(const Level& L, int prec, int neumann, const void* x, const Ep
     apply_t<double>(L, neumann, x, ep, F, s);
   else
     apply_t<float>(L, neumann, x, ep, F, s);
+}
+
+void launch_gather_epi(const Level& L, int prec, const void* R, const Epi& ep, hipStream_t s) {
+  if (prec == 0)
+    launch_gather_rt<double>((const double*)R, nullptr, L.g, 0, typed<double>(ep), s);
+  else
+    launch_gather_rt<float>((const float*)R, nullptr, L.g, 0, typed<float>(ep), s);
 }
 
 void launch_diag(const Level& L, double* diag, double* F, hipStream_t s) {

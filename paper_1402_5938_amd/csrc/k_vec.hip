@@ -1,5 +1,5 @@
-// Streaming kernels: h/p transfers as separable 1D passes, the coarsest-level dense solve,
-// the fused smoother updates, deterministic dot products and the PCG vector updates.
+// Streaming kernels: the coarsest-level dense solve, the fused smoother updates, deterministic
+// dot products and the PCG vector updates.
 #include "internal.h"
 
 namespace gllmg {
@@ -8,106 +8,6 @@ namespace {
 
 constexpr int kT = 256;
 inline unsigned nb(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
-
-// ------------------------------------------------------------------ transfers
-// The prolongation P_ij = phi_j^{coarse}(p_i) (paper §2.2, Eq. (Pstencil)) of a tensorized
-// basis on a structured mesh is the Kronecker product of 1D matrices, so x_f = P x_c runs as
-// one 1D pass per axis; the restriction P^T runs the transposed 1D passes. Each pass reads
-// `in` (dims = out dims except along `axis`, where it has `ilen` entries).
-template <typename T>
-__global__ void __launch_bounds__(kT)
-k_tpass(const T* __restrict__ in, T* __restrict__ out, int dim, int axis, int o0, int o1, int o2,
-        int ilen, int restrict_mode, const int* __restrict__ pstart, const T* __restrict__ pw,
-        int nw, const int* __restrict__ rptr, const int* __restrict__ ridx,
-        const T* __restrict__ rw, int in_mask, int out_mask, int add) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t tot = (int64_t)o0 * o1 * o2;
-  if (t >= tot) return;
-  int c[3];
-  c[0] = (int)(t % o0);
-  c[1] = (int)((t / o0) % o1);
-  c[2] = (int)(t / ((int64_t)o0 * o1));
-  int idims[3] = {o0, o1, o2};
-  idims[axis] = ilen;
-  // input offset of the line through c along `axis`, and its stride
-  int cc[3] = {c[0], c[1], c[2]};
-  cc[axis] = 0;
-  const int64_t base = cc[0] + (int64_t)idims[0] * (cc[1] + (int64_t)idims[1] * cc[2]);
-  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)idims[0] : (int64_t)idims[0] * idims[1]);
-  bool other_bnd = false;  // input boundary in the other axes (same coordinates as the output)
-  for (int a = 0; a < dim; ++a)
-    if (a != axis) other_bnd = other_bnd || c[a] == 0 || c[a] == idims[a] - 1;
-  const int J = c[axis];
-  T acc = T(0);
-  if (!(in_mask && other_bnd)) {
-    if (!restrict_mode) {
-      const int s0 = pstart[J];
-      for (int m = 0; m < nw; ++m) {
-        const int I = s0 + m;
-        if (in_mask && (I == 0 || I == ilen - 1)) continue;
-        acc += pw[J * nw + m] * in[base + stride * I];
-      }
-    } else {
-      for (int q = rptr[J]; q < rptr[J + 1]; ++q) {
-        const int I = ridx[q];
-        if (in_mask && (I == 0 || I == ilen - 1)) continue;
-        acc += rw[q] * in[base + stride * I];
-      }
-    }
-  }
-  if (out_mask) {
-    bool ob = false;
-    for (int a = 0; a < dim; ++a) {
-      const int od = a == 0 ? o0 : (a == 1 ? o1 : o2);
-      ob = ob || c[a] == 0 || c[a] == od - 1;
-    }
-    if (ob) acc = T(0);
-  }
-  out[t] = add ? out[t] + acc : acc;
-}
-
-template <typename T>
-void tpass(const Transfer1D& tb, int prec, const void* in, void* out, int dim, int axis,
-           int o0, int o1, int o2, int ilen, int restrict_mode, int in_mask, int out_mask, int add,
-           hipStream_t s) {
-  const T* pw = prec == 0 ? (const T*)tb.pw64 : (const T*)tb.pw32;
-  const T* rw = prec == 0 ? (const T*)tb.rw64 : (const T*)tb.rw32;
-  const int64_t tot = (int64_t)o0 * o1 * o2;
-  hipLaunchKernelGGL(k_tpass<T>, dim3(nb(tot)), dim3(kT), 0, s, (const T*)in, (T*)out, dim, axis,
-                     o0, o1, o2, ilen, restrict_mode, tb.pstart, pw, tb.nw, tb.rptr, tb.ridx, rw,
-                     in_mask, out_mask, add);
-  GLLMG_HIP(hipGetLastError());
-}
-
-template <typename T>
-void prolong_t(const Level& F, const Level& C, int prec, const void* xc, void* xf, bool add,
-               void* t1, void* t2, hipStream_t s) {
-  const int* nf = F.g.nn;
-  const int* nc = C.g.nn;
-  if (F.g.dim == 2) {
-    tpass<T>(F.tr[0], prec, xc, t1, 2, 0, nf[0], nc[1], 1, nc[0], 0, 1, 0, 0, s);
-    tpass<T>(F.tr[1], prec, t1, xf, 2, 1, nf[0], nf[1], 1, nc[1], 0, 0, 1, add ? 1 : 0, s);
-  } else {
-    tpass<T>(F.tr[0], prec, xc, t1, 3, 0, nf[0], nc[1], nc[2], nc[0], 0, 1, 0, 0, s);
-    tpass<T>(F.tr[1], prec, t1, t2, 3, 1, nf[0], nf[1], nc[2], nc[1], 0, 0, 0, 0, s);
-    tpass<T>(F.tr[2], prec, t2, xf, 3, 2, nf[0], nf[1], nf[2], nc[2], 0, 0, 1, add ? 1 : 0, s);
-  }
-}
-
-template <typename T>
-void restrict_t(const Level& F, const Level& C, int prec, const void* rf, void* rc, void* t1,
-                void* t2, hipStream_t s) {
-  const int* nf = F.g.nn;
-  const int* nc = C.g.nn;
-  if (F.g.dim == 2) {
-    tpass<T>(F.tr[0], prec, rf, t1, 2, 0, nc[0], nf[1], 1, nf[0], 1, 1, 0, 0, s);
-    tpass<T>(F.tr[1], prec, t1, rc, 2, 1, nc[0], nc[1], 1, nf[1], 1, 0, 1, 0, s);
-  } else {
-    tpass<T>(F.tr[0], prec, rf, t1, 3, 0, nc[0], nf[1], nf[2], nf[0], 1, 1, 0, 0, s);
-    tpass<T>(F.tr[1], prec, t1, t2, 3, 1, nc[0], nc[1], nf[2], nf[1], 1, 0, 0, 0, s);
-    tpass<T>(F.tr[2], prec, t2, rc, 3, 2, nc[0], nc[1], nc[2], nf[2], 1, 0, 1, 0, s);
-  }
-}
 
 // ------------------------------------------------------------------ coarsest level
 // x = A_II^{-1} b on the interior nodes (dense inverse, rows in lexicographic interior order),
@@ -287,37 +187,6 @@ __global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, doubl
 
 }  // namespace
 
-size_t transfer_temp_elems(const Level& F, const Level& C) {
-  const int* nf = F.g.nn;
-  const int* nc = C.g.nn;
-  size_t a, b;
-  if (F.g.dim == 2) {
-    a = (size_t)nf[0] * nc[1];
-    b = (size_t)nc[0] * nf[1];
-    return a > b ? a : b;
-  }
-  const size_t p1 = (size_t)nf[0] * nc[1] * nc[2], p2 = (size_t)nf[0] * nf[1] * nc[2];
-  const size_t r1 = (size_t)nc[0] * nf[1] * nf[2], r2 = (size_t)nc[0] * nc[1] * nf[2];
-  a = p1 > p2 ? p1 : p2;
-  b = r1 > r2 ? r1 : r2;
-  return a > b ? a : b;
-}
-
-void launch_prolong(const Level& F, const Level& C, int prec, const void* xc, void* xf, bool add,
-                    void* t1, void* t2, hipStream_t s) {
-  if (prec == 0)
-    prolong_t<double>(F, C, prec, xc, xf, add, t1, t2, s);
-  else
-    prolong_t<float>(F, C, prec, xc, xf, add, t1, t2, s);
-}
-
-void launch_restrict(const Level& F, const Level& C, int prec, const void* rf, void* rc, void* t1,
-                     void* t2, hipStream_t s) {
-  if (prec == 0)
-    restrict_t<double>(F, C, prec, rf, rc, t1, t2, s);
-  else
-    restrict_t<float>(F, C, prec, rf, rc, t1, t2, s);
-}
 
 void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s) {
   if (prec == 0)

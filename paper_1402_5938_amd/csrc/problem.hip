@@ -110,8 +110,6 @@ struct gllmg_problem {
   bool owns_ws = false;
   double* mass = nullptr;
   void* F = nullptr;
-  void* T1 = nullptr;
-  void* T2 = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
   int* flag = nullptr;
@@ -155,7 +153,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const gllmg_config& c = P->cfg;
   const bool f32 = c.vcycle_prec == GLLMG_F32;
   P->L.resize(specs.size());
-  size_t face = 0, ttmp = 0;
+  size_t face = 0;
   for (size_t l = 0; l < specs.size(); ++l) {
     Level& L = P->L[l];
     L.g = make_grid(c.dim, specs[l]);
@@ -184,26 +182,15 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   for (size_t l = 0; l + 1 < specs.size(); ++l) {
     Level& F = P->L[l];
     Level& C = P->L[l + 1];
-    ttmp = std::max(ttmp, transfer_temp_elems(F, C));
-    for (int a = 0; a < c.dim; ++a) {
-      Transfer1D& t = F.tr[a];
-      t.nf = F.g.nn[a];
-      t.nc = C.g.nn[a];
-      t.nw = C.n;
-      t.pstart = (int*)A.take(sizeof(int) * t.nf);
-      t.pw64 = (double*)A.take(sizeof(double) * t.nf * t.nw);
-      t.pw32 = (float*)A.take(sizeof(float) * t.nf * t.nw);
-      t.rptr = (int*)A.take(sizeof(int) * (t.nc + 1));
-      t.ridx = (int*)A.take(sizeof(int) * t.nf * t.nw);
-      t.rw64 = (double*)A.take(sizeof(double) * t.nf * t.nw);
-      t.rw32 = (float*)A.take(sizeof(float) * t.nf * t.nw);
-    }
+    face = std::max(face, restrict_buffer_elems(F, C));
+    F.tp.nch = F.g.p == C.g.p ? 2 : 1;
+    const size_t np = (size_t)F.tp.nch * F.n * C.n;
+    F.tp.P64 = (double*)A.take(sizeof(double) * np);
+    F.tp.P32 = (float*)A.take(sizeof(float) * np);
   }
   const int64_t N0 = P->L[0].g.N;
   P->mass = (double*)A.take(sizeof(double) * N0);
   P->F = A.take(sizeof(double) * std::max<size_t>(face, 1));
-  P->T1 = A.take(sizeof(double) * std::max<size_t>(ttmp, 1));
-  P->T2 = A.take(sizeof(double) * std::max<size_t>(ttmp, 1));
   P->scal = (double*)A.take(sizeof(double) * 64);
   P->part = (double*)A.take(sizeof(double) * kDotBlocks);
   P->flag = (int*)A.take(sizeof(int) * 4);
@@ -298,62 +285,26 @@ void residual(gllmg_problem* P, int l, int pr, const void* b, const void* x, voi
   apply_epi(P, l, pr, 0, x, ep, s);
 }
 
+// The 1D matrix of the transfer from level l to level l + 1 (paper §2.2): coarse basis
+// function c evaluated at fine node i of child `ch`, whose reference coordinate in the coarse
+// element is xi_i (p-coarsening: same element) or (xi_i + 2 ch - 1) / 2 (h-coarsening: the
+// fine element is half ch of the coarse one along the axis).
 void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
   Level& F = P->L[l];
   Level& C = P->L[l + 1];
   const RefElem& rf = P->re[l];
   const RefElem& rc = P->re[l + 1];
-  const bool ptype = F.g.p != C.g.p;
-  for (int a = 0; a < F.g.dim; ++a) {
-    Transfer1D& t = F.tr[a];
-    const int nef = F.g.ne[a], pf = F.g.p, pc = C.g.p, nw = t.nw;
-    std::vector<int> pstart(t.nf);
-    std::vector<double> pw((size_t)t.nf * nw);
-    for (int J = 0; J < t.nf; ++J) {
-      int ef = std::min(J / pf, nef - 1);
-      const int i = J - ef * pf;
-      int ec;
-      double xc;
-      if (ptype) {
-        ec = ef;
-        xc = rf.xi[i];
-      } else {
-        ec = ef / 2;
-        const int ch = ef % 2;
-        xc = (rf.xi[i] + 2.0 * ch - 1.0) / 2.0;
-      }
-      pstart[J] = ec * pc;
-      lagrange_at(rc, xc, &pw[(size_t)J * nw]);
+  const int nf = F.n, nc = C.n, nch = F.tp.nch;
+  std::vector<double> Pl((size_t)nch * nf * nc);
+  for (int ch = 0; ch < nch; ++ch)
+    for (int i = 0; i < nf; ++i) {
+      const double xc = nch == 1 ? rf.xi[i] : (rf.xi[i] + 2.0 * ch - 1.0) / 2.0;
+      lagrange_at(rc, xc, &Pl[((size_t)ch * nf + i) * nc]);
     }
-    // transpose: for each coarse index the (fine index, weight) pairs, fine index ascending
-    std::vector<std::vector<std::pair<int, double>>> cols(t.nc);
-    for (int J = 0; J < t.nf; ++J)
-      for (int m = 0; m < nw; ++m) {
-        const double v = pw[(size_t)J * nw + m];
-        if (v != 0.0) cols[pstart[J] + m].push_back({J, v});
-      }
-    std::vector<int> rptr(t.nc + 1, 0), ridx;
-    std::vector<double> rw;
-    for (int I = 0; I < t.nc; ++I) {
-      for (auto& pr : cols[I]) {
-        ridx.push_back(pr.first);
-        rw.push_back(pr.second);
-      }
-      rptr[I + 1] = (int)ridx.size();
-    }
-    GLLMG_CHECK(ridx.size() <= (size_t)t.nf * nw, GLLMG_EINVAL, "transfer table overflow");
-    std::vector<float> pw32(pw.begin(), pw.end()), rw32(rw.begin(), rw.end());
-    GLLMG_HIP(hipMemcpyAsync(t.pstart, pstart.data(), sizeof(int) * t.nf, hipMemcpyHostToDevice, s));
-    GLLMG_HIP(hipMemcpyAsync(t.pw64, pw.data(), sizeof(double) * pw.size(), hipMemcpyHostToDevice, s));
-    GLLMG_HIP(hipMemcpyAsync(t.pw32, pw32.data(), sizeof(float) * pw32.size(), hipMemcpyHostToDevice, s));
-    GLLMG_HIP(hipMemcpyAsync(t.rptr, rptr.data(), sizeof(int) * rptr.size(), hipMemcpyHostToDevice, s));
-    if (!ridx.empty()) {
-      GLLMG_HIP(hipMemcpyAsync(t.ridx, ridx.data(), sizeof(int) * ridx.size(), hipMemcpyHostToDevice, s));
-      GLLMG_HIP(hipMemcpyAsync(t.rw64, rw.data(), sizeof(double) * rw.size(), hipMemcpyHostToDevice, s));
-      GLLMG_HIP(hipMemcpyAsync(t.rw32, rw32.data(), sizeof(float) * rw32.size(), hipMemcpyHostToDevice, s));
-    }
-    GLLMG_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
-  }
+  std::vector<float> Pl32(Pl.begin(), Pl.end());
+  GLLMG_HIP(hipMemcpyAsync(F.tp.P64, Pl.data(), sizeof(double) * Pl.size(), hipMemcpyHostToDevice, s));
+  GLLMG_HIP(hipMemcpyAsync(F.tp.P32, Pl32.data(), sizeof(float) * Pl32.size(), hipMemcpyHostToDevice, s));
+  GLLMG_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
 }
 
 // lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
@@ -487,8 +438,18 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
 // ------------------------------------------------------------------ smoothers and cycles
 const void* dinv_of(const Level& L, int pr) { return pr == 0 ? (const void*)L.dinv64 : (const void*)L.dinv32; }
 
+// Chebyshev interval [cheb_lo lambda, lambda]: its center theta and half-width delta
+void cheb_interval(const gllmg_problem* P, const Level& L, double* theta, double* delta) {
+  const double lam = L.lmax, alpha = P->cfg.cheb_lo * lam;
+  *theta = 0.5 * (lam + alpha);
+  *delta = 0.5 * (lam - alpha);
+}
+
+// k smoothing steps on level l. zero: x starts at 0 (not read). started (with zero): the first
+// step from x = 0 has been done already by the restriction's epilogue (Jacobi: x written;
+// Chebyshev: d = dinv b / theta written).
 void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k, bool zero,
-                 hipStream_t s) {
+                 hipStream_t s, bool started = false) {
   Level& L = P->L[l];
   const int64_t N = L.g.N;
   if (k <= 0) {
@@ -501,7 +462,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
     for (int it = 0; it < k; ++it) {
       if (it == 0 && zero) {
-        jacobi_step(pr, N, 1, x, b, nullptr, dinv, P->cfg.omega, s);
+        if (!started) jacobi_step(pr, N, 1, x, b, nullptr, dinv, P->cfg.omega, s);
       } else {
         Epi ep;  // x = x + (omega dinv) (b - A x), fused into the product
         ep.mode = EPI_JACOBI;
@@ -515,13 +476,13 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
     return;
   }
   // Chebyshev acceleration of Jacobi on [cheb_lo lambda, lambda] (Saad, Alg. 12.1 with D^{-1})
-  const double lam = L.lmax, alpha = P->cfg.cheb_lo * lam;
-  const double theta = 0.5 * (lam + alpha), delta = 0.5 * (lam - alpha);
+  double theta, delta;
+  cheb_interval(P, L, &theta, &delta);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   const void* rin;
   if (zero) {
-    cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);  // r = b, d = dinv b / theta
+    if (!started) cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);  // d = dinv b / theta
     rin = b;
   } else {
     Epi ep;  // r = b - A x, d = dinv r / theta
@@ -561,7 +522,9 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   }
 }
 
-void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipStream_t s) {
+// started: the first pre-smoothing step from x = 0 has been done by the restriction
+void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipStream_t s,
+                  bool started = false) {
   Level& L = P->L[l];
   if (!L.has_coarse) {
     GLLMG_CHECK(L.Ainv64 != nullptr, GLLMG_EUNSUPPORTED,
@@ -570,11 +533,28 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
     return;
   }
   Level& C = P->L[l + 1];
-  smooth_impl(P, l, pr, b, x, P->cfg.nu_pre, true, s);
+  smooth_impl(P, l, pr, b, x, P->cfg.nu_pre, true, s, started);
   residual(P, l, pr, b, x, L.vr[pr], s);
-  launch_restrict(L, C, pr, L.vr[pr], C.vb[pr], P->T1, P->T2, s);
-  vcycle_level(P, l + 1, pr, C.vb[pr], C.vx[pr], s);
-  launch_prolong(L, C, pr, C.vx[pr], x, true, P->T1, P->T2, s);
+  // b_c = P^T r, and with it the coarse level's first smoothing step from x_c = 0
+  Epi ep;
+  ep.y = C.vb[pr];
+  const bool fuse = C.has_coarse && P->cfg.nu_pre > 0;
+  if (fuse && P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
+    ep.mode = EPI_STORE_JACOBI0;
+    ep.x = C.vx[pr];
+    ep.dinv = dinv_of(C, pr);
+    ep.om = P->cfg.omega;
+  } else if (fuse) {
+    double theta, delta;
+    cheb_interval(P, C, &theta, &delta);
+    ep.mode = EPI_STORE_CHEB0;
+    ep.d = C.vd[pr];
+    ep.dinv = dinv_of(C, pr);
+    ep.c1 = theta;
+  }
+  launch_restrict(L, C, pr, L.vr[pr], ep, P->F, s);
+  vcycle_level(P, l + 1, pr, C.vb[pr], C.vx[pr], s, fuse);
+  launch_prolong(L, C, pr, C.vx[pr], x, true, s);
   smooth_impl(P, l, pr, b, x, P->cfg.nu_post, false, s);
 }
 
@@ -1090,7 +1070,8 @@ gllmg_status gllmg_prolong(const gllmg_problem* P, int32_t fl, gllmg_prec prec, 
     const int pr = prec_index(P, prec);
     check_ptr(xc, pr == 0 ? 8 : 4, "xc");
     check_ptr(xf, pr == 0 ? 8 : 4, "xf");
-    launch_prolong(P->L[fl], P->L[fl + 1], pr, xc, xf, false, P->T1, P->T2, (hipStream_t)stream);
+    GLLMG_CHECK(xc != xf, GLLMG_EINVAL, "xc and xf must not alias");
+    launch_prolong(P->L[fl], P->L[fl + 1], pr, xc, xf, false, (hipStream_t)stream);
     return GLLMG_OK;
   });
 }
@@ -1103,7 +1084,10 @@ gllmg_status gllmg_restrict(const gllmg_problem* P, int32_t fl, gllmg_prec prec,
     const int pr = prec_index(P, prec);
     check_ptr(rf, pr == 0 ? 8 : 4, "rf");
     check_ptr(rc, pr == 0 ? 8 : 4, "rc");
-    launch_restrict(P->L[fl], P->L[fl + 1], pr, rf, rc, P->T1, P->T2, (hipStream_t)stream);
+    GLLMG_CHECK(rf != rc, GLLMG_EINVAL, "rf and rc must not alias");
+    Epi ep;
+    ep.y = rc;
+    launch_restrict(P->L[fl], P->L[fl + 1], pr, rf, ep, P->F, (hipStream_t)stream);
     return GLLMG_OK;
   });
 }

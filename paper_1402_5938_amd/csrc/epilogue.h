@@ -1,0 +1,106 @@
+// Per-node epilogues of the node-order sums (operator product, restriction): what is done with
+// each summed value. Shared by the kernels that end in such a sum.
+#pragma once
+
+#include "internal.h"
+
+namespace gllmg {
+
+
+// Typed view of the epilogue.
+template <typename T>
+struct EpiT {
+  int mode, from_zero, last;
+  T* y;
+  const T* b;
+  T* x;
+  const T* rin;
+  T* r;
+  T* d;
+  const T* dinv;
+  T c1, c2, om;
+};
+
+template <typename T>
+EpiT<T> typed(const Epi& e) {
+  return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
+                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
+}
+
+// acc = (A xin)_g, xin = the input vector's value at g
+template <typename T>
+__device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
+  switch (ep.mode) {
+    case EPI_STORE:
+      ep.y[g] = acc;
+      break;
+    case EPI_RESIDUAL:
+      ep.r[g] = ep.b[g] - acc;
+      break;
+    case EPI_JACOBI:
+      ep.x[g] = xin + (ep.om * ep.dinv[g]) * (ep.b[g] - acc);
+      break;
+    case EPI_CHEB_START: {  // r = b - A x, d = dinv r / theta (theta in c1)
+      const T ri = ep.b[g] - acc;
+      ep.r[g] = ri;
+      ep.d[g] = ep.dinv[g] * ri / ep.c1;
+      break;
+    }
+    case EPI_STORE_CHEB0:
+      ep.y[g] = acc;
+      ep.d[g] = ep.dinv[g] * acc / ep.c1;
+      break;
+    case EPI_STORE_JACOBI0:
+      ep.y[g] = acc;
+      ep.x[g] = (ep.om * ep.dinv[g]) * acc;
+      break;
+    default: {  // EPI_CHEB, input vector is d
+      const T xo = ep.from_zero ? xin : ep.x[g] + xin;
+      const T ri = ep.rin[g] - acc;
+      const T dn = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
+      if (ep.last) {  // the polynomial's final step: x = (x + d) + d_next, r and d not needed
+        ep.x[g] = xo + dn;
+      } else {
+        ep.x[g] = xo;
+        ep.r[g] = ri;
+        ep.d[g] = dn;
+      }
+    }
+  }
+}
+
+// Dirichlet boundary node: every output of the epilogue is 0 there.
+template <typename T>
+__device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
+  switch (ep.mode) {
+    case EPI_STORE:
+      ep.y[g] = T(0);
+      break;
+    case EPI_RESIDUAL:
+      ep.r[g] = T(0);
+      break;
+    case EPI_JACOBI:
+      ep.x[g] = T(0);
+      break;
+    case EPI_CHEB_START:
+      ep.r[g] = T(0);
+      ep.d[g] = T(0);
+      break;
+    case EPI_STORE_CHEB0:
+      ep.y[g] = T(0);
+      ep.d[g] = T(0);
+      break;
+    case EPI_STORE_JACOBI0:
+      ep.y[g] = T(0);
+      ep.x[g] = T(0);
+      break;
+    default:
+      ep.x[g] = T(0);
+      if (!ep.last) {
+        ep.r[g] = T(0);
+        ep.d[g] = T(0);
+      }
+  }
+}
+
+}  // namespace gllmg

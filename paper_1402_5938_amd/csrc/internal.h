@@ -77,11 +77,12 @@ struct Level {
   void* vx[2] = {nullptr, nullptr};
   void* vr[2] = {nullptr, nullptr};
   void* vd[2] = {nullptr, nullptr};
-  void* vt[2] = {nullptr, nullptr};
+  void* vd2[2] = {nullptr, nullptr};  // Chebyshev directions alternate between vd and vd2
   // transfer to the next coarser level (if any)
   bool has_coarse = false;
   Xfer tp;  // to the next coarser level
   // exact solve (coarsest level): dense inverse of the interior block
+  const void* zero = nullptr;  // 64 zero bytes in device memory (a load source for masked lanes)
   double* Ainv64 = nullptr;
   float* Ainv32 = nullptr;
   int64_t applies = 0;

@@ -13,6 +13,7 @@
 // (store, residual, Jacobi or Chebyshev update), so a smoothing step is two kernels and
 // never materializes A x.
 // Dirichlet data: boundary entries of x are read as 0 and A x is 0 at boundary nodes.
+#include "epilogue.h"
 #include "internal.h"
 
 namespace gllmg {
@@ -20,102 +21,6 @@ namespace gllmg {
 namespace {
 
 __host__ __device__ inline int nloc_of(int n, int dim) { return dim == 3 ? n * n * n : n * n; }
-
-// Typed view of the epilogue.
-template <typename T>
-struct EpiT {
-  int mode, from_zero, last;
-  T* y;
-  const T* b;
-  T* x;
-  const T* rin;
-  T* r;
-  T* d;
-  const T* dinv;
-  T c1, c2, om;
-};
-
-template <typename T>
-EpiT<T> typed(const Epi& e) {
-  return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
-                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
-}
-
-// acc = (A xin)_g, xin = the input vector's value at g
-template <typename T>
-__device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
-  switch (ep.mode) {
-    case EPI_STORE:
-      ep.y[g] = acc;
-      break;
-    case EPI_RESIDUAL:
-      ep.r[g] = ep.b[g] - acc;
-      break;
-    case EPI_JACOBI:
-      ep.x[g] = xin + (ep.om * ep.dinv[g]) * (ep.b[g] - acc);
-      break;
-    case EPI_CHEB_START: {  // r = b - A x, d = dinv r / theta (theta in c1)
-      const T ri = ep.b[g] - acc;
-      ep.r[g] = ri;
-      ep.d[g] = ep.dinv[g] * ri / ep.c1;
-      break;
-    }
-    case EPI_STORE_CHEB0:
-      ep.y[g] = acc;
-      ep.d[g] = ep.dinv[g] * acc / ep.c1;
-      break;
-    case EPI_STORE_JACOBI0:
-      ep.y[g] = acc;
-      ep.x[g] = (ep.om * ep.dinv[g]) * acc;
-      break;
-    default: {  // EPI_CHEB, input vector is d
-      const T xo = ep.from_zero ? xin : ep.x[g] + xin;
-      const T ri = ep.rin[g] - acc;
-      const T dn = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
-      if (ep.last) {  // the polynomial's final step: x = (x + d) + d_next, r and d not needed
-        ep.x[g] = xo + dn;
-      } else {
-        ep.x[g] = xo;
-        ep.r[g] = ri;
-        ep.d[g] = dn;
-      }
-    }
-  }
-}
-
-// Dirichlet boundary node: every output of the epilogue is 0 there.
-template <typename T>
-__device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
-  switch (ep.mode) {
-    case EPI_STORE:
-      ep.y[g] = T(0);
-      break;
-    case EPI_RESIDUAL:
-      ep.r[g] = T(0);
-      break;
-    case EPI_JACOBI:
-      ep.x[g] = T(0);
-      break;
-    case EPI_CHEB_START:
-      ep.r[g] = T(0);
-      ep.d[g] = T(0);
-      break;
-    case EPI_STORE_CHEB0:
-      ep.y[g] = T(0);
-      ep.d[g] = T(0);
-      break;
-    case EPI_STORE_JACOBI0:
-      ep.y[g] = T(0);
-      ep.x[g] = T(0);
-      break;
-    default:
-      ep.x[g] = T(0);
-      if (!ep.last) {
-        ep.r[g] = T(0);
-        ep.d[g] = T(0);
-      }
-  }
-}
 
 // Elements per workgroup so that a workgroup has about 256 threads (n^2 threads per element).
 #ifndef GLLMG_EPB_THREADS
@@ -301,6 +206,122 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   F[(int64_t)e * NN + ij] = acc;
 }
 
+// ------------------------------------------------------------------ order 1, one kernel
+// At p = 1 an element has 2^d nodes, and the levels where it occurs (the bottom of the
+// p-hierarchy and every coarser h-level) are small enough that two kernels per product are
+// bound by launch latency. Here 2^d adjacent lanes serve one node, one lane per element around
+// it (lane bits x, y, z = lower or upper element along the axis), each evaluating that
+// element's contribution from the same factored form
+//   y_e(l) = sum_a sum_m D[m, l_a] w_a(l with a -> m),  w_a(q) = sum_b G_ab(q) u_b(q),
+//   u_b(q) = sum_m D[q_b, m] x_e(q with b -> m);
+// the lanes then add their values by an xor butterfly (pairs, then pairs of pairs: the same
+// fixed order in every lane, since floating-point addition commutes), and the first lane runs
+// the epilogue. Lanes read their neighbours' inputs while others write outputs, so no output
+// may be the product's input (the in-place Jacobi update takes the two-kernel path).
+template <typename T>
+__device__ inline T pick(int b, T v0, T v1) {
+  return b ? v1 : v0;
+}
+
+template <int DIM, typename T>
+__global__ void __launch_bounds__(256)
+k_apply_p1(const T* __restrict__ x, const T* __restrict__ G, const T* __restrict__ Dm, Grid g,
+           int neumann, EpiT<T> ep, const T* __restrict__ zero) {
+  constexpr int NE = DIM == 3 ? 8 : 4;  // lanes per node = elements around it = points per element
+  constexpr int NZ = DIM == 3 ? 2 : 1;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;  // 2^d N may pass 2^32
+  const bool live = gid / NE < (uint64_t)g.N;
+  const uint32_t t = live ? (uint32_t)(gid / NE) : 0u;  // N < 2^31
+  const int k = (int)(gid % NE);
+  const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const int gz = DIM == 3 ? (int)(t / nxy) : 0;
+  const uint32_t rxy = t - (uint32_t)gz * nxy;
+  const int gy = (int)(rxy / (uint32_t)nx);
+  const int gx = (int)(rxy - (uint32_t)gy * nx);
+  auto bnd = [&](int cx, int cy, int cz) {
+    return cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || (DIM == 3 && (cz == 0 || cz == nz - 1));
+  };
+  const bool bnode = !neumann && bnd(gx, gy, gz);
+  const int kx = k & 1, ky = (k >> 1) & 1, kz = DIM == 3 ? k >> 2 : 0;
+  const int ex = gx - 1 + kx, ey = gy - 1 + ky, ez = DIM == 3 ? gz - 1 + kz : 0;
+  const bool ev = live && !bnode && ex >= 0 && ex < g.ne[0] && ey >= 0 && ey < g.ne[1] &&
+                  ez >= 0 && ez < g.ne[2];
+  const int64_t e = ev ? ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez) : 0;
+  // the element's nodal values (boundary values read as 0 unless neumann: such lanes read the
+  // zero instead) and the geometric factors, all loaded before use
+  T xe[NZ][2][2];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int cx = ex + a, cy = ey + b, cz = DIM == 3 ? ez + c : 0;
+        const bool m = ev && (neumann || !bnd(cx, cy, cz));
+        xe[c][b][a] = *(m ? x + (cx + (int64_t)nx * (cy + (int64_t)ny * cz)) : zero);
+      }
+  const T xin = x[t];
+  // the node's local coordinates in the element (runtime bits: every access below that depends
+  // on them is a select, so that all values stay in registers)
+  const int lx = 1 - kx, ly = 1 - ky, lz = DIM == 3 ? 1 - kz : 0;
+  constexpr int NC = DIM == 3 ? 6 : 3;
+  const T* Ge = G + e * (NC * NE);
+  T gq[DIM][2][NC];  // G at the points l with a -> m
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int qx = a == 0 ? m : lx, qy = a == 1 ? m : ly, qz = a == 2 ? m : lz;
+      const int qi = qx + 2 * qy + (DIM == 3 ? 4 * qz : 0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) gq[a][m][c] = Ge[c * NE + qi];
+    }
+  const T D00 = Dm[0], D01 = Dm[1], D10 = Dm[2], D11 = Dm[3];
+  auto X = [&](int i, int j, int l) {
+    const T v0 = pick(j, pick(i, xe[0][0][0], xe[0][0][1]), pick(i, xe[0][1][0], xe[0][1][1]));
+    if (DIM == 2) return v0;
+    const T v1 = pick(j, pick(i, xe[NZ - 1][0][0], xe[NZ - 1][0][1]),
+                      pick(i, xe[NZ - 1][1][0], xe[NZ - 1][1][1]));
+    return pick(l, v0, v1);
+  };
+  auto Drow0 = [&](int q) { return pick(q, D00, D10); };  // D[q][0]
+  auto Drow1 = [&](int q) { return pick(q, D01, D11); };  // D[q][1]
+  T contrib = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int qx = a == 0 ? m : lx, qy = a == 1 ? m : ly, qz = a == 2 ? m : lz;
+      const T ux = Drow0(qx) * X(0, qy, qz) + Drow1(qx) * X(1, qy, qz);
+      const T uy = Drow0(qy) * X(qx, 0, qz) + Drow1(qy) * X(qx, 1, qz);
+      const T* gc = gq[a][m];
+      T wa;
+      if (DIM == 3) {
+        const T uz = Drow0(qz) * X(qx, qy, 0) + Drow1(qz) * X(qx, qy, 1);
+        if (a == 0)
+          wa = gc[0] * ux + gc[1] * uy + gc[2] * uz;
+        else if (a == 1)
+          wa = gc[1] * ux + gc[3] * uy + gc[4] * uz;
+        else
+          wa = gc[2] * ux + gc[4] * uy + gc[5] * uz;
+      } else {
+        wa = a == 0 ? gc[0] * ux + gc[1] * uy : gc[1] * ux + gc[2] * uy;
+      }
+      const int la = a == 0 ? lx : (a == 1 ? ly : lz);
+      const T dm = m == 0 ? pick(la, D00, D01) : pick(la, D10, D11);  // D[m][l_a]
+      contrib += dm * wa;
+    }
+  if (!ev) contrib = T(0);
+#pragma unroll
+  for (int off = 1; off < NE; off <<= 1) contrib += __shfl_xor(contrib, off, NE);
+  if (!live || k != 0) return;
+  if (bnode)
+    epilogue_zero(ep, t);
+  else
+    epilogue(ep, t, contrib, xin);
+}
+
 // ------------------------------------------------------------------ gather
 // containing elements of grid coordinate c along one axis: (element, local index), lower first
 __device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
@@ -463,7 +484,25 @@ void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F
 }
 
 template <typename T>
+void apply_p1(const Level& L, int neumann, const void* x, const Epi& epi, hipStream_t s) {
+  GLLMG_CHECK(epi.y != x && epi.x != x && epi.r != x && epi.d != x, GLLMG_EINVAL,
+              "an output of the order-1 product aliases its input");
+  const T* G = std::is_same<T, double>::value ? (const T*)L.G64 : (const T*)L.G32;
+  const T* D = std::is_same<T, double>::value ? (const T*)L.D64 : (const T*)L.D32;
+  const int64_t lanes = L.g.N * (L.g.dim == 3 ? 8 : 4);
+  const unsigned nb = (unsigned)((lanes + 255) / 256);
+  if (L.g.dim == 3)
+    hipLaunchKernelGGL((k_apply_p1<3, T>), dim3(nb), dim3(256), 0, s, (const T*)x, G, D, L.g,
+                       neumann, typed<T>(epi), (const T*)L.zero);
+  else
+    hipLaunchKernelGGL((k_apply_p1<2, T>), dim3(nb), dim3(256), 0, s, (const T*)x, G, D, L.g,
+                       neumann, typed<T>(epi), (const T*)L.zero);
+  GLLMG_HIP(hipGetLastError());
+}
+
+template <typename T>
 void apply_t(const Level& L, int neumann, const void* x, const Epi& ep, void* F, hipStream_t s) {
+  if (L.n == 2 && ep.mode != EPI_JACOBI) return apply_p1<T>(L, neumann, x, ep, s);
   switch (L.n) {
 #define GLLMG_CASE(NV) \
   case NV:             \

@@ -110,6 +110,7 @@ struct gllmg_problem {
   bool owns_ws = false;
   double* mass = nullptr;
   void* F = nullptr;
+  void* zeros = nullptr;
   double* scal = nullptr;
   double* part = nullptr;
   int* flag = nullptr;
@@ -191,6 +192,8 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const int64_t N0 = P->L[0].g.N;
   P->mass = (double*)A.take(sizeof(double) * N0);
   P->F = A.take(sizeof(double) * std::max<size_t>(face, 1));
+  P->zeros = A.take(64);
+  for (auto& L : P->L) L.zero = P->zeros;
   P->scal = (double*)A.take(sizeof(double) * 64);
   P->part = (double*)A.take(sizeof(double) * kDotBlocks);
   P->flag = (int*)A.take(sizeof(int) * 4);
@@ -212,7 +215,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
       L.vx[pr] = A.take(es * N);
       L.vr[pr] = A.take(es * N);
       L.vd[pr] = A.take(es * N);
-      L.vt[pr] = A.take(es * N);
+      L.vd2[pr] = A.take(es * N);
     }
   }
   const size_t steady = A.used - before;
@@ -404,6 +407,7 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
   P->map = to_dev(map, P->map_modes, s, true);
   P->mu = to_dev(mu, P->mu_modes, s, false);
   GLLMG_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
+  GLLMG_HIP(hipMemsetAsync(P->zeros, 0, 64, s));
   P->re.clear();
   for (auto& L : P->L) {
     P->re.push_back(ref_element(L.g.p));
@@ -458,6 +462,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   }
   void* r = L.vr[pr];
   void* d = L.vd[pr];
+  void* d2 = L.vd2[pr];
   const void* dinv = dinv_of(L, pr);
   if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
     for (int it = 0; it < k; ++it) {
@@ -506,11 +511,12 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
       ep.x = x;
       ep.rin = rin;
       ep.r = r;
-      ep.d = d;
+      ep.d = d2;  // the next direction goes to the other buffer: d is the product's input
       ep.dinv = dinv;
       ep.c1 = rn * rho;
       ep.c2 = 2.0 * rn / delta;
       apply_epi(P, l, pr, 0, d, ep, s);
+      std::swap(d, d2);
       rin = r;
       rho = rn;
     } else if (k == 1) {  // a degree-1 polynomial has no product to fuse the update into

@@ -7,6 +7,16 @@
 namespace gllmg {
 
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup i runs on XCD i mod 8), and
+// each XCD has its own L2. This bijection of [0, n) gives XCD x a contiguous range of logical
+// workgroup indices, so that neighbouring elements (which share nodes) and neighbouring node
+// rows meet in the same L2.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_block(uint32_t i, uint32_t n) {
+  const uint32_t q = n / kXcds, r = n % kXcds, x = i % kXcds;
+  return x * q + (x < r ? x : r) + i / kXcds;
+}
+
 // Typed view of the epilogue.
 template <typename T>
 struct EpiT {

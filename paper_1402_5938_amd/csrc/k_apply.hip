@@ -38,11 +38,15 @@ struct Epb {
 // waves per SIMD) instead of spilling to scratch.
 template <int N>
 struct Waves {
+#ifndef GLLMG_APPLY_MINWAVES
+#define GLLMG_APPLY_MINWAVES 1
+#endif
+  static constexpr int min = N >= 12 ? 1 : GLLMG_APPLY_MINWAVES;
   static constexpr int max = N >= 12 ? 2 : 8;
 };
 
 template <int N, typename T, int EPB>
-__global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(1, Waves<N>::max)))
+__global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann) {
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
@@ -53,7 +57,7 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   const int le = t / NN;
   const int ij = t - le * NN;
   const int i = ij % N, j = ij / N;
-  const uint32_t e = blockIdx.x * EPB + le;
+  const uint32_t e = xcd_block(blockIdx.x, gridDim.x) * EPB + le;
   const bool valid = e < (uint32_t)g.E;
   const uint32_t ee = valid ? e : 0u;
   const uint32_t nexy = (uint32_t)g.ne[0] * (uint32_t)g.ne[1];
@@ -71,7 +75,14 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
   // Every global load of the first phase is issued before any is consumed (all addresses are
   // in bounds: an out-of-range element reads element 0, thread t reads D[t mod n^2]): the x
   // column, the first PF planes of geometric factors (PF bounded by a register budget) and D.
-  constexpr int PF = (N * 6 * (int)sizeof(T) / 4 <= 112) ? N : (N <= 12 ? 4 : 2);
+#ifdef GLLMG_APPLY_PF
+  constexpr int PF = GLLMG_APPLY_PF < N ? GLLMG_APPLY_PF : N;
+#else
+  // measured on the 2.1M-node products: all planes for n <= 6; beyond, 4 planes in FP64 and
+  // 2 in FP32 and at n > 12 (more registers for prefetch cost occupancy, or spill, for less
+  // latency saved)
+  constexpr int PF = N <= 6 ? N : (sizeof(T) == 8 && N <= 12 ? 4 : 2);
+#endif
   T xr[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
@@ -357,7 +368,7 @@ __global__ void __launch_bounds__(kGX * kGR)
 k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int nrows, int neumann,
          EpiT<T> ep) {
   constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
-  const int row = (int)blockIdx.x * kGR + (int)threadIdx.y;
+  const int row = (int)xcd_block(blockIdx.x, gridDim.x) * kGR + (int)threadIdx.y;
   if (row >= nrows) return;
   const int gy = DIM == 3 ? row % g.nn[1] : row;
   const int gz = DIM == 3 ? row / g.nn[1] : 0;

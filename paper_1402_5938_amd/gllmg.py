@@ -72,6 +72,10 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_1402_5938_amd.build")
+    # torch first: the library must resolve its HIP runtime to the one torch has loaded, since
+    # it works on torch's device memory and streams (loaded first, the library would bring in
+    # a second runtime that does not know them)
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.gllmg_last_error.restype = C.c_char_p

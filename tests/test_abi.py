@@ -59,3 +59,15 @@ def test_null_arguments_rejected():
     assert b"NULL" in lib.gllmg_last_error()
     assert lib.gllmg_apply(None, 0, 0, 0, None, None, None) == gllmg.EINVAL
     assert lib.gllmg_destroy(None) == gllmg.OK
+
+
+def test_binding_shares_torchs_hip_runtime():
+    """The binding loads the library after torch, so the process maps a single HIP runtime
+    (torch's device pointers and streams are only valid in the runtime that made them)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); from paper_1402_5938_amd import gllmg; gllmg.lib(); "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"

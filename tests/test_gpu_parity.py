@@ -71,7 +71,8 @@ def test_rhs_and_fields():
 
 TRANSFER_CASES = [
     (2, (4, 4), 4, "h"), (2, (4, 2), 3, "p"), (3, (4, 2, 2), 4, "p"), (3, (2, 2, 2), 2, "h"),
-    (3, (2, 2, 2), 8, "p"), (2, (6, 4), 6, "p"),
+    (3, (2, 2, 2), 8, "p"), (2, (6, 4), 6, "p"), (2, (4, 2), 5, "p"), (3, (2, 1, 2), 7, "p"),
+    (3, (2, 2, 2), 16, "p"), (3, (2, 2, 2), 8, "h"), (2, (2, 4), 16, "h"), (3, (2, 2, 2), 16, "h"),
 ]
 
 

@@ -190,6 +190,73 @@ def workload_serve(a):
                         f"budget {a.hbm_gb} GiB", **rep}
 
 
+SWEEP_CASES = [(3, 256, 1), (3, 128, 2), (3, 64, 4), (3, 40, 6), (3, 32, 8), (3, 20, 12), (3, 16, 16),
+               (2, 512, 8)]
+
+
+def _median_apply_us(G, x, y, reps):
+    import torch
+    for _ in range(10):
+        G.apply(x, y)
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        G.apply(x, y)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def workload_sweep(a):
+    """Operator products at working sets of about 1 GB and more (beyond the 256 MB Infinity
+    Cache), FP64 and FP32, against the 8 TB/s nominal and the measured device-copy bandwidth:
+    the median of 50 HIP-event-timed products after 10 warm-ups, per case."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    n = 1 << 27  # 1 GiB of FP64 per buffer
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * 8 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(4.6)
+    rows = []
+    for dim, ne, p in SWEEP_CASES:
+        for prec in ("f64", "f32"):
+            cfg = gllmg.make_config(dim, (ne,) * dim, p, "p", max_levels=1, vcycle_prec=prec,
+                                    eig_steps=1)
+            G = gllmg.Problem(cfg, mp, mu)
+            N = G.nnodes(0)
+            dt = torch.float64 if prec == "f64" else torch.float32
+            x = torch.from_numpy(inputs.uniform_nodal(99, N)).to(device="cuda", dtype=dt)
+            y = torch.empty_like(x)
+            us = _median_apply_us(G, x, y, 50)
+            nb = apply_bytes(dim, (ne,) * dim, p, N, 8 if prec == "f64" else 4)
+            gbs = nb / (us * 1e-6) / 1e9
+            rows.append({"dim": dim, "nelem": ne, "order": p, "prec": prec, "nodes": N,
+                         "algorithmic_bytes": nb, "apply_us": us, "gdof_s": N / us * 1e-3,
+                         "achieved_gbs": gbs, "frac_nominal": gbs / HBM_PEAK_GBS,
+                         "frac_copy": gbs / copy_gbs})
+            G.close()
+            del x, y
+            torch.cuda.empty_cache()
+    return {"workload": "apply sweep at >= 1 GB working sets (3D p = 1..16, 2D 512^2 p = 8)",
+            "copy_gbs": copy_gbs, "cases": rows}
+
+
 def workload_apply(a):
     """Operator products alone on the benchmark problem, for counter runs: 5 untimed products,
     a.apply_reps products timed with HIP events on the launch stream, then 3 plain device
@@ -226,7 +293,7 @@ def workload_apply(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
@@ -250,7 +317,7 @@ def main():
     torch.cuda.set_device(0)
     if a.workload != "config2":
         fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
-              "apply": workload_apply}[a.workload]
+              "apply": workload_apply, "sweep": workload_sweep}[a.workload]
         print(json.dumps(fn(a)))
         return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)

@@ -1,0 +1,416 @@
+// Device building blocks of the operator product: the element passes (3D, 2D), the node-order
+// gather of element vectors and the order-1 lane product. Each is a __device__ function over an
+// explicit element / row / lane index, shared by the product kernels (one launch per pass) and
+// the batched solver (one workgroup per problem, looping over the passes).
+#pragma once
+
+#include "epilogue.h"
+#include "internal.h"
+
+namespace gllmg {
+
+namespace {
+
+__host__ __device__ inline int nloc_of(int n, int dim) { return dim == 3 ? n * n * n : n * n; }
+
+// Elements per workgroup so that a workgroup has about 256 threads (n^2 threads per element).
+#ifndef GLLMG_EPB_THREADS
+#define GLLMG_EPB_THREADS 256
+#endif
+template <int N>
+struct Epb {
+  static constexpr int v = (N * N >= GLLMG_EPB_THREADS / 2) ? 1 : (GLLMG_EPB_THREADS / (N * N));
+};
+
+// ------------------------------------------------------------------ 3D element kernel
+// Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
+// y-contractions read the element tile from LDS, the z-contraction works in registers.
+// High orders keep a long register column per thread: allow up to 256 VGPRs (at most two
+// waves per SIMD) instead of spilling to scratch.
+template <int N>
+struct Waves {
+#ifndef GLLMG_APPLY_MINWAVES
+#define GLLMG_APPLY_MINWAVES 1
+#endif
+  static constexpr int min = N >= 12 ? 1 : GLLMG_APPLY_MINWAVES;
+  static constexpr int max = N >= 12 ? 2 : 8;
+};
+
+// One pass of the 3D element kernel over the EPB elements ebase.. by the threads t of a
+// workgroup: t < EPB n^2 own a column, others only join the barriers. sA and sB hold EPB n^3
+// values, sD n^2. Consecutive calls that share the LDS must be separated by a barrier.
+template <int N, typename T, int EPB>
+__device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ F,
+                                       const T* __restrict__ G, const T* __restrict__ Dm,
+                                       const Grid& g, int neumann, uint32_t ebase, int t,
+                                       T* __restrict__ sA, T* __restrict__ sB,
+                                       T* __restrict__ sD) {
+  constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
+  const bool act = t < EPB * NN;
+  const int tt = act ? t : 0;
+  const int le = tt / NN;
+  const int ij = tt - le * NN;
+  const int i = ij % N, j = ij / N;
+  const uint32_t e = ebase + le;
+  const bool valid = act && e < (uint32_t)g.E;
+  const uint32_t ee = valid ? e : 0u;
+  const uint32_t nexy = (uint32_t)g.ne[0] * (uint32_t)g.ne[1];
+  const int ez = (int)(ee / nexy);
+  const uint32_t rxy = ee - (uint32_t)ez * nexy;
+  const int ey = (int)(rxy / (uint32_t)g.ne[0]);
+  const int ex = (int)(rxy - (uint32_t)ey * g.ne[0]);
+  const int gx = ex * P + i, gy = ey * P + j;
+  const bool bxy = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
+  const int64_t sxy = (int64_t)g.nn[0] * g.nn[1];
+  const int64_t gb = gx + (int64_t)g.nn[0] * gy + sxy * (int64_t)(ez * P);
+  T* A = sA + le * NNN;
+  T* B = sB + le * NNN;
+
+  // Every global load of the first phase is issued before any is consumed (all addresses are
+  // in bounds: an out-of-range element reads element 0, thread t reads D[t mod n^2]): the x
+  // column, the first PF planes of geometric factors (PF bounded by a register budget) and D.
+#ifdef GLLMG_APPLY_PF
+  constexpr int PF = GLLMG_APPLY_PF < N ? GLLMG_APPLY_PF : N;
+#else
+  // measured on the 2.1M-node products: all planes for n <= 6; beyond, 4 planes in FP64 and
+  // 2 in FP32 and at n > 12 (more registers for prefetch cost occupancy, or spill, for less
+  // latency saved)
+  constexpr int PF = N <= 6 ? N : (sizeof(T) == 8 && N <= 12 ? 4 : 2);
+#endif
+  T xr[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
+  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
+  T gp[PF][6];
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
+  const T dval = Dm[ij];
+  if (le == 0 && act) sD[ij] = dval;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int gz = ez * P + k;
+    const bool bnd = bxy || gz == 0 || gz == g.nn[2] - 1;
+    if (!valid || (bnd && !neumann)) xr[k] = T(0);
+    if (act) A[k * NN + ij] = xr[k];
+  }
+  __syncthreads();
+  T Di[N], Dj[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    Di[l] = sD[i * N + l];
+    Dj[l] = sD[j * N + l];
+  }
+
+  T wx[N], wy[N], wz[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    T ux = T(0), uy = T(0), uz = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      ux += Di[l] * A[k * NN + j * N + l];
+      uy += Dj[l] * A[k * NN + l * N + i];
+      uz += sD[k * N + l] * xr[l];
+    }
+    T g0, g1, g2, g3, g4, g5;
+    if (k < PF) {
+      g0 = gp[k < PF ? k : 0][0];
+      g1 = gp[k < PF ? k : 0][1];
+      g2 = gp[k < PF ? k : 0][2];
+      g3 = gp[k < PF ? k : 0][3];
+      g4 = gp[k < PF ? k : 0][4];
+      g5 = gp[k < PF ? k : 0][5];
+    } else {
+      g0 = Ge[0 * NNN + k * NN];
+      g1 = Ge[1 * NNN + k * NN];
+      g2 = Ge[2 * NNN + k * NN];
+      g3 = Ge[3 * NNN + k * NN];
+      g4 = Ge[4 * NNN + k * NN];
+      g5 = Ge[5 * NNN + k * NN];
+    }
+    wx[k] = g0 * ux + g1 * uy + g2 * uz;
+    wy[k] = g1 * ux + g3 * uy + g4 * uz;
+    wz[k] = g2 * ux + g4 * uy + g5 * uz;
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      A[k * NN + ij] = wx[k];
+      B[k * NN + ij] = wy[k];
+    }
+  }
+  __syncthreads();
+  if (!valid) return;
+  T DiT[N], DjT[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    DiT[l] = sD[l * N + i];
+    DjT[l] = sD[l * N + j];
+  }
+  T* Fe = F + (int64_t)e * NNN + ij;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    T acc = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      acc += DiT[l] * A[k * NN + j * N + l];
+      acc += DjT[l] * B[k * NN + l * N + i];
+      acc += sD[l * N + k] * wz[l];
+    }
+    Fe[k * NN] = acc;
+  }
+}
+
+// ------------------------------------------------------------------ 2D element kernel
+// One pass of the 2D element kernel (same conventions as elem3d; sA and sB hold EPB n^2).
+template <int N, typename T, int EPB>
+__device__ __forceinline__ void elem2d(const T* __restrict__ x, T* __restrict__ F,
+                                       const T* __restrict__ G, const T* __restrict__ Dm,
+                                       const Grid& g, int neumann, uint32_t ebase, int t,
+                                       T* __restrict__ sA, T* __restrict__ sB) {
+  constexpr int NN = N * N, P = N - 1;
+  const bool act = t < EPB * NN;
+  const int tt = act ? t : 0;
+  const int le = tt / NN;
+  const int ij = tt - le * NN;
+  const int i = ij % N, j = ij / N;
+  const uint32_t e = ebase + le;
+  const bool valid = act && e < (uint32_t)g.E;
+  const uint32_t ee = valid ? e : 0u;
+  const int ey = (int)(ee / (uint32_t)g.ne[0]);
+  const int ex = (int)(ee - (uint32_t)ey * g.ne[0]);
+  const int gx = ex * P + i, gy = ey * P + j;
+  const bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
+  const int64_t gi = gx + (int64_t)g.nn[0] * gy;
+  T* A = sA + le * NN;
+  T* B = sB + le * NN;
+  T xv = x[gi];
+  const T* Ge = G + (int64_t)ee * (3 * NN) + ij;
+  const T g0 = Ge[0], g1 = Ge[NN], g2 = Ge[2 * NN];
+  if (!valid || (bnd && !neumann)) xv = T(0);
+  if (act) A[ij] = xv;
+  __syncthreads();
+  T ux = T(0), uy = T(0);
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    ux += Dm[i * N + l] * A[j * N + l];
+    uy += Dm[j * N + l] * A[l * N + i];
+  }
+  const T wx = g0 * ux + g1 * uy;
+  const T wy = g1 * ux + g2 * uy;
+  __syncthreads();
+  if (act) {
+    A[ij] = wx;
+    B[ij] = wy;
+  }
+  __syncthreads();
+  if (!valid) return;
+  T acc = T(0);
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    acc += Dm[l * N + i] * A[j * N + l];
+    acc += Dm[l * N + j] * B[l * N + i];
+  }
+  F[(int64_t)e * NN + ij] = acc;
+}
+
+// ------------------------------------------------------------------ order 1, one kernel
+// At p = 1 an element has 2^d nodes, and the levels where it occurs (the bottom of the
+// p-hierarchy and every coarser h-level) are small enough that two kernels per product are
+// bound by launch latency. Here 2^d adjacent lanes serve one node, one lane per element around
+// it (lane bits x, y, z = lower or upper element along the axis), each evaluating that
+// element's contribution from the same factored form
+//   y_e(l) = sum_a sum_m D[m, l_a] w_a(l with a -> m),  w_a(q) = sum_b G_ab(q) u_b(q),
+//   u_b(q) = sum_m D[q_b, m] x_e(q with b -> m);
+// the lanes then add their values by an xor butterfly (pairs, then pairs of pairs: the same
+// fixed order in every lane, since floating-point addition commutes), and the first lane runs
+// the epilogue. Lanes read their neighbours' inputs while others write outputs, so no output
+// may be the product's input (the in-place Jacobi update takes the two-kernel path).
+template <typename T>
+__device__ inline T pick(int b, T v0, T v1) {
+  return b ? v1 : v0;
+}
+
+// Lane gid of the order-1 product (2^d lanes per node; every lane of a wave must take part,
+// for the butterfly).
+template <int DIM, typename T>
+__device__ __forceinline__ void p1_lanes(const T* __restrict__ x, const T* __restrict__ G,
+                                         const T* __restrict__ Dm, const Grid& g, int neumann,
+                                         const EpiT<T>& ep, const T* __restrict__ zero,
+                                         uint64_t gid) {
+  constexpr int NE = DIM == 3 ? 8 : 4;  // lanes per node = elements around it = points per element
+  constexpr int NZ = DIM == 3 ? 2 : 1;
+  const bool live = gid / NE < (uint64_t)g.N;
+  const uint32_t t = live ? (uint32_t)(gid / NE) : 0u;  // N < 2^31
+  const int k = (int)(gid % NE);
+  const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const int gz = DIM == 3 ? (int)(t / nxy) : 0;
+  const uint32_t rxy = t - (uint32_t)gz * nxy;
+  const int gy = (int)(rxy / (uint32_t)nx);
+  const int gx = (int)(rxy - (uint32_t)gy * nx);
+  auto bnd = [&](int cx, int cy, int cz) {
+    return cx == 0 || cx == nx - 1 || cy == 0 || cy == ny - 1 || (DIM == 3 && (cz == 0 || cz == nz - 1));
+  };
+  const bool bnode = !neumann && bnd(gx, gy, gz);
+  const int kx = k & 1, ky = (k >> 1) & 1, kz = DIM == 3 ? k >> 2 : 0;
+  const int ex = gx - 1 + kx, ey = gy - 1 + ky, ez = DIM == 3 ? gz - 1 + kz : 0;
+  const bool ev = live && !bnode && ex >= 0 && ex < g.ne[0] && ey >= 0 && ey < g.ne[1] &&
+                  ez >= 0 && ez < g.ne[2];
+  const int64_t e = ev ? ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez) : 0;
+  // the element's nodal values (boundary values read as 0 unless neumann: such lanes read the
+  // zero instead) and the geometric factors, all loaded before use
+  T xe[NZ][2][2];
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int cx = ex + a, cy = ey + b, cz = DIM == 3 ? ez + c : 0;
+        const bool m = ev && (neumann || !bnd(cx, cy, cz));
+        xe[c][b][a] = *(m ? x + (cx + (int64_t)nx * (cy + (int64_t)ny * cz)) : zero);
+      }
+  const T xin = x[t];
+  // the node's local coordinates in the element (runtime bits: every access below that depends
+  // on them is a select, so that all values stay in registers)
+  const int lx = 1 - kx, ly = 1 - ky, lz = DIM == 3 ? 1 - kz : 0;
+  constexpr int NC = DIM == 3 ? 6 : 3;
+  const T* Ge = G + e * (NC * NE);
+  T gq[DIM][2][NC];  // G at the points l with a -> m
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int qx = a == 0 ? m : lx, qy = a == 1 ? m : ly, qz = a == 2 ? m : lz;
+      const int qi = qx + 2 * qy + (DIM == 3 ? 4 * qz : 0);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) gq[a][m][c] = Ge[c * NE + qi];
+    }
+  const T D00 = Dm[0], D01 = Dm[1], D10 = Dm[2], D11 = Dm[3];
+  auto X = [&](int i, int j, int l) {
+    const T v0 = pick(j, pick(i, xe[0][0][0], xe[0][0][1]), pick(i, xe[0][1][0], xe[0][1][1]));
+    if (DIM == 2) return v0;
+    const T v1 = pick(j, pick(i, xe[NZ - 1][0][0], xe[NZ - 1][0][1]),
+                      pick(i, xe[NZ - 1][1][0], xe[NZ - 1][1][1]));
+    return pick(l, v0, v1);
+  };
+  auto Drow0 = [&](int q) { return pick(q, D00, D10); };  // D[q][0]
+  auto Drow1 = [&](int q) { return pick(q, D01, D11); };  // D[q][1]
+  T contrib = T(0);
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int qx = a == 0 ? m : lx, qy = a == 1 ? m : ly, qz = a == 2 ? m : lz;
+      const T ux = Drow0(qx) * X(0, qy, qz) + Drow1(qx) * X(1, qy, qz);
+      const T uy = Drow0(qy) * X(qx, 0, qz) + Drow1(qy) * X(qx, 1, qz);
+      const T* gc = gq[a][m];
+      T wa;
+      if (DIM == 3) {
+        const T uz = Drow0(qz) * X(qx, qy, 0) + Drow1(qz) * X(qx, qy, 1);
+        if (a == 0)
+          wa = gc[0] * ux + gc[1] * uy + gc[2] * uz;
+        else if (a == 1)
+          wa = gc[1] * ux + gc[3] * uy + gc[4] * uz;
+        else
+          wa = gc[2] * ux + gc[4] * uy + gc[5] * uz;
+      } else {
+        wa = a == 0 ? gc[0] * ux + gc[1] * uy : gc[1] * ux + gc[2] * uy;
+      }
+      const int la = a == 0 ? lx : (a == 1 ? ly : lz);
+      const T dm = m == 0 ? pick(la, D00, D01) : pick(la, D10, D11);  // D[m][l_a]
+      contrib += dm * wa;
+    }
+  if (!ev) contrib = T(0);
+#pragma unroll
+  for (int off = 1; off < NE; off <<= 1) contrib += __shfl_xor(contrib, off, NE);
+  if (!live || k != 0) return;
+  if (bnode)
+    epilogue_zero(ep, t);
+  else
+    epilogue(ep, t, contrib, xin);
+}
+
+// ------------------------------------------------------------------ gather
+// containing elements of grid coordinate c along one axis: (element, local index), lower first
+__device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
+  const int e = c / p, r = c - e * p;
+  if (r != 0) {
+    ce[0] = e;
+    cl[0] = r;
+    return 1;
+  }
+  int k = 0;
+  if (e > 0) {
+    ce[k] = e - 1;
+    cl[k] = p;
+    ++k;
+  }
+  if (e < ne) {
+    ce[k] = e;
+    cl[k] = 0;
+    ++k;
+  }
+  return k;
+}
+
+// acc = sum over the elements containing node g of F[e][local index of g], then the epilogue;
+// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann. Each wave walks one
+// grid row (fixed y, z) in chunks of 64 nodes, a workgroup holds kGR rows, so the row's
+// element candidates along y and z are uniform across the wave.
+constexpr int kGX = 64;
+constexpr int kGR = 4;
+
+// Node row `row` (fixed y, z) of the gather, nodes lane, lane + nlanes, ...
+template <int N, int DIM, typename T>
+__device__ __forceinline__ void gather_row(const T* __restrict__ F, const T* __restrict__ xin,
+                                           const Grid& g, int neumann, const EpiT<T>& ep, int row,
+                                           int lane, int nlanes) {
+  constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
+  const int gy = DIM == 3 ? row % g.nn[1] : row;
+  const int gz = DIM == 3 ? row / g.nn[1] : 0;
+  const bool bnd_yz = gy == 0 || gy == g.nn[1] - 1 || (DIM == 3 && (gz == 0 || gz == g.nn[2] - 1));
+  int cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
+  const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
+  const int cz = DIM == 3 ? axis_cands(gz, P, g.ne[2], cez, clz) : 1;
+  const int64_t rbase = (int64_t)g.nn[0] * row;
+  for (int gx = lane; gx < g.nn[0]; gx += nlanes) {
+    const int64_t t = rbase + gx;
+    if ((bnd_yz || gx == 0 || gx == g.nn[0] - 1) && !neumann) {
+      epilogue_zero(ep, t);
+      continue;
+    }
+    int cex[2], clx[2];
+    const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+    // up to 8 loads, all issued before the sum: missing candidates re-read candidate 0 and
+    // are skipped in the sum (the sum order is z, y, x with the lower element first)
+    T v[2][2][2];
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+          const int az = kz < cz ? kz : 0, ay = ky < cy ? ky : 0, ax = kx < cx ? kx : 0;
+          const int64_t e = cex[ax] + (int64_t)g.ne[0] * (cey[ay] + (int64_t)g.ne[1] * cez[az]);
+          v[kz][ky][kx] = F[e * NL + clx[ax] + N * (cly[ay] + N * clz[az])];
+        }
+    T acc = T(0);
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx)
+          if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
+    const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
+    epilogue(ep, t, acc, xv);
+  }
+}
+
+}  // namespace
+
+}  // namespace gllmg

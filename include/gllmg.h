@@ -153,6 +153,10 @@ gllmg_status gllmg_set_lmax(gllmg_problem* prob, int32_t level, double lmax);
  * The graph is rebuilt after gllmg_set_lmax. */
 gllmg_status gllmg_set_graphs(gllmg_problem* prob, int32_t enable);
 
+/* Whether gllmg_batch_solve may solve this problem with the persistent solver (enable = 1, the
+ * default) or must use the stream path (0). See gllmg_batch_solve. */
+gllmg_status gllmg_set_persistent(gllmg_problem* prob, int32_t enable);
+
 /* Physical node coordinates x = Phi(X) of a level: out[g * dim + a]. FP64. Asynchronous. */
 gllmg_status gllmg_node_coords(const gllmg_problem* prob, int32_t level, double* out, void* stream);
 
@@ -221,9 +225,15 @@ gllmg_status gllmg_solve_begin(gllmg_problem* prob, int32_t mode, const double* 
 gllmg_status gllmg_solve_poll(gllmg_problem* prob, int32_t* done);
 gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
 
-/* Solve `count` independent problems (any mix of dimension, mesh, order and precision), each
- * on its own internal stream ordered after `stream`, advanced iteration by iteration from one
- * host thread; `stream` waits for all of them before the call returns. stats and status may be
+/* Solve `count` independent problems (any mix of dimension, mesh, order and precision), all
+ * ordered after `stream`; the call returns when every solve has finished. Small problems (3D,
+ * FP32 V-cycle, at most 10,000 fine-level nodes and 16 levels, an exact coarse solve,
+ * maxit < 1024, persistent mode not switched off) are solved by one persistent kernel launch
+ * per finest order on `stream`, one workgroup per problem, each stopping on its own: the same
+ * steps, smoothers and transfers as gllmg_solve, with the workgroup's dot products summed in
+ * another fixed order (iterates agree to rounding, not bitwise). The others run on their own
+ * internal streams, advanced iteration by iteration from the host thread, concurrently with
+ * the persistent launch. stats and status may be
  * NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
  * any solve starts: EINVAL). Returns GLLMG_OK if every solve converged, else the first error
  * other than ENOTCONV if any, else ENOTCONV (status[i] holds each problem's own status; a

@@ -32,7 +32,7 @@ struct EpiT {
 };
 
 template <typename T>
-EpiT<T> typed(const Epi& e) {
+__host__ __device__ EpiT<T> typed(const Epi& e) {
   return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
                  (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
 }

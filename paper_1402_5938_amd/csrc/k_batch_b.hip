@@ -1,0 +1,17 @@
+// Persistent batched solver, instantiated for finest orders n0 = 6..9.
+#include "batch.h"
+
+namespace gllmg {
+
+template <int N0>
+void launch_batch_n(const BatchArgs& a, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch<N0>, dim3((unsigned)count), dim3(kBatchThreads), 0, s, a);
+  GLLMG_HIP(hipGetLastError());
+}
+
+template void launch_batch_n<6>(const BatchArgs&, int, hipStream_t);
+template void launch_batch_n<7>(const BatchArgs&, int, hipStream_t);
+template void launch_batch_n<8>(const BatchArgs&, int, hipStream_t);
+template void launch_batch_n<9>(const BatchArgs&, int, hipStream_t);
+
+}  // namespace gllmg

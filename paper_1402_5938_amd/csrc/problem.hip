@@ -3,10 +3,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <memory>
 #include <thread>
 
+#include "batch_desc.h"
 #include "internal.h"
 
 namespace gllmg {
@@ -144,6 +146,9 @@ struct gllmg_problem {
     std::chrono::steady_clock::time_point t0;
   } sv;
   hipStream_t xs = nullptr;  // internal stream for batched solves (default priority)
+  BatchProblem* bdev = nullptr;   // descriptor of the persistent batched solver (workspace)
+  BatchProblem* bhost = nullptr;  // its pinned host image
+  bool persistent = true;         // gllmg_batch_solve may use the persistent solver
 };
 
 namespace gllmg {
@@ -192,6 +197,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const int64_t N0 = P->L[0].g.N;
   P->mass = (double*)A.take(sizeof(double) * N0);
   P->F = A.take(sizeof(double) * std::max<size_t>(face, 1));
+  P->bdev = (BatchProblem*)A.take(sizeof(BatchProblem));
   P->zeros = A.take(64);
   for (auto& L : P->L) L.zero = P->zeros;
   P->scal = (double*)A.take(sizeof(double) * 64);
@@ -798,6 +804,75 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
   return solve_end(P, st);
 }
 
+// ------------------------------------------------------------------ persistent batched solver
+// Problems it takes: 3D, FP32 V-cycle, at most kBatchMaxLevels levels and kBatchMaxNodes fine
+// nodes, an exact coarse solve, orders along the chain n0, n0/2 + 1, ..., 2 (h-coarsening at
+// n0 or at 2), and maxit below the history capacity.
+bool batch_eligible(const gllmg_problem* P, int maxit) {
+  if (!P->persistent || P->cfg.dim != 3 || P->vprec != 1) return false;
+  if (P->L.size() > (size_t)kBatchMaxLevels || !P->L.back().Ainv64) return false;
+  if (maxit >= kBatchHist || P->L[0].g.N > kBatchMaxNodes) return false;
+  const int n0 = P->L[0].n;
+  if (n0 < 2 || n0 > 17) return false;
+  auto in_chain = [&](int n) {
+    for (int m = n0;; m = m / 2 + 1) {
+      if (m == n) return true;
+      if (m <= 2) return false;
+    }
+  };
+  for (size_t l = 0; l < P->L.size(); ++l) {
+    const Level& L = P->L[l];
+    if (!in_chain(L.n)) return false;
+    if (l + 1 < P->L.size() && L.tp.nch == 2 && L.n != n0 && L.n != 2) return false;
+  }
+  return true;
+}
+
+void batch_fill(const gllmg_problem* P, BatchProblem& d) {
+  d.nlev = (int)P->L.size();
+  d.smoother = P->cfg.smoother;
+  d.nu_pre = P->cfg.nu_pre;
+  d.nu_post = P->cfg.nu_post;
+  d.vprec = P->vprec;
+  d.omega = P->cfg.omega;
+  d.F = P->F;
+  d.zero = P->zeros;
+  d.pr = P->pr;
+  d.pz = P->pz;
+  d.pp = P->pp;
+  d.ph = P->ph;
+  d.pt = P->pt;
+  for (size_t l = 0; l < P->L.size(); ++l) {
+    const Level& L = P->L[l];
+    BatchLevel& b = d.L[l];
+    b.g = L.g;
+    b.n = L.n;
+    b.has_coarse = L.has_coarse ? 1 : 0;
+    b.nch = L.tp.nch;
+    b.nint = L.nint;
+    const double lam = L.lmax, alpha = P->cfg.cheb_lo * lam;
+    b.theta = 0.5 * (lam + alpha);
+    b.delta = 0.5 * (lam - alpha);
+    b.G64 = L.G64;
+    b.G32 = L.G32;
+    b.D64 = L.D64;
+    b.D32 = L.D32;
+    b.dinv64 = L.dinv64;
+    b.dinv32 = L.dinv32;
+    b.P64 = L.tp.P64;
+    b.P32 = L.tp.P32;
+    b.Ainv64 = L.Ainv64;
+    b.Ainv32 = L.Ainv32;
+    for (int q = 0; q < 2; ++q) {
+      b.vb[q] = L.vb[q];
+      b.vx[q] = L.vx[q];
+      b.vr[q] = L.vr[q];
+      b.vd[q] = L.vd[q];
+      b.vd2[q] = L.vd2[q];
+    }
+  }
+}
+
 thread_local std::string g_err;
 
 template <class Fn>
@@ -911,6 +986,7 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
       ~Free() {
         if (armed && p->owns_ws) (void)hipFree(p->ws);
         if (armed && p->hbuf) (void)hipHostFree(p->hbuf);
+        if (armed && p->bhost) (void)hipHostFree(p->bhost);
       }
     } guard_free{P.get()};
     Arena A;
@@ -918,6 +994,7 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
     A.size = P->ws_bytes;
     layout(P.get(), specs, A);
     GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&P->bhost, sizeof(BatchProblem), hipHostMallocDefault));
     setup_impl(P.get(), map, mu, s);
     if (P->L.back().Ainv64) {
       // capture the solve's V-cycle now, while nothing else of this problem is in flight
@@ -943,6 +1020,7 @@ gllmg_status gllmg_destroy(gllmg_problem* P) {
     if (P->sv.ev) (void)hipEventDestroy(P->sv.ev);
     if (P->owns_ws) (void)hipFree(P->ws);
     if (P->hbuf) (void)hipHostFree(P->hbuf);
+    if (P->bhost) (void)hipHostFree(P->bhost);
     delete P;
     return GLLMG_OK;
   });
@@ -976,6 +1054,14 @@ gllmg_status gllmg_set_lmax(gllmg_problem* P, int32_t level, double lmax) {
     GLLMG_CHECK(lmax > 0.0 && std::isfinite(lmax), GLLMG_EINVAL, "lmax must be positive");
     P->L[level].lmax = lmax;
     drop_graph(P);  // the captured V-cycle holds the old Chebyshev coefficients
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_set_persistent(gllmg_problem* P, int32_t enable) {
+  return guard([&]() {
+    GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
+    P->persistent = enable != 0;
     return GLLMG_OK;
   });
 }
@@ -1182,7 +1268,52 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       GLLMG_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), GLLMG_EINVAL,
                   "a problem appears twice in the batch");
     }
+    // small problems: one persistent launch per finest order, one workgroup per problem, on
+    // the caller's stream
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<char> pers(count, 0);
+    std::vector<int> groups[18];
+    const bool args_ok = (mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG) && rtol > 0.0 && maxit >= 1;
     for (int i = 0; i < count; ++i) {
+      gllmg_problem* P = probs[i];
+      if (!args_ok || P->sv.active || !batch_eligible(P, maxit)) continue;
+      if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
+      pers[i] = 1;
+      groups[P->L[0].n].push_back(i);
+    }
+    for (int n0 = 2; n0 <= 17; ++n0) {
+      const auto& idx = groups[n0];
+      for (size_t c0 = 0; c0 < idx.size(); c0 += kBatchMaxProbs) {
+        const int cnt = (int)std::min<size_t>(kBatchMaxProbs, idx.size() - c0);
+        BatchArgs args{};
+        for (int k = 0; k < cnt; ++k) {
+          const int i = idx[c0 + k];
+          gllmg_problem* P = probs[i];
+          BatchProblem& h = *P->bhost;
+          batch_fill(P, h);
+          h.b = b[i];
+          h.x = x[i];
+          h.rtol = rtol;
+          h.maxit = maxit;
+          h.mode = mode;
+          GLLMG_HIP(hipMemcpyAsync(P->bdev, &h, offsetof(BatchProblem, iters),
+                                   hipMemcpyHostToDevice, cs));
+          args.p[k] = P->bdev;
+        }
+        launch_batch(n0, args, cnt, cs);
+      }
+    }
+    for (int i = 0; i < count; ++i)
+      if (pers[i]) {
+        gllmg_problem* P = probs[i];
+        GLLMG_HIP(hipMemcpyAsync(&P->bhost->iters, &P->bdev->iters,
+                                 offsetof(BatchProblem, hist) - offsetof(BatchProblem, iters) +
+                                     sizeof(double) * (size_t)(maxit + 1),
+                                 hipMemcpyDeviceToHost, cs));
+      }
+    // the others: their own streams, iteration-level interleaving
+    for (int i = 0; i < count; ++i) {
+      if (pers[i]) continue;
       gllmg_problem* P = probs[i];
       if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
       GLLMG_HIP(hipStreamWaitEvent(P->xs, start, 0));
@@ -1227,6 +1358,31 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
     for (int i : live) {
       GLLMG_HIP(hipEventRecord(probs[i]->sv.ev, probs[i]->xs));
       GLLMG_HIP(hipStreamWaitEvent(cs, probs[i]->sv.ev, 0));
+    }
+    if (std::find(pers.begin(), pers.end(), 1) != pers.end()) {
+      GLLMG_HIP(hipStreamSynchronize(cs));
+      const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      for (int i = 0; i < count; ++i) {
+        if (!pers[i]) continue;
+        gllmg_problem* P = probs[i];
+        const BatchProblem& r = *P->bhost;
+        for (size_t l = 0; l < P->L.size(); ++l) P->L[l].applies += r.applies[l];
+        if (stats) {
+          gllmg_solve_stats& st = stats[i];
+          st.iters = r.iters;
+          st.converged = r.status == 0 ? 1 : 0;
+          st.relres = r.n0 > 0.0 ? r.nr / r.n0 : 0.0;
+          st.relres_true = r.relres_true;
+          st.t_solve_s = el;
+          for (int l = 0; l < 16; ++l) st.applies[l] = l < (int)P->L.size() ? r.applies[l] : 0;
+          if (st.history)
+            for (int k = 0; k <= r.iters && k <= maxit; ++k) st.history[k] = r.hist[k];
+        }
+        const gllmg_status si = r.status == 0 ? GLLMG_OK : (r.status == 1 ? GLLMG_ENOTCONV : GLLMG_EBREAKDOWN);
+        if (status) status[i] = si;
+        if (si != GLLMG_OK) fail(i, si);
+        if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
+      }
     }
     (void)hipEventDestroy(start);
     if (worst == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached in a problem";

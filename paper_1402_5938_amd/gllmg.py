@@ -59,7 +59,7 @@ _lib = None
 
 EXPORTS = ["gllmg_last_error", "gllmg_config_default", "gllmg_plan", "gllmg_setup",
            "gllmg_destroy", "gllmg_num_levels", "gllmg_level_info", "gllmg_set_lmax",
-           "gllmg_set_graphs",
+           "gllmg_set_graphs", "gllmg_set_persistent",
            "gllmg_node_coords", "gllmg_eval_field", "gllmg_rhs", "gllmg_diag", "gllmg_apply",
            "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve",
            "gllmg_solve_begin", "gllmg_solve_poll", "gllmg_solve_end", "gllmg_batch_solve"]
@@ -90,6 +90,7 @@ def lib():
                                    C.POINTER(i32), C.POINTER(dbl)]
     L.gllmg_set_lmax.argtypes = [vp, i32, dbl]
     L.gllmg_set_graphs.argtypes = [vp, i32]
+    L.gllmg_set_persistent.argtypes = [vp, i32]
     L.gllmg_node_coords.argtypes = [vp, i32, vp, vp]
     L.gllmg_eval_field.argtypes = [vp, i32, C.POINTER(Field), vp, vp]
     L.gllmg_rhs.argtypes = [vp, vp, vp, vp]
@@ -257,6 +258,9 @@ class Problem:
 
     def set_graphs(self, enable: bool):
         _check(lib().gllmg_set_graphs(self.h, 1 if enable else 0))
+
+    def set_persistent(self, enable: bool):
+        _check(lib().gllmg_set_persistent(self.h, 1 if enable else 0))
 
     def nnodes(self, l=0):
         return self.levels[l].nnodes

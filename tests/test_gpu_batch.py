@@ -87,7 +87,8 @@ def _mix():
 
 
 def test_batch_equals_alone():
-    """Every problem of a mixed batch gives bitwise the result it gives alone."""
+    """On the stream path every problem of a mixed batch gives bitwise the result it gives
+    alone."""
     import torch
     from paper_1402_5938_amd import gllmg
     probs, bs, alone = [], [], []
@@ -95,6 +96,7 @@ def test_batch_equals_alone():
     for k, (dim, ne, p, prec) in enumerate(_mix()):
         cfg = gllmg.make_config(dim, ne, p, "p", vcycle_prec=prec)
         P = gllmg.Problem(cfg, mp, mu)
+        P.set_persistent(False)
         f = torch.from_numpy(np.random.default_rng(100 + k).uniform(-1, 1, P.nnodes(0))).cuda()
         b = P.rhs(f)
         x = torch.zeros_like(b)
@@ -119,5 +121,85 @@ def test_batch_equals_alone():
     for k, a in enumerate(act):
         assert a.result.iters == alone[k][0].iters
         assert torch.equal(xs2[k], alone[k][1]), k
+    for P in probs:
+        P.close()
+
+
+def _persistent_set(modes=("pcg",)):
+    """3D problems with an FP32 V-cycle (the persistent solver's), with a few 2D and FP64 ones
+    mixed in (stream path, run concurrently)."""
+    return [(3, (2, 2, 2), 4, "f32", "p", 0), (3, (4, 4, 4), 2, "f32", "p", 0),
+            (3, (2, 2, 2), 8, "f32", "p", 0), (3, (2, 2, 2), 16, "f32", "p", 0),
+            (3, (4, 4, 4), 1, "f32", "p", 0), (3, (2, 2, 4), 3, "f32", "p", 0),
+            (3, (4, 2, 2), 4, "f32", "h", 0), (3, (2, 2, 2), 6, "f32", "p", 0),
+            (3, (1, 1, 1), 16, "f32", "p", 4), (3, (1, 2, 1), 12, "f32", "p", 4),
+            (2, (4, 4), 8, "f32", "p", 0), (3, (2, 2, 2), 4, "f64", "p", 0)]
+
+
+@pytest.mark.parametrize("mode", ["pcg", "mg"])
+def test_persistent_batch_matches_stream_path(mode):
+    """The persistent solver (one workgroup per problem) against gllmg_solve on the stream
+    path: equal iteration counts, status and product counts; residual histories to 1e-5 and
+    solutions to 1e-8 relative. The workgroup's FP64 dot products sum in another fixed order;
+    the resulting 1e-16 differences of the residual can round to different FP32 inputs of the
+    V-cycle, so the preconditioned iterates drift apart by FP32 rounding (seen: 3e-7 in the
+    history), bounded by the convergence to 1e-10."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
+    probs, bs, alone = [], [], []
+    for k, (dim, ne, p, prec, hier, ml) in enumerate(_persistent_set()):
+        cfg = gllmg.make_config(dim, ne, p, hier, vcycle_prec=prec, max_levels=ml)
+        P = gllmg.Problem(cfg, mp, mu)
+        f = torch.from_numpy(np.random.default_rng(300 + k).uniform(-1, 1, P.nnodes(0))).cuda()
+        b = P.rhs(f)
+        x = torch.zeros_like(b)
+        alone.append((P.solve(b, x, mode=mode, rtol=1e-10, maxit=200), x.clone()))
+        probs.append(P)
+        bs.append(b)
+    for rep in range(2):  # twice: the descriptors are refilled per call
+        xs = [torch.zeros_like(b) for b in bs]
+        res = gllmg.batch_solve(probs, bs, xs, mode=mode, rtol=1e-10, maxit=200)
+        torch.cuda.synchronize()
+        for k, (r, (ra, xa)) in enumerate(zip(res, alone)):
+            assert r.status == ra.status and r.iters == ra.iters, (k, r.iters, ra.iters)
+            assert r.converged
+            h, ha = np.array(r.history), np.array(ra.history)
+            assert np.max(np.abs(h - ha) / ha) <= 1e-5, k
+            assert torch.linalg.norm(xs[k] - xa) <= 1e-8 * torch.linalg.norm(xa), k
+            assert abs(r.relres_true - ra.relres_true) <= 1e-2 * ra.relres_true
+            assert r.applies == ra.applies, (k, r.applies, ra.applies)
+    for P in probs:
+        P.close()
+
+
+def test_persistent_batch_failures_are_per_problem():
+    """maxit reached and a NaN right-hand side end only their own problem's solve."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
+    probs, bs = [], []
+    for k in range(3):
+        cfg = gllmg.make_config(3, (2, 2, 2), 4, "p", vcycle_prec="f32")
+        P = gllmg.Problem(cfg, mp, mu)
+        b = P.rhs(torch.from_numpy(inputs.uniform_nodal(k, P.nnodes(0))).cuda())
+        if k == 1:
+            b[P.nnodes(0) // 2] = float("nan")
+        probs.append(P)
+        bs.append(b)
+    import ctypes as C
+    n = 3
+    xs = [torch.zeros_like(b) for b in bs]
+    status = (C.c_int * n)()
+    st = gllmg.lib().gllmg_batch_solve((C.c_void_p * n)(*[p.h for p in probs]),
+                                       (C.c_void_p * n)(*[b.data_ptr() for b in bs]),
+                                       (C.c_void_p * n)(*[x.data_ptr() for x in xs]),
+                                       n, gllmg.MODE_PCG, C.c_double(1e-10), 3, None, status, None)
+    torch.cuda.synchronize()
+    assert st == gllmg.EBREAKDOWN
+    assert list(status) == [gllmg.ENOTCONV, gllmg.EBREAKDOWN, gllmg.ENOTCONV]
+    res = gllmg.batch_solve([probs[0], probs[2]], [bs[0], bs[2]],
+                            [torch.zeros_like(bs[0]), torch.zeros_like(bs[2])], rtol=1e-10)
+    assert all(r.converged for r in res)
     for P in probs:
         P.close()

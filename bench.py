@@ -178,15 +178,16 @@ def workload_batch(a):
 
 
 def workload_serve(a):
-    """Poisson-arrival stream (mean 200 req/s) of mixed 2D/3D solves to 1e-8 under an HBM
-    budget; p50/p99 latency and solves/s over the first a.serve_s seconds of arrivals."""
+    """Poisson-arrival stream (mean a.serve_rate req/s, 200 by default) of mixed 2D/3D solves to
+    1e-8 under an HBM budget; p50/p99 latency and solves/s over the first a.serve_s seconds of
+    arrivals."""
     from paper_1402_5938_amd import inputs
     from paper_1402_5938_amd.serve import Server
-    trace = inputs.serving_trace(seed=0, rate=200.0, duration_s=a.serve_s)
+    trace = inputs.serving_trace(seed=0, rate=a.serve_rate, duration_s=a.serve_s)
     srv = Server(hbm_budget=int(a.hbm_gb * 2 ** 30), max_active=64)
     rep = srv.run(trace, time_scale=1.0, max_wall_s=a.serve_s * 20 + 60)
     srv.close()
-    return {"workload": f"serve: {len(trace)} requests over {a.serve_s} s at 200 req/s, "
+    return {"workload": f"serve: {len(trace)} requests over {a.serve_s} s at {a.serve_rate:g} req/s, "
                         f"budget {a.hbm_gb} GiB", **rep}
 
 
@@ -296,6 +297,7 @@ def main():
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

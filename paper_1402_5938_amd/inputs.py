@@ -101,6 +101,18 @@ class Problem:
             return uniform_nodal(self.f_seed, self.nnodes)
         return None
 
+    def nodal_rhs_device(self, device="cuda"):
+        """Served requests: nodal f ~ U[-1,1] drawn on the device (torch's counter-based
+        generator seeded with f_seed), as a client would hand over data already in GPU memory;
+        None if f is a field."""
+        import torch
+        if self.f_seed is None:
+            return None
+        g = torch.Generator(device=device)
+        g.manual_seed(self.f_seed & 0x7FFFFFFFFFFFFFFF)
+        u = torch.rand(self.nnodes, dtype=torch.float64, device=device, generator=g)
+        return u.mul_(2.0).sub_(1.0)
+
 
 def node_count(nelem, order) -> int:
     return int(np.prod([ne * order + 1 for ne in nelem]))

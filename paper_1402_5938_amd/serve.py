@@ -83,7 +83,7 @@ class Record:
 
 class Server:
     def __init__(self, hbm_budget: int, max_active: int = 64, nstreams: int = 8,
-                 keep_solutions: bool = False, setup_threads: int = 3):
+                 keep_solutions: bool = False, setup_threads: int = 6):
         import torch
         self.ledger = HbmLedger(hbm_budget)
         self.max_active = max_active
@@ -115,11 +115,9 @@ class Server:
                 with torch.cuda.stream(s):
                     P = gllmg.Problem(request_config(req.problem), req.problem.map,
                                       req.problem.mu, stream=s)
-                    fn = req.problem.nodal_rhs()
-                    if fn is None:
+                    f = req.problem.nodal_rhs_device()
+                    if f is None:
                         f = P.eval_field(req.problem.f, stream=s)
-                    else:
-                        f = torch.from_numpy(fn).to("cuda", non_blocking=False)
                     b = P.rhs(f, stream=s)
                     x = torch.zeros_like(b)
                     del f

@@ -65,7 +65,7 @@ def test_server_same_alone_and_in_mix():
     for req in trace:
         rec = srv.records[req.rid]
         P = gllmg.Problem(request_config(req.problem), req.problem.map, req.problem.mu)
-        b = P.rhs(torch.from_numpy(req.problem.nodal_rhs()).cuda())
+        b = P.rhs(req.problem.nodal_rhs_device())
         x = torch.zeros_like(b)
         res = P.solve(b, x, rtol=req.problem.rtol, maxit=req.problem.maxit)
         assert res.iters == rec.iters and res.converged

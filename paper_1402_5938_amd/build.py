@@ -23,6 +23,9 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are disabled for every HIP translation unit
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # fully unrolled element loops index their register arrays with constants only; the
+         # default size limit for a requested full unroll is too small at p = 16
+         "-mllvm", "-pragma-unroll-threshold=65536",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
 
 

@@ -99,11 +99,11 @@ __device__ __attribute__((noinline)) void b_apply_n(const BatchCtx& c, int l, co
     return;
   }
   constexpr int EPB = BEpb<N, T>::v;
-  T* sA = (T*)c.lds;
+  T* sD = (T*)c.lds;
+  T* sA = sD + N * N;
   T* sB = sA + EPB * N * N * N;
-  T* sD = sB + EPB * N * N * N;
   for (uint32_t eb = 0; eb < (uint32_t)g.E; eb += EPB) {
-    elem3d<N, T, EPB>(x, F, G, D, g, 0, eb, threadIdx.x, sA, sB, sD);
+    elem3d_any<N, T, EPB>(x, F, G, D, g, 0, eb, threadIdx.x, sA, sB, sD);
     __syncthreads();
   }
   const int nrows = (int)(g.N / g.nn[0]);

@@ -22,6 +22,13 @@ struct Epb {
   static constexpr int v = (N * N >= GLLMG_EPB_THREADS / 2) ? 1 : (GLLMG_EPB_THREADS / (N * N));
 };
 
+// An opaque use that makes the compiler compute v at this point (and not later, where it is
+// consumed, which can keep all of its operands alive meanwhile).
+template <typename T>
+__device__ __forceinline__ void pin(T& v) {
+  asm volatile("" : "+v"(v));
+}
+
 // ------------------------------------------------------------------ 3D element kernel
 // Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
 // y-contractions read the element tile from LDS, the z-contraction works in registers.
@@ -32,8 +39,11 @@ struct Waves {
 #ifndef GLLMG_APPLY_MINWAVES
 #define GLLMG_APPLY_MINWAVES 1
 #endif
-  static constexpr int min = N >= 12 ? 1 : GLLMG_APPLY_MINWAVES;
-  static constexpr int max = N >= 12 ? 2 : 8;
+#ifndef GLLMG_APPLY_MINWAVES_HP
+#define GLLMG_APPLY_MINWAVES_HP 1
+#endif
+  static constexpr int min = N >= 12 ? GLLMG_APPLY_MINWAVES_HP : GLLMG_APPLY_MINWAVES;
+  static constexpr int max = N >= 12 ? 4 : 8;
 };
 
 // One pass of the 3D element kernel over the EPB elements ebase.. by the threads t of a
@@ -132,6 +142,14 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
     wx[k] = g0 * ux + g1 * uy + g2 * uz;
     wy[k] = g1 * ux + g3 * uy + g4 * uz;
     wz[k] = g2 * ux + g4 * uy + g5 * uz;
+    // in FP64 from n = 9 on, forming the fluxes here (not at their uses after the barrier)
+    // lowers the register count from two to three waves per SIMD (measured: 3% faster at
+    // n = 9; at lower orders and in FP32 the compiler's placement is as fast or faster)
+    if constexpr (sizeof(T) == 8 && N >= 9) {
+      pin(wx[k]);
+      pin(wy[k]);
+      pin(wz[k]);
+    }
   }
   __syncthreads();
   if (act) {
@@ -161,6 +179,199 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
     }
     Fe[k * NN] = acc;
   }
+}
+
+// High orders: the same element pass arranged for a register budget of two waves per SIMD
+// (at most 256 registers per thread), where the low-order form needs more and runs one
+// workgroup per CU, with no overlap of one element's loads and another's arithmetic:
+// * the z-contraction reads the thread's own column back from LDS (no register copy of x);
+// * the x-flux goes to the second LDS tile, still unused, as soon as it is formed, the
+//   y-flux once every thread has finished reading the input tile;
+// * the contractions run in chunks of HP_CHUNK terms, software-pipelined: the LDS reads of
+//   chunk s+1 are issued before the products of chunk s, with a scheduling barrier between
+//   chunks so that the compiler does not hoist all reads of a plane (which is what fills the
+//   registers otherwise).
+// The sums are formed in the same order as in elem3d.
+// chunk length: measured best 3 in FP64 and 2 in FP32 (n = 13, 17)
+#ifndef GLLMG_HP_CHUNK
+#define GLLMG_HP_CHUNK (sizeof(T) == 8 ? 3 : 2)
+#endif
+template <int N, typename T, int EPB>
+__device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict__ F,
+                                          const T* __restrict__ G, const T* __restrict__ Dm,
+                                          const Grid& g, int neumann, uint32_t ebase, int t,
+                                          T* __restrict__ sA, T* __restrict__ sB,
+                                          T* __restrict__ sD) {
+  constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
+  constexpr int C = GLLMG_HP_CHUNK, NC = (N + C - 1) / C, S = N * NC;
+  const bool act = t < EPB * NN;
+  const int tt = act ? t : 0;
+  const int le = tt / NN;
+  const int ij = tt - le * NN;
+  const int i = ij % N, j = ij / N;
+  const uint32_t e = ebase + le;
+  const bool valid = act && e < (uint32_t)g.E;
+  const uint32_t ee = valid ? e : 0u;
+  const uint32_t nexy = (uint32_t)g.ne[0] * (uint32_t)g.ne[1];
+  const int ez = (int)(ee / nexy);
+  const uint32_t rxy = ee - (uint32_t)ez * nexy;
+  const int ey = (int)(rxy / (uint32_t)g.ne[0]);
+  const int ex = (int)(rxy - (uint32_t)ey * g.ne[0]);
+  const int gx = ex * P + i, gy = ey * P + j;
+  const bool bxy = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
+  const int64_t sxy = (int64_t)g.nn[0] * g.nn[1];
+  const int64_t gb = gx + (int64_t)g.nn[0] * gy + sxy * (int64_t)(ez * P);
+  T* A = sA + le * NNN;
+  T* B = sB + le * NNN;
+
+  // loads issued before use (all in bounds, as in elem3d): the x column, the geometric factors
+  // of the first PF planes (a ring refilled PF planes ahead) and D
+  constexpr int PF = 2;
+  const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
+  T gp[PF][6];
+#pragma unroll
+  for (int k = 0; k < PF; ++k)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
+  {
+    T xr[N];
+#pragma unroll
+    for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
+    const T dval = Dm[ij];
+    if (le == 0 && act) sD[ij] = dval;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int gz = ez * P + k;
+      const bool bnd = bxy || gz == 0 || gz == g.nn[2] - 1;
+      if (!valid || (bnd && !neumann)) xr[k] = T(0);
+      if (act) A[k * NN + ij] = xr[k];
+    }
+  }
+  __syncthreads();
+  T Di[N], Dj[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    Di[l] = sD[i * N + l];
+    Dj[l] = sD[j * N + l];
+  }
+
+  // phase 1: u = D-contractions of the tile along x, y, z; flux w = G u per node
+  T bx[2][C], by[2][C], bz[2][C], bd[2][C];
+  auto load1 = [&](int s, int buf) {
+    const int k = s / NC, c = s - (s / NC) * NC;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int l = c * C + q;
+      if (l < N) {
+        bx[buf][q] = A[k * NN + j * N + l];
+        by[buf][q] = A[k * NN + l * N + i];
+        bz[buf][q] = A[l * NN + ij];
+        bd[buf][q] = sD[k * N + l];
+      }
+    }
+  };
+  T wy[N], wz[N];
+  T ux = T(0), uy = T(0), uz = T(0);
+  load1(0, 0);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int k = s / NC, c = s - (s / NC) * NC;
+    if (s + 1 < S) load1(s + 1 < S ? s + 1 : 0, (s + 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int l = c * C + q;
+      if (l < N) {
+        ux += Di[l] * bx[s & 1][q];
+        uy += Dj[l] * by[s & 1][q];
+        uz += bd[s & 1][q] * bz[s & 1][q];
+      }
+    }
+    if (c == NC - 1) {
+      T gk[6];
+#pragma unroll
+      for (int cc = 0; cc < 6; ++cc) gk[cc] = gp[k % PF][cc];
+      if (k + PF < N) {
+#pragma unroll
+        for (int cc = 0; cc < 6; ++cc) gp[k % PF][cc] = Ge[cc * NNN + (k + PF < N ? k + PF : 0) * NN];
+      }
+      const T wx = gk[0] * ux + gk[1] * uy + gk[2] * uz;
+      wy[k] = gk[1] * ux + gk[3] * uy + gk[4] * uz;
+      wz[k] = gk[2] * ux + gk[4] * uy + gk[5] * uz;
+      // form the fluxes here: otherwise the compiler sinks them to their uses after the
+      // barrier and keeps u and the six factors of every plane alive instead
+      pin(wy[k]);
+      pin(wz[k]);
+      if (act) B[k * NN + ij] = wx;
+      ux = uy = uz = T(0);
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) A[k * NN + ij] = wy[k];
+  }
+  __syncthreads();
+  if (!valid) return;
+  T DiT[N], DjT[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    DiT[l] = sD[l * N + i];
+    DjT[l] = sD[l * N + j];
+  }
+
+  // phase 2: transposed contractions of the fluxes (x-flux in B, y-flux in A, z in registers)
+  T cx[2][C], cy[2][C], cd[2][C];
+  auto load2 = [&](int s, int buf) {
+    const int k = s / NC, c = s - (s / NC) * NC;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int l = c * C + q;
+      if (l < N) {
+        cx[buf][q] = B[k * NN + j * N + l];
+        cy[buf][q] = A[k * NN + l * N + i];
+        cd[buf][q] = sD[l * N + k];
+      }
+    }
+  };
+  T* Fe = F + (int64_t)e * NNN + ij;
+  T acc = T(0);
+  load2(0, 0);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int k = s / NC, c = s - (s / NC) * NC;
+    if (s + 1 < S) load2(s + 1 < S ? s + 1 : 0, (s + 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int l = c * C + q;
+      if (l < N) {
+        acc += DiT[l] * cx[s & 1][q];
+        acc += DjT[l] * cy[s & 1][q];
+        acc += cd[s & 1][q] * wz[l];
+      }
+    }
+    if (c == NC - 1) {
+      Fe[k * NN] = acc;
+      acc = T(0);
+    }
+  }
+}
+
+// elem3d or, from n = GLLMG_HIGHP_N on, elem3d_hp
+#ifndef GLLMG_HIGHP_N
+#define GLLMG_HIGHP_N 12
+#endif
+template <int N, typename T, int EPB>
+__device__ __forceinline__ void elem3d_any(const T* __restrict__ x, T* __restrict__ F,
+                                           const T* __restrict__ G, const T* __restrict__ Dm,
+                                           const Grid& g, int neumann, uint32_t ebase, int t,
+                                           T* __restrict__ sA, T* __restrict__ sB,
+                                           T* __restrict__ sD) {
+  if constexpr (N >= GLLMG_HIGHP_N)
+    elem3d_hp<N, T, EPB>(x, F, G, Dm, g, neumann, ebase, t, sA, sB, sD);
+  else
+    elem3d<N, T, EPB>(x, F, G, Dm, g, neumann, ebase, t, sA, sB, sD);
 }
 
 // ------------------------------------------------------------------ 2D element kernel

@@ -23,11 +23,14 @@ template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann) {
-  __shared__ T sA[EPB * N * N * N];
-  __shared__ T sB[EPB * N * N * N];
-  __shared__ T sD[N * N];
-  elem3d<N, T, EPB>(x, F, G, Dm, g, neumann, xcd_block(blockIdx.x, gridDim.x) * EPB, threadIdx.x,
-                    sA, sB, sD);
+  // one LDS array with D first: D's addresses are then small enough for the immediate offset
+  // of an LDS instruction (no address register per D entry)
+  __shared__ T lds[N * N + 2 * EPB * N * N * N];
+  T* sD = lds;
+  T* sA = lds + N * N;
+  T* sB = sA + EPB * N * N * N;
+  elem3d_any<N, T, EPB>(x, F, G, Dm, g, neumann, xcd_block(blockIdx.x, gridDim.x) * EPB, threadIdx.x,
+                        sA, sB, sD);
 }
 
 template <int N, typename T, int EPB>

@@ -25,7 +25,16 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per operator product read by the FETCH_SIZE / WRITE_SIZE counters (calibrated on a
 # plain copy kernel), with the hash of the apply kernels' source they were taken on
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_warped_16cubed_p8_hbm_traffic.txt")
-APPLY_SOURCE = os.path.join(ROOT, "paper_1402_5938_amd", "csrc", "k_apply.hip")
+# the sources the operator-product kernels are compiled from
+APPLY_SOURCES = [os.path.join(ROOT, "paper_1402_5938_amd", "csrc", f)
+                 for f in ("k_apply.hip", "dev_apply.h", "epilogue.h")]
+
+
+def apply_source_sha():
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 CALIB_COPY_BYTES = 256 * 2 ** 20
 
 
@@ -39,8 +48,7 @@ def measured_traffic(nelem, order):
         if ":" in line and not line.lstrip().startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(APPLY_SOURCE, "rb").read()).hexdigest()
-    if kv.get("k_apply_sha256") != sha or kv.get("problem") != f"{nelem}^3 hexes p={order}":
+    if kv.get("apply_sources_sha256") != apply_source_sha() or kv.get("problem") != f"{nelem}^3 hexes p={order}":
         return None
     try:
         return float(kv["hbm_bytes_per_apply"])

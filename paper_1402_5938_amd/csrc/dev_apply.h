@@ -568,58 +568,84 @@ __device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
   return k;
 }
 
-// acc = sum over the elements containing node g of F[e][local index of g], then the epilogue;
-// on the domain boundary A x = 0 (all epilogue outputs 0) unless neumann. Each wave walks one
-// grid row (fixed y, z) in chunks of 64 nodes, a workgroup holds kGR rows, so the row's
-// element candidates along y and z are uniform across the wave.
-constexpr int kGX = 64;
-constexpr int kGR = 4;
+// Sum over the elements containing node (gx, gy, gz) of F[e][local index of the node], in the
+// order z, y, x with the lower element first. Along y and z the candidates are the same for a
+// whole grid row, so those branches are uniform where a wave covers one row; along x a missing
+// second candidate re-reads the first (all loads are issued before the sum).
+template <int N, int DIM, typename T>
+__device__ __forceinline__ T gather_sum(const T* __restrict__ F, const Grid& g, int gx, int gy,
+                                        int gz) {
+  constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
+  int cex[2], clx[2], cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
+  const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+  const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
+  const int cz = DIM == 3 ? axis_cands(gz, P, g.ne[2], cez, clz) : 1;
+  T v[2][2][2];
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+      if (kz < cz && ky < cy) {
+        const int64_t eyz = (int64_t)g.ne[0] * (cey[ky] + (int64_t)g.ne[1] * cez[kz]);
+        const int lyz = N * (cly[ky] + N * clz[kz]);
+#pragma unroll
+        for (int kx = 0; kx < 2; ++kx) {
+          const int ax = kx < cx ? kx : 0;
+          v[kz][ky][kx] = F[(cex[ax] + eyz) * NL + clx[ax] + lyz];
+        }
+      }
+  T acc = T(0);
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx)
+        if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
+  return acc;
+}
 
-// Node row `row` (fixed y, z) of the gather, nodes lane, lane + nlanes, ...
+// acc = gather_sum at node t, then the epilogue; on the domain boundary A x = 0 (all epilogue
+// outputs 0) unless neumann.
+template <int N, int DIM, typename T>
+__device__ __forceinline__ void gather_at(const T* __restrict__ F, const T* __restrict__ xin,
+                                          const Grid& g, int neumann, const EpiT<T>& ep,
+                                          int64_t t, int gx, int gy, int gz) {
+  const bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1 ||
+                   (DIM == 3 && (gz == 0 || gz == g.nn[2] - 1));
+  if (bnd && !neumann) {
+    epilogue_zero(ep, t);
+    return;
+  }
+  const T acc = gather_sum<N, DIM, T>(F, g, gx, gy, gz);
+  const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
+  epilogue(ep, t, acc, xv);
+}
+
+// One node per thread in node order (t < N): consecutive threads walk a grid row, so a wave
+// covers one row or the end of one and the start of the next.
+template <int N, int DIM, typename T>
+__device__ __forceinline__ void gather_node(const T* __restrict__ F, const T* __restrict__ xin,
+                                            const Grid& g, int neumann, const EpiT<T>& ep,
+                                            uint32_t t) {
+  const uint32_t row = t / (uint32_t)g.nn[0];
+  const int gx = (int)(t - row * (uint32_t)g.nn[0]);
+  const int gz = DIM == 3 ? (int)(row / (uint32_t)g.nn[1]) : 0;
+  const int gy = DIM == 3 ? (int)(row - (uint32_t)gz * (uint32_t)g.nn[1]) : (int)row;
+  gather_at<N, DIM, T>(F, xin, g, neumann, ep, (int64_t)t, gx, gy, gz);
+}
+
+// Node row `row` (fixed y, z) of the gather, nodes lane, lane + nlanes, ... (a wave per row:
+// the y and z candidates are uniform across it).
 template <int N, int DIM, typename T>
 __device__ __forceinline__ void gather_row(const T* __restrict__ F, const T* __restrict__ xin,
                                            const Grid& g, int neumann, const EpiT<T>& ep, int row,
                                            int lane, int nlanes) {
-  constexpr int P = N - 1, NL = DIM == 3 ? N * N * N : N * N;
   const int gy = DIM == 3 ? row % g.nn[1] : row;
   const int gz = DIM == 3 ? row / g.nn[1] : 0;
-  const bool bnd_yz = gy == 0 || gy == g.nn[1] - 1 || (DIM == 3 && (gz == 0 || gz == g.nn[2] - 1));
-  int cey[2], cly[2], cez[2] = {0, 0}, clz[2] = {0, 0};
-  const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
-  const int cz = DIM == 3 ? axis_cands(gz, P, g.ne[2], cez, clz) : 1;
   const int64_t rbase = (int64_t)g.nn[0] * row;
-  for (int gx = lane; gx < g.nn[0]; gx += nlanes) {
-    const int64_t t = rbase + gx;
-    if ((bnd_yz || gx == 0 || gx == g.nn[0] - 1) && !neumann) {
-      epilogue_zero(ep, t);
-      continue;
-    }
-    int cex[2], clx[2];
-    const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
-    // up to 8 loads, all issued before the sum: missing candidates re-read candidate 0 and
-    // are skipped in the sum (the sum order is z, y, x with the lower element first)
-    T v[2][2][2];
-#pragma unroll
-    for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-      for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-        for (int kx = 0; kx < 2; ++kx) {
-          const int az = kz < cz ? kz : 0, ay = ky < cy ? ky : 0, ax = kx < cx ? kx : 0;
-          const int64_t e = cex[ax] + (int64_t)g.ne[0] * (cey[ay] + (int64_t)g.ne[1] * cez[az]);
-          v[kz][ky][kx] = F[e * NL + clx[ax] + N * (cly[ay] + N * clz[az])];
-        }
-    T acc = T(0);
-#pragma unroll
-    for (int kz = 0; kz < 2; ++kz)
-#pragma unroll
-      for (int ky = 0; ky < 2; ++ky)
-#pragma unroll
-        for (int kx = 0; kx < 2; ++kx)
-          if (kz < cz && ky < cy && kx < cx) acc += v[kz][ky][kx];
-    const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
-    epilogue(ep, t, acc, xv);
-  }
+  for (int gx = lane; gx < g.nn[0]; gx += nlanes)
+    gather_at<N, DIM, T>(F, xin, g, neumann, ep, rbase + gx, gx, gy, gz);
 }
 
 }  // namespace

@@ -50,6 +50,32 @@ k_apply_p1(const T* __restrict__ x, const T* __restrict__ G, const T* __restrict
   p1_lanes<DIM, T>(x, G, Dm, g, neumann, ep, zero, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+#ifndef GLLMG_GATHER_ROWS
+constexpr int kGT = 256;
+
+template <int N, int DIM, typename T>
+__global__ void __launch_bounds__(kGT)
+k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep) {
+  const uint32_t t = xcd_block(blockIdx.x, gridDim.x) * (uint32_t)kGT + threadIdx.x;
+  if (t >= (uint32_t)g.N) return;
+  gather_node<N, DIM, T>(F, xin, g, neumann, ep, t);
+}
+
+template <int N, typename T>
+void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
+                   hipStream_t s) {
+  GLLMG_CHECK(g.N < ((int64_t)1 << 32) - kGT, GLLMG_EUNSUPPORTED, "level too large for 32-bit node indices");
+  const dim3 grid((unsigned)((g.N + kGT - 1) / kGT)), block(kGT);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, block, 0, s, F, xin, g, neumann, ep);
+  else
+    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, block, 0, s, F, xin, g, neumann, ep);
+  GLLMG_HIP(hipGetLastError());
+}
+#else
+constexpr int kGX = 64;
+constexpr int kGR = 4;
+
 template <int N, int DIM, typename T>
 __global__ void __launch_bounds__(kGX * kGR)
 k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int nrows, int neumann,
@@ -70,6 +96,7 @@ void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const E
     hipLaunchKernelGGL((k_gather<N, 2, T>), grid, block, 0, s, F, xin, g, nrows, neumann, ep);
   GLLMG_HIP(hipGetLastError());
 }
+#endif
 
 template <typename T>
 void launch_gather_rt(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,

@@ -153,8 +153,8 @@ gllmg_status gllmg_set_lmax(gllmg_problem* prob, int32_t level, double lmax);
  * The graph is rebuilt after gllmg_set_lmax. */
 gllmg_status gllmg_set_graphs(gllmg_problem* prob, int32_t enable);
 
-/* Whether gllmg_batch_solve may solve this problem with the persistent solver (enable = 1, the
- * default) or must use the stream path (0). See gllmg_batch_solve. */
+/* Whether gllmg_batch_solve may solve this problem with the persistent solver or in a launch
+ * group (enable = 1, the default) or must give it its own stream (0). See gllmg_batch_solve. */
 gllmg_status gllmg_set_persistent(gllmg_problem* prob, int32_t enable);
 
 /* Physical node coordinates x = Phi(X) of a level: out[g * dim + a]. FP64. Asynchronous. */
@@ -231,10 +231,16 @@ gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
  * maxit < 1024, persistent mode not switched off) are solved by one persistent kernel launch
  * per finest order on `stream`, one workgroup per problem, each stopping on its own: the same
  * steps, smoothers and transfers as gllmg_solve, with the workgroup's dot products summed in
- * another fixed order (iterates agree to rounding, not bitwise). The others run on their own
- * internal streams, advanced iteration by iteration from the host thread, concurrently with
- * the persistent launch. stats and status may be
- * NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
+ * another fixed order (iterates agree to rounding, not bitwise). In PCG mode, two or more of
+ * the others that share one shape (dimension, elements, order, hierarchy, smoother, degrees and
+ * V-cycle precision; coefficients and maps may differ) form a launch group: one lockstep PCG
+ * in which every kernel is launched once for all of them, each problem leaving the launches
+ * when its own solve ends; each result equals gllmg_solve's bit for bit. A group copies b and
+ * x through level-0 workspace vectors that its solve does not use otherwise, allocates a small
+ * device and pinned buffer (a few bytes per problem) for the call, and runs on the first
+ * problem's internal stream, concurrently with the persistent launch. The remaining problems
+ * run on their own internal streams, advanced iteration by iteration from the host thread.
+ * stats and status may be NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
  * any solve starts: EINVAL). Returns GLLMG_OK if every solve converged, else the first error
  * other than ENOTCONV if any, else ENOTCONV (status[i] holds each problem's own status; a
  * problem that fails does not stop the others). */

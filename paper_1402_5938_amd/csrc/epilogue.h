@@ -29,12 +29,65 @@ struct EpiT {
   T* d;
   const T* dinv;
   T c1, c2, om;
+  const double* cc;
 };
 
 template <typename T>
 __host__ __device__ EpiT<T> typed(const Epi& e) {
   return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
-                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om};
+                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om, e.cc};
+}
+
+// ------------------------------------------------------------------ launch groups
+// pointer p of problem 0 moved to problem k (d = its byte offset); null stays null
+template <typename P>
+__device__ inline P* shift(P* p, int64_t d) {
+  return p ? (P*)((char*)p + d) : p;
+}
+
+// Problem blockIdx.y of the launch: false if it is inactive; *d = its byte offset.
+__device__ inline bool grp_begin(const Grp& g, int64_t* d) {
+  const int k = blockIdx.y;
+  if (g.act && g.act[k] == 0) return false;
+  *d = g.dlt ? g.dlt[k] : 0;
+  return true;
+}
+
+// Entry of a kernel instantiated for launch groups (GR) or for one problem (no group code at
+// all: d = 0 and nothing is read, so single-problem launches pay no latency for groups).
+template <bool GR>
+__device__ inline bool grp_enter(const Grp& g, int64_t* d) {
+  if constexpr (GR) {
+    return grp_begin(g, d);
+  } else {
+    *d = 0;
+    return true;
+  }
+}
+
+// the epilogue of problem k (offset d): its pointers and, from its table, its coefficients
+template <typename T>
+__device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
+  e.y = shift(e.y, d);
+  e.b = shift(e.b, d);
+  e.x = shift(e.x, d);
+  e.rin = shift(e.rin, d);
+  e.r = shift(e.r, d);
+  e.d = shift(e.d, d);
+  e.dinv = shift(e.dinv, d);
+  if (e.cc) {
+    const double* c = shift(e.cc, d);
+    e.c1 = (T)c[0];
+    e.c2 = (T)c[1];
+  }
+  return e;
+}
+template <bool GR, typename T>
+__device__ inline EpiT<T> shift_epi(const EpiT<T>& e, int64_t d) {
+  if constexpr (GR)
+    return shift(e, d);
+  else
+    return e;
 }
 
 // acc = (A xin)_g, xin = the input vector's value at g

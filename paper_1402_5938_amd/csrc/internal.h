@@ -1,6 +1,8 @@
 // Internal declarations of the gllmg library: level data, kernel launchers, host helpers.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -85,6 +87,8 @@ struct Level {
   const void* zero = nullptr;  // 64 zero bytes in device memory (a load source for masked lanes)
   double* Ainv64 = nullptr;
   float* Ainv32 = nullptr;
+  // Chebyshev coefficients on the device: pair 0 = (theta, delta), pair i = (c1, c2) of step i
+  double* ctab = nullptr;
   int64_t applies = 0;
 };
 
@@ -163,7 +167,42 @@ struct Epi {
   void* d = nullptr;
   const void* dinv = nullptr;
   double c1 = 0, c2 = 0, om = 0;
+  // when set: c1, c2 are read on the device from cc[0], cc[1] (per problem in a launch group)
+  const double* cc = nullptr;
 };
+
+// Launch groups: several problems of one shape in each launch (batched solves). Problem k's
+// device buffers lie at the same offsets in its workspace as problem 0's, so a kernel reaches
+// them by adding dlt[k] bytes to the pointers it was given for problem 0; act[k] == 0 skips
+// problem k. Kernels take a Grp argument ({nullptr, nullptr}: one problem) and run problem
+// blockIdx.y; launches made while a LaunchGroup is current have gridDim.y = count.
+struct Grp {
+  const int64_t* dlt;
+  const int* act;
+};
+struct LaunchGroup {
+  Grp g;
+  int count;
+};
+const LaunchGroup* launch_group();          // the current group of this thread, or nullptr
+void set_launch_group(const LaunchGroup* g);
+inline Grp cur_grp() {
+  const LaunchGroup* g = launch_group();
+  return g ? g->g : Grp{nullptr, nullptr};
+}
+inline unsigned grp_count() {
+  const LaunchGroup* g = launch_group();
+  return g ? (unsigned)g->count : 1u;
+}
+// f(std::true_type) inside a launch group, else f(std::false_type): launchers pick the kernel
+// instance with or without the group code
+template <class F>
+void with_gr(F&& f) {
+  if (launch_group())
+    f(std::true_type{});
+  else
+    f(std::false_type{});
+}
 void launch_apply(const Level& L, int prec, int neumann, const void* x, const Epi& ep, void* F,
                   hipStream_t s);
 size_t face_buffer_elems(const Level& L);
@@ -198,8 +237,10 @@ void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s);        // v = e
 void cast_64_32(int64_t n, const double* a, float* out, hipStream_t s);
 void cast_32_64(int64_t n, const float* a, double* out, hipStream_t s);
 // Chebyshev / Jacobi fused updates
+// d = dinv (b - t) / theta (r = b - t when t is given); th, when given, holds theta on the
+// device (per problem in a launch group) and replaces the argument
 void cheb_start(int prec, int64_t n, const void* b, const void* t, const void* dinv,
-                double inv_theta, void* r, void* d, hipStream_t s);
+                double theta, void* r, void* d, hipStream_t s, const double* th = nullptr);
 void cheb_step(int prec, int64_t n, int x_from_zero, void* x, const void* rin, void* r,
                const void* t, void* d, const void* dinv, double c1, double c2, hipStream_t s);
 void jacobi_step(int prec, int64_t n, int x_from_zero, void* x, const void* b, const void* t,
@@ -211,6 +252,9 @@ void dot(int prec, int64_t n, const void* a, const void* b, double* partials, do
 // scalar(s) in device memory for the PCG iteration
 void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* x, double* r,
                    const double* p, const double* h, double* partials, double* rr, hipStream_t s);
+// dst[k cnt + i] = scal[i] (src = the first problem's scalars) for every active problem k of
+// the current launch group (dst is not shifted: one buffer for the group)
+void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s);
 void pcg_update_p(int64_t n, const double* scal, int i_num, int i_den, double* p,
                   const double* z, hipStream_t s);
 void start_vector(const Grid& g, uint64_t seed, int level, double* v, hipStream_t s);

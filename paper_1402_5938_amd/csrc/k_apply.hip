@@ -19,10 +19,16 @@ namespace gllmg {
 
 namespace {
 
-template <int N, typename T, int EPB>
+template <int N, typename T, int EPB, bool GR>
 __global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
-          const T* __restrict__ Dm, Grid g, int neumann) {
+          const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  x = shift(x, dk);
+  F = shift(F, dk);
+  G = shift(G, dk);
+  Dm = shift(Dm, dk);
   // one LDS array with D first: D's addresses are then small enough for the immediate offset
   // of an LDS instruction (no address register per D entry)
   __shared__ T lds[N * N + 2 * EPB * N * N * N];
@@ -33,70 +39,62 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
                         sA, sB, sD);
 }
 
-template <int N, typename T, int EPB>
+template <int N, typename T, int EPB, bool GR>
 __global__ void __launch_bounds__(EPB * N * N)
 k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
-          const T* __restrict__ Dm, Grid g, int neumann) {
+          const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  x = shift(x, dk);
+  F = shift(F, dk);
+  G = shift(G, dk);
+  Dm = shift(Dm, dk);
   __shared__ T sA[EPB * N * N];
   __shared__ T sB[EPB * N * N];
   elem2d<N, T, EPB>(x, F, G, Dm, g, neumann, blockIdx.x * EPB, threadIdx.x, sA, sB);
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
 k_apply_p1(const T* __restrict__ x, const T* __restrict__ G, const T* __restrict__ Dm, Grid g,
-           int neumann, EpiT<T> ep, const T* __restrict__ zero) {
+           int neumann, EpiT<T> ep, const T* __restrict__ zero, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
   // 2^d N may pass 2^32
-  p1_lanes<DIM, T>(x, G, Dm, g, neumann, ep, zero, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  p1_lanes<DIM, T>(shift(x, dk), shift(G, dk), shift(Dm, dk), g, neumann, shift_epi<GR>(ep, dk),
+                   shift(zero, dk), (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-#ifndef GLLMG_GATHER_ROWS
 constexpr int kGT = 256;
 
-template <int N, int DIM, typename T>
+template <int N, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(kGT)
-k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep) {
+k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep,
+         Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
   const uint32_t t = xcd_block(blockIdx.x, gridDim.x) * (uint32_t)kGT + threadIdx.x;
   if (t >= (uint32_t)g.N) return;
-  gather_node<N, DIM, T>(F, xin, g, neumann, ep, t);
+  gather_node<N, DIM, T>(shift(F, dk), shift(xin, dk), g, neumann, shift_epi<GR>(ep, dk), t);
 }
 
 template <int N, typename T>
 void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
                    hipStream_t s) {
   GLLMG_CHECK(g.N < ((int64_t)1 << 32) - kGT, GLLMG_EUNSUPPORTED, "level too large for 32-bit node indices");
-  const dim3 grid((unsigned)((g.N + kGT - 1) / kGT)), block(kGT);
+  const dim3 grid((unsigned)((g.N + kGT - 1) / kGT), grp_count()), block(kGT);
   if (g.dim == 3)
-    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, block, 0, s, F, xin, g, neumann, ep);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_gather<N, 3, T, GR>), grid, block, 0, s, F, xin, g, neumann, ep, cur_grp());
+    });
   else
-    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, block, 0, s, F, xin, g, neumann, ep);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_gather<N, 2, T, GR>), grid, block, 0, s, F, xin, g, neumann, ep, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
-#else
-constexpr int kGX = 64;
-constexpr int kGR = 4;
-
-template <int N, int DIM, typename T>
-__global__ void __launch_bounds__(kGX * kGR)
-k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int nrows, int neumann,
-         EpiT<T> ep) {
-  const int row = (int)xcd_block(blockIdx.x, gridDim.x) * kGR + (int)threadIdx.y;
-  if (row >= nrows) return;
-  gather_row<N, DIM, T>(F, xin, g, neumann, ep, row, threadIdx.x, kGX);
-}
-
-template <int N, typename T>
-void launch_gather(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
-                   hipStream_t s) {
-  const int nrows = (int)(g.N / g.nn[0]);
-  const dim3 grid((unsigned)((nrows + kGR - 1) / kGR)), block(kGX, kGR);
-  if (g.dim == 3)
-    hipLaunchKernelGGL((k_gather<N, 3, T>), grid, block, 0, s, F, xin, g, nrows, neumann, ep);
-  else
-    hipLaunchKernelGGL((k_gather<N, 2, T>), grid, block, 0, s, F, xin, g, nrows, neumann, ep);
-  GLLMG_HIP(hipGetLastError());
-}
-#endif
 
 template <typename T>
 void launch_gather_rt(const T* F, const T* xin, const Grid& g, int neumann, const EpiT<T>& ep,
@@ -160,11 +158,17 @@ void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F
   constexpr int EPB = Epb<N>::v;
   const unsigned nb = (unsigned)((L.g.E + EPB - 1) / EPB);
   if (L.g.dim == 3)
-    hipLaunchKernelGGL((k_apply3d<N, T, EPB>), dim3(nb), dim3(EPB * N * N), 0, s, (const T*)x,
-                       (T*)F, G, D, L.g, neumann);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_apply3d<N, T, EPB, GR>), dim3(nb, grp_count()), dim3(EPB * N * N), 0, s,
+                       (const T*)x, (T*)F, G, D, L.g, neumann, cur_grp());
+    });
   else
-    hipLaunchKernelGGL((k_apply2d<N, T, EPB>), dim3(nb), dim3(EPB * N * N), 0, s, (const T*)x,
-                       (T*)F, G, D, L.g, neumann);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_apply2d<N, T, EPB, GR>), dim3(nb, grp_count()), dim3(EPB * N * N), 0, s,
+                       (const T*)x, (T*)F, G, D, L.g, neumann, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
   launch_gather<N, T>((const T*)F, (const T*)x, L.g, neumann, typed<T>(epi), s);
 }
@@ -178,11 +182,17 @@ void apply_p1(const Level& L, int neumann, const void* x, const Epi& epi, hipStr
   const int64_t lanes = L.g.N * (L.g.dim == 3 ? 8 : 4);
   const unsigned nb = (unsigned)((lanes + 255) / 256);
   if (L.g.dim == 3)
-    hipLaunchKernelGGL((k_apply_p1<3, T>), dim3(nb), dim3(256), 0, s, (const T*)x, G, D, L.g,
-                       neumann, typed<T>(epi), (const T*)L.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_apply_p1<3, T, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const T*)x, G,
+                       D, L.g, neumann, typed<T>(epi), (const T*)L.zero, cur_grp());
+    });
   else
-    hipLaunchKernelGGL((k_apply_p1<2, T>), dim3(nb), dim3(256), 0, s, (const T*)x, G, D, L.g,
-                       neumann, typed<T>(epi), (const T*)L.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_apply_p1<2, T, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const T*)x, G,
+                       D, L.g, neumann, typed<T>(epi), (const T*)L.zero, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 

@@ -26,10 +26,16 @@ namespace gllmg {
 
 namespace {
 
-template <int MF, int NCH, int DIM, typename T>
+template <int MF, int NCH, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(XEpb<MF>::v * MF * MF)
 k_prolong(const T* __restrict__ xc, T* __restrict__ xf, const T* __restrict__ Pl, Grid gf,
-          Grid gc, int add, const T* __restrict__ zero) {
+          Grid gc, int add, const T* __restrict__ zero, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  xc = shift(xc, dk);
+  xf = shift(xf, dk);
+  Pl = shift(Pl, dk);
+  zero = shift(zero, dk);
   using L = ProlongLds<MF, NCH, DIM, T>;
   __shared__ T s1[L::EPB * L::S1];
   __shared__ T s2[L::EPB * L::S2];
@@ -38,10 +44,16 @@ k_prolong(const T* __restrict__ xc, T* __restrict__ xf, const T* __restrict__ Pl
                                 threadIdx.x, s1, s2, sP);
 }
 
-template <int MF, int NCH, int DIM, typename T>
+template <int MF, int NCH, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(XEpb<MF>::v * MF * MF)
 k_restrict(const T* __restrict__ rf, T* __restrict__ R, const T* __restrict__ Pl, Grid gf,
-           Grid gc, const T* __restrict__ zero) {
+           Grid gc, const T* __restrict__ zero, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  rf = shift(rf, dk);
+  R = shift(R, dk);
+  Pl = shift(Pl, dk);
+  zero = shift(zero, dk);
   using L = RestrictLds<MF, NCH, DIM, T>;
   __shared__ T su[L::EPB * L::SU];
   __shared__ T s1[L::EPB * L::S1];
@@ -50,16 +62,20 @@ k_restrict(const T* __restrict__ rf, T* __restrict__ R, const T* __restrict__ Pl
                                  threadIdx.x, su, s1, sP);
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
-k_restrict_p1h(const T* __restrict__ rf, Grid gf, Grid gc, EpiT<T> ep) {
-  restrict_p1h_node<DIM, T>(rf, gf, gc, ep, blockIdx.x * blockDim.x + threadIdx.x);
+k_restrict_p1h(const T* __restrict__ rf, Grid gf, Grid gc, EpiT<T> ep, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  restrict_p1h_node<DIM, T>(shift(rf, dk), gf, gc, shift_epi<GR>(ep, dk), blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-template <int DIM, typename T>
+template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
-k_prolong_p1h(const T* __restrict__ xc, T* __restrict__ xf, Grid gf, Grid gc, int add) {
-  prolong_p1h_node<DIM, T>(xc, xf, gf, gc, add, blockIdx.x * blockDim.x + threadIdx.x);
+k_prolong_p1h(const T* __restrict__ xc, T* __restrict__ xf, Grid gf, Grid gc, int add, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  prolong_p1h_node<DIM, T>(shift(xc, dk), shift(xf, dk), gf, gc, add, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int MF, int NCH, typename T>
@@ -70,11 +86,17 @@ void prolong_n(const Level& F, const Level& C, const T* Pl, const T* xc, T* xf, 
   constexpr int EPB = XEpb<MF>::v;
   const unsigned nb = (unsigned)((F.g.E + EPB - 1) / EPB);
   if (F.g.dim == 3)
-    hipLaunchKernelGGL((k_prolong<MF, NCH, 3, T>), dim3(nb), dim3(EPB * MF * MF), 0, s, xc, xf, Pl,
-                       F.g, C.g, add, (const T*)F.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_prolong<MF, NCH, 3, T, GR>), dim3(nb, grp_count()), dim3(EPB * MF * MF), 0, s,
+                       xc, xf, Pl, F.g, C.g, add, (const T*)F.zero, cur_grp());
+    });
   else
-    hipLaunchKernelGGL((k_prolong<MF, NCH, 2, T>), dim3(nb), dim3(EPB * MF * MF), 0, s, xc, xf, Pl,
-                       F.g, C.g, add, (const T*)F.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_prolong<MF, NCH, 2, T, GR>), dim3(nb, grp_count()), dim3(EPB * MF * MF), 0, s,
+                       xc, xf, Pl, F.g, C.g, add, (const T*)F.zero, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 
@@ -85,11 +107,17 @@ void restrict_n(const Level& F, const Level& C, const T* Pl, const T* rf, T* R, 
   constexpr int EPB = XEpb<MF>::v;
   const unsigned nb = (unsigned)((C.g.E + EPB - 1) / EPB);
   if (F.g.dim == 3)
-    hipLaunchKernelGGL((k_restrict<MF, NCH, 3, T>), dim3(nb), dim3(EPB * MF * MF), 0, s, rf, R, Pl,
-                       F.g, C.g, (const T*)F.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_restrict<MF, NCH, 3, T, GR>), dim3(nb, grp_count()), dim3(EPB * MF * MF), 0, s,
+                       rf, R, Pl, F.g, C.g, (const T*)F.zero, cur_grp());
+    });
   else
-    hipLaunchKernelGGL((k_restrict<MF, NCH, 2, T>), dim3(nb), dim3(EPB * MF * MF), 0, s, rf, R, Pl,
-                       F.g, C.g, (const T*)F.zero);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_restrict<MF, NCH, 2, T, GR>), dim3(nb, grp_count()), dim3(EPB * MF * MF), 0, s,
+                       rf, R, Pl, F.g, C.g, (const T*)F.zero, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 
@@ -123,13 +151,25 @@ void launch_prolong(const Level& F, const Level& C, int prec, const void* xc, vo
     GLLMG_CHECK(C.n == 2 && F.g.dim == C.g.dim, GLLMG_EINVAL, "levels do not match the transfer");
     const unsigned nb = (unsigned)((F.g.N + 255) / 256);
     if (prec == 0 && F.g.dim == 3)
-      hipLaunchKernelGGL((k_prolong_p1h<3, double>), dim3(nb), dim3(256), 0, s, (const double*)xc, (double*)xf, F.g, C.g, a);
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_prolong_p1h<3, double, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const double*)xc, (double*)xf, F.g, C.g, a, cur_grp());
+      });
     else if (prec == 0)
-      hipLaunchKernelGGL((k_prolong_p1h<2, double>), dim3(nb), dim3(256), 0, s, (const double*)xc, (double*)xf, F.g, C.g, a);
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_prolong_p1h<2, double, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const double*)xc, (double*)xf, F.g, C.g, a, cur_grp());
+      });
     else if (F.g.dim == 3)
-      hipLaunchKernelGGL((k_prolong_p1h<3, float>), dim3(nb), dim3(256), 0, s, (const float*)xc, (float*)xf, F.g, C.g, a);
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_prolong_p1h<3, float, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const float*)xc, (float*)xf, F.g, C.g, a, cur_grp());
+      });
     else
-      hipLaunchKernelGGL((k_prolong_p1h<2, float>), dim3(nb), dim3(256), 0, s, (const float*)xc, (float*)xf, F.g, C.g, a);
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_prolong_p1h<2, float, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const float*)xc, (float*)xf, F.g, C.g, a, cur_grp());
+      });
     GLLMG_HIP(hipGetLastError());
     return;
   }
@@ -151,13 +191,25 @@ void launch_restrict(const Level& F, const Level& C, int prec, const void* rf, c
     GLLMG_CHECK(C.n == 2 && F.g.dim == C.g.dim, GLLMG_EINVAL, "levels do not match the transfer");
     const unsigned nb = (unsigned)((C.g.N + 255) / 256);
     if (prec == 0 && F.g.dim == 3)
-      hipLaunchKernelGGL((k_restrict_p1h<3, double>), dim3(nb), dim3(256), 0, s, (const double*)rf, F.g, C.g, typed<double>(ep));
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_restrict_p1h<3, double, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const double*)rf, F.g, C.g, typed<double>(ep), cur_grp());
+      });
     else if (prec == 0)
-      hipLaunchKernelGGL((k_restrict_p1h<2, double>), dim3(nb), dim3(256), 0, s, (const double*)rf, F.g, C.g, typed<double>(ep));
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_restrict_p1h<2, double, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const double*)rf, F.g, C.g, typed<double>(ep), cur_grp());
+      });
     else if (F.g.dim == 3)
-      hipLaunchKernelGGL((k_restrict_p1h<3, float>), dim3(nb), dim3(256), 0, s, (const float*)rf, F.g, C.g, typed<float>(ep));
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_restrict_p1h<3, float, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const float*)rf, F.g, C.g, typed<float>(ep), cur_grp());
+      });
     else
-      hipLaunchKernelGGL((k_restrict_p1h<2, float>), dim3(nb), dim3(256), 0, s, (const float*)rf, F.g, C.g, typed<float>(ep));
+      with_gr([&](auto gr) {
+        constexpr bool GR = decltype(gr)::value;
+        hipLaunchKernelGGL((k_restrict_p1h<2, float, GR>), dim3(nb, grp_count()), dim3(256), 0, s, (const float*)rf, F.g, C.g, typed<float>(ep), cur_grp());
+      });
     GLLMG_HIP(hipGetLastError());
     return;
   }

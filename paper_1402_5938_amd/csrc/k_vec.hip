@@ -1,6 +1,6 @@
 // Streaming kernels: the coarsest-level dense solve, the fused smoother updates, deterministic
 // dot products and the PCG vector updates.
-#include "internal.h"
+#include "epilogue.h"
 
 namespace gllmg {
 
@@ -12,10 +12,15 @@ inline unsigned nb(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 // ------------------------------------------------------------------ coarsest level
 // x = A_II^{-1} b on the interior nodes (dense inverse, rows in lexicographic interior order),
 // 0 on the boundary.
-template <typename T>
+template <typename T, bool GR>
 __global__ void __launch_bounds__(kT)
 k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* __restrict__ x,
-         Grid g) {
+         Grid g, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  Ainv = shift(Ainv, dk);
+  b = shift(b, dk);
+  x = shift(x, dk);
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.N) return;
   const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
@@ -38,11 +43,18 @@ k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* _
 }
 
 // ------------------------------------------------------------------ elementwise
-template <typename T> __global__ void k_copy(int64_t n, const T* a, T* o) {
+template <typename T, bool GR> __global__ void k_copy(int64_t n, const T* a, T* o, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  a = shift(a, dk);
+  o = shift(o, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = a[i];
 }
-template <typename T> __global__ void k_zero(int64_t n, T* o) {
+template <typename T, bool GR> __global__ void k_zero(int64_t n, T* o, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  o = shift(o, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = T(0);
 }
@@ -50,7 +62,11 @@ template <typename T> __global__ void k_sub(int64_t n, const T* a, const T* b, T
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = a[i] - b[i];
 }
-template <typename T> __global__ void k_axpy(int64_t n, T al, const T* x, T* y) {
+template <typename T, bool GR> __global__ void k_axpy(int64_t n, T al, const T* x, T* y, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  x = shift(x, dk);
+  y = shift(y, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = y[i] + al * x[i];
 }
@@ -58,11 +74,21 @@ template <typename T> __global__ void k_scale_mul(int64_t n, T al, const T* a, c
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = al * a[i] * b[i];
 }
-__global__ void k_c6432(int64_t n, const double* a, float* o) {
+template <bool GR>
+__global__ void k_c6432(int64_t n, const double* a, float* o, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  a = shift(a, dk);
+  o = shift(o, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = (float)a[i];
 }
-__global__ void k_c3264(int64_t n, const float* a, double* o) {
+template <bool GR>
+__global__ void k_c3264(int64_t n, const float* a, double* o, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  a = shift(a, dk);
+  o = shift(o, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = (double)a[i];
 }
@@ -89,8 +115,17 @@ __global__ void k_set_unit(int64_t n, int64_t idx, double* v) {
 }
 
 // Chebyshev start: r = b - t (t = A x; t == nullptr means x = 0 and r = b), d = dinv r / theta.
-template <typename T>
-__global__ void k_cheb_start(int64_t n, const T* b, const T* t, const T* dinv, T theta, T* r, T* d) {
+template <typename T, bool GR>
+__global__ void k_cheb_start(int64_t n, const T* b, const T* t, const T* dinv, T theta, T* r, T* d,
+                             const double* th, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  b = shift(b, dk);
+  t = shift(t, dk);
+  dinv = shift(dinv, dk);
+  r = shift(r, dk);
+  d = shift(d, dk);
+  if (GR && th) theta = (T)shift(th, dk)[0];
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T ri = b[i];
@@ -115,8 +150,15 @@ __global__ void k_cheb_step(int64_t n, int from_zero, T* x, const T* rin, T* r, 
 }
 
 // Damped Jacobi: x += (omega dinv) (b - t), or x = (omega dinv) b from a zero guess.
-template <typename T>
-__global__ void k_jacobi(int64_t n, int from_zero, T* x, const T* b, const T* t, const T* dinv, T om) {
+template <typename T, bool GR>
+__global__ void k_jacobi(int64_t n, int from_zero, T* x, const T* b, const T* t, const T* dinv, T om,
+                         Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  x = shift(x, dk);
+  b = shift(b, dk);
+  t = shift(t, dk);
+  dinv = shift(dinv, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (from_zero)
@@ -140,8 +182,14 @@ __device__ inline double block_sum(double v) {
   return sh[0];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const T* b, double* part) {
+template <typename T, bool GR>
+__global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const T* b, double* part,
+                                                     Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  a = shift(a, dk);
+  b = shift(b, dk);
+  part = shift(part, dk);
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     acc += (double)a[i] * (double)b[i];
@@ -149,7 +197,12 @@ __global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out) {
+template <bool GR>
+__global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  part = shift(part, dk);
+  out = shift(out, dk);
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += kT) acc += part[i];
   const double s = block_sum(acc);
@@ -161,10 +214,26 @@ inline int dot_grid(int64_t n) {
   return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
 }
 
+// dst[k cnt + i] = src[i] of problem k (blockIdx.y): a launch group's scalars side by side
+__global__ void k_collect(const double* src, int cnt, double* dst, Grp gp) {
+  int64_t dk;
+  if (!grp_begin(gp, &dk)) return;
+  if ((int)threadIdx.x < cnt) dst[(int64_t)blockIdx.y * cnt + threadIdx.x] = shift(src, dk)[threadIdx.x];
+}
+
 // alpha = scal[num] / scal[den]; x += alpha p; r -= alpha h; partial sums of r.r
+template <bool GR>
 __global__ void __launch_bounds__(kT)
 k_pcg_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r, const double* p,
-         const double* h, double* part) {
+         const double* h, double* part, Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  scal = shift(scal, dk);
+  x = shift(x, dk);
+  r = shift(r, dk);
+  p = shift(p, dk);
+  h = shift(h, dk);
+  part = shift(part, dk);
   const double al = scal[inum] / scal[iden];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
@@ -178,7 +247,14 @@ k_pcg_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r
 }
 
 // beta = scal[num] / scal[den]; p = z + beta p
-__global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z) {
+template <bool GR>
+__global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z,
+                        Grp gp) {
+  int64_t dk;
+  if (!grp_enter<GR>(gp, &dk)) return;
+  scal = shift(scal, dk);
+  p = shift(p, dk);
+  z = shift(z, dk);
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double be = scal[inum] / scal[iden];
@@ -190,29 +266,48 @@ __global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, doubl
 
 void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_coarse<double>, dim3(nb(L.g.N)), dim3(kT), 0, s, L.Ainv64, L.nint,
-                       (const double*)b, (double*)x, L.g);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_coarse<double, GR>), dim3(nb(L.g.N), grp_count()), dim3(kT), 0, s, L.Ainv64, L.nint,
+                       (const double*)b, (double*)x, L.g, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_coarse<float>, dim3(nb(L.g.N)), dim3(kT), 0, s, L.Ainv32, L.nint,
-                       (const float*)b, (float*)x, L.g);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_coarse<float, GR>), dim3(nb(L.g.N), grp_count()), dim3(kT), 0, s, L.Ainv32, L.nint,
+                       (const float*)b, (float*)x, L.g, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 
 void vec_copy(int prec, int64_t n, const void* a, void* o, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_copy<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)a, (double*)o);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_copy<double, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (const double*)a, (double*)o, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_copy<float>, dim3(nb(n)), dim3(kT), 0, s, n, (const float*)a, (float*)o);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_copy<float, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (const float*)a, (float*)o, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 void vec_zero(int prec, int64_t n, void* o, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_zero<double>, dim3(nb(n)), dim3(kT), 0, s, n, (double*)o);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_zero<double, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (double*)o, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_zero<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float*)o);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_zero<float, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (float*)o, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 void vec_sub(int prec, int64_t n, const void* a, const void* b, void* o, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   if (prec == 0)
     hipLaunchKernelGGL(k_sub<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)a,
                        (const double*)b, (double*)o);
@@ -223,14 +318,21 @@ void vec_sub(int prec, int64_t n, const void* a, const void* b, void* o, hipStre
 }
 void vec_axpy(int prec, int64_t n, double al, const void* x, void* y, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_axpy<double>, dim3(nb(n)), dim3(kT), 0, s, n, al, (const double*)x, (double*)y);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_axpy<double, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, al, (const double*)x, (double*)y, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_axpy<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float)al, (const float*)x,
-                       (float*)y);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_axpy<float, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (float)al, (const float*)x,
+                       (float*)y, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 void vec_scale_mul(int prec, int64_t n, double al, const void* a, const void* b, void* o,
                    hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   if (prec == 0)
     hipLaunchKernelGGL(k_scale_mul<double>, dim3(nb(n)), dim3(kT), 0, s, n, al, (const double*)a,
                        (const double*)b, (double*)o);
@@ -240,19 +342,23 @@ void vec_scale_mul(int prec, int64_t n, double al, const void* a, const void* b,
   GLLMG_HIP(hipGetLastError());
 }
 void vec_div(int64_t n, const double* a, double den, double* o, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   hipLaunchKernelGGL(k_div, dim3(nb(n)), dim3(kT), 0, s, n, a, den, o);
   GLLMG_HIP(hipGetLastError());
 }
 void vec_sqrt(int64_t n, const double* a, double* o, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   hipLaunchKernelGGL(k_sqrt, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
   GLLMG_HIP(hipGetLastError());
 }
 void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
                   hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   hipLaunchKernelGGL(k_axpy_dev, dim3(nb(n)), dim3(kT), 0, s, n, coef, sign, x, y);
   GLLMG_HIP(hipGetLastError());
 }
 void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   if (prec == 0)
     hipLaunchKernelGGL(k_recip_masked<double>, dim3(nb(n)), dim3(kT), 0, s, n, (double*)v);
   else
@@ -260,29 +366,45 @@ void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s) {
   GLLMG_HIP(hipGetLastError());
 }
 void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   hipLaunchKernelGGL(k_set_unit, dim3(nb(n)), dim3(kT), 0, s, n, idx, v);
   GLLMG_HIP(hipGetLastError());
 }
 void cast_64_32(int64_t n, const double* a, float* o, hipStream_t s) {
-  hipLaunchKernelGGL(k_c6432, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_c6432<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, o, cur_grp());
+  });
   GLLMG_HIP(hipGetLastError());
 }
 void cast_32_64(int64_t n, const float* a, double* o, hipStream_t s) {
-  hipLaunchKernelGGL(k_c3264, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_c3264<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, o, cur_grp());
+  });
   GLLMG_HIP(hipGetLastError());
 }
 void cheb_start(int prec, int64_t n, const void* b, const void* t, const void* dinv, double theta,
-                void* r, void* d, hipStream_t s) {
+                void* r, void* d, hipStream_t s, const double* th) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_cheb_start<double>, dim3(nb(n)), dim3(kT), 0, s, n, (const double*)b,
-                       (const double*)t, (const double*)dinv, theta, (double*)r, (double*)d);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_cheb_start<double, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (const double*)b,
+                       (const double*)t, (const double*)dinv, theta, (double*)r, (double*)d, th,
+                       cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_cheb_start<float>, dim3(nb(n)), dim3(kT), 0, s, n, (const float*)b,
-                       (const float*)t, (const float*)dinv, (float)theta, (float*)r, (float*)d);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_cheb_start<float, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, (const float*)b,
+                       (const float*)t, (const float*)dinv, (float)theta, (float*)r, (float*)d, th,
+                       cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 void cheb_step(int prec, int64_t n, int from_zero, void* x, const void* rin, void* r, const void* t,
                void* d, const void* dinv, double c1, double c2, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   if (prec == 0)
     hipLaunchKernelGGL(k_cheb_step<double>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (double*)x,
                        (const double*)rin, (double*)r, (const double*)t, (double*)d,
@@ -296,37 +418,66 @@ void cheb_step(int prec, int64_t n, int from_zero, void* x, const void* rin, voi
 void jacobi_step(int prec, int64_t n, int from_zero, void* x, const void* b, const void* t,
                  const void* dinv, double om, hipStream_t s) {
   if (prec == 0)
-    hipLaunchKernelGGL(k_jacobi<double>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (double*)x,
-                       (const double*)b, (const double*)t, (const double*)dinv, om);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_jacobi<double, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, from_zero, (double*)x,
+                       (const double*)b, (const double*)t, (const double*)dinv, om, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_jacobi<float>, dim3(nb(n)), dim3(kT), 0, s, n, from_zero, (float*)x,
-                       (const float*)b, (const float*)t, (const float*)dinv, (float)om);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_jacobi<float, GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, from_zero, (float*)x,
+                       (const float*)b, (const float*)t, (const float*)dinv, (float)om, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
 }
 void dot(int prec, int64_t n, const void* a, const void* b, double* part, double* res,
          hipStream_t s) {
   const int g = dot_grid(n);
   if (prec == 0)
-    hipLaunchKernelGGL(k_dot_partial<double>, dim3(g), dim3(kT), 0, s, n, (const double*)a,
-                       (const double*)b, part);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_dot_partial<double, GR>), dim3(g, grp_count()), dim3(kT), 0, s, n, (const double*)a,
+                       (const double*)b, part, cur_grp());
+    });
   else
-    hipLaunchKernelGGL(k_dot_partial<float>, dim3(g), dim3(kT), 0, s, n, (const float*)a,
-                       (const float*)b, part);
+    with_gr([&](auto gr) {
+      constexpr bool GR = decltype(gr)::value;
+      hipLaunchKernelGGL((k_dot_partial<float, GR>), dim3(g, grp_count()), dim3(kT), 0, s, n, (const float*)a,
+                       (const float*)b, part, cur_grp());
+    });
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kT), 0, s, (const double*)part, g, res);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, res, cur_grp());
+  });
   GLLMG_HIP(hipGetLastError());
 }
 void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r,
                    const double* p, const double* h, double* part, double* rr, hipStream_t s) {
   const int g = dot_grid(n);
-  hipLaunchKernelGGL(k_pcg_xr, dim3(g), dim3(kT), 0, s, n, scal, inum, iden, x, r, p, h, part);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_pcg_xr<GR>), dim3(g, grp_count()), dim3(kT), 0, s, n, scal, inum, iden, x, r, p, h, part, cur_grp());
+  });
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kT), 0, s, (const double*)part, g, rr);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, rr, cur_grp());
+  });
+  GLLMG_HIP(hipGetLastError());
+}
+void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s) {
+  GLLMG_CHECK(cnt >= 1 && cnt <= 64, GLLMG_EINVAL, "scalar count out of range");
+  hipLaunchKernelGGL(k_collect, dim3(1, grp_count()), dim3(64), 0, s, src, cnt, dst, cur_grp());
   GLLMG_HIP(hipGetLastError());
 }
 void pcg_update_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z,
                   hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_p, dim3(nb(n)), dim3(kT), 0, s, n, scal, inum, iden, p, z);
+  with_gr([&](auto gr) {
+    constexpr bool GR = decltype(gr)::value;
+    hipLaunchKernelGGL((k_pcg_p<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, scal, inum, iden, p, z, cur_grp());
+  });
   GLLMG_HIP(hipGetLastError());
 }
 

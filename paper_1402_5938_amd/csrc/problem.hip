@@ -154,6 +154,9 @@ struct gllmg_problem {
 namespace gllmg {
 namespace {
 
+// pairs in a level's Chebyshev coefficient table: (theta, delta) and steps 1 .. k - 1
+inline int ctab_pairs(const gllmg_config& c) { return std::max(std::max(c.nu_pre, c.nu_post), 1) + 1; }
+
 // Lay out (or only size) the whole device footprint.
 size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const gllmg_config& c = P->cfg;
@@ -175,6 +178,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
     L.w64 = (double*)A.take(sizeof(double) * n);
     L.G64 = (double*)A.take(sizeof(double) * L.npts * L.ncomp);
     L.G32 = f32 ? (float*)A.take(sizeof(float) * L.npts * L.ncomp) : nullptr;
+    L.ctab = (double*)A.take(sizeof(double) * 2 * ctab_pairs(c));
     L.dinv64 = (double*)A.take(sizeof(double) * L.g.N);
     L.dinv32 = f32 ? (float*)A.take(sizeof(float) * L.g.N) : nullptr;
     face = std::max(face, face_buffer_elems(L));
@@ -455,6 +459,31 @@ void cheb_interval(const gllmg_problem* P, const Level& L, double* theta, double
   *delta = 0.5 * (lam - alpha);
 }
 
+// The Chebyshev coefficients of every level as smooth_impl forms them, into the levels'
+// device tables (read by launch groups). Stream-ordered on s (never the legacy stream, which
+// would conflict with another thread's graph capture) and complete on return.
+void fill_ctab(gllmg_problem* P, hipStream_t s) {
+  const int np = ctab_pairs(P->cfg);
+  std::vector<double> t(2 * (size_t)np);
+  for (auto& L : P->L) {
+    double theta, delta;
+    cheb_interval(P, L, &theta, &delta);
+    std::fill(t.begin(), t.end(), 0.0);
+    t[0] = theta;
+    t[1] = delta;
+    const double sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int i = 1; i < np; ++i) {
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      t[2 * i] = rn * rho;
+      t[2 * i + 1] = 2.0 * rn / delta;
+      rho = rn;
+    }
+    GLLMG_HIP(hipMemcpyAsync(L.ctab, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+  }
+}
+
 // k smoothing steps on level l. zero: x starts at 0 (not read). started (with zero): the first
 // step from x = 0 has been done already by the restriction's epilogue (Jacobi: x written;
 // Chebyshev: d = dinv b / theta written).
@@ -489,11 +518,14 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   // Chebyshev acceleration of Jacobi on [cheb_lo lambda, lambda] (Saad, Alg. 12.1 with D^{-1})
   double theta, delta;
   cheb_interval(P, L, &theta, &delta);
+  // in a launch group each problem takes its own coefficients from its table (same values as
+  // computed here for the first problem, from each problem's lambda_max)
+  const bool grp = launch_group() != nullptr;
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
   const void* rin;
   if (zero) {
-    if (!started) cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s);  // d = dinv b / theta
+    if (!started) cheb_start(pr, N, b, nullptr, dinv, theta, r, d, s, grp ? L.ctab : nullptr);  // d = dinv b / theta
     rin = b;
   } else {
     Epi ep;  // r = b - A x, d = dinv r / theta
@@ -503,6 +535,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
     ep.d = d;
     ep.dinv = dinv;
     ep.c1 = theta;
+    if (grp) ep.cc = L.ctab;
     apply_epi(P, l, pr, 0, x, ep, s);
     rin = r;
   }
@@ -521,6 +554,7 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
       ep.dinv = dinv;
       ep.c1 = rn * rho;
       ep.c2 = 2.0 * rn / delta;
+      if (grp) ep.cc = L.ctab + 2 * i;
       apply_epi(P, l, pr, 0, d, ep, s);
       std::swap(d, d2);
       rin = r;
@@ -563,6 +597,7 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
     ep.d = C.vd[pr];
     ep.dinv = dinv_of(C, pr);
     ep.c1 = theta;
+    if (launch_group()) ep.cc = C.ctab;
   }
   launch_restrict(L, C, pr, L.vr[pr], ep, P->F, s);
   vcycle_level(P, l + 1, pr, C.vb[pr], C.vx[pr], s, fuse);
@@ -873,6 +908,205 @@ void batch_fill(const gllmg_problem* P, BatchProblem& d) {
   }
 }
 
+thread_local const LaunchGroup* g_launch_group = nullptr;
+
+// ------------------------------------------------------------------ launch groups of a batch
+// Problems that a launch group can take together: the same levels, smoother and V-cycle
+// precision, and every device buffer at the same offset in its workspace (the layout is a
+// function of the configuration, so equal configurations give equal offsets).
+bool same_shape(const gllmg_problem* A, const gllmg_problem* B) {
+  const gllmg_config &a = A->cfg, &b = B->cfg;
+  if (a.dim != b.dim || a.smoother != b.smoother || a.nu_pre != b.nu_pre ||
+      a.nu_post != b.nu_post || a.omega != b.omega || A->vprec != B->vprec ||
+      A->L.size() != B->L.size())
+    return false;
+  auto collect = [](const gllmg_problem* P, std::vector<int64_t>& o) {
+    auto off = [P](const void* q) { return q ? (int64_t)((const char*)q - P->ws) : (int64_t)-1; };
+    for (const auto& L : P->L) {
+      o.insert(o.end(), {L.g.ne[0], L.g.ne[1], L.g.ne[2], L.g.p, (int64_t)L.has_coarse,
+                         (int64_t)L.tp.nch, off(L.G64), off(L.G32), off(L.D64), off(L.D32),
+                         off(L.dinv64), off(L.dinv32), off(L.tp.P64), off(L.tp.P32), off(L.Ainv64),
+                         off(L.Ainv32), off(L.ctab), off(L.zero)});
+      for (int q = 0; q < 2; ++q)
+        o.insert(o.end(), {off(L.vb[q]), off(L.vx[q]), off(L.vr[q]), off(L.vd[q]), off(L.vd2[q])});
+    }
+    o.insert(o.end(), {off(P->F), off(P->scal), off(P->part), off(P->pr), off(P->pz), off(P->pp),
+                       off(P->ph), off(P->pt), off(P->zeros)});
+  };
+  std::vector<int64_t> oa, ob;
+  collect(A, oa);
+  collect(B, ob);
+  return oa == ob;
+}
+
+// Result of one problem of a group solve.
+struct GroupOut {
+  int iters = 0;
+  bool conv = false, breakdown = false;
+  double n0 = 0, nr = 0, rt = 0;
+  std::vector<double> hist;
+};
+
+// Device and pinned buffers of one group solve.
+struct GroupMem {
+  int64_t* dlt = nullptr;
+  int* act = nullptr;
+  double* sc = nullptr;
+  int* hact = nullptr;
+  double* hsc = nullptr;
+  ~GroupMem() {
+    if (dlt) (void)hipFree(dlt);
+    if (act) (void)hipFree(act);
+    if (sc) (void)hipFree(sc);
+    if (hact) (void)hipHostFree(hact);
+    if (hsc) (void)hipHostFree(hsc);
+  }
+};
+
+// Makes a launch group current for this thread while it lives.
+struct GroupScope {
+  explicit GroupScope(const LaunchGroup* g) { set_launch_group(g); }
+  ~GroupScope() { set_launch_group(nullptr); }
+};
+
+// PCG (Alg. 1 of the paper with the V-cycle preconditioner) on K problems of one shape in
+// lockstep: every kernel of an iteration runs once for all problems still iterating (a
+// problem leaves the launches when it has converged, broken down or reached maxit). Each
+// problem follows exactly the arithmetic of its own solve (same kernels, same reduction
+// trees), so the results equal gllmg_solve's bit for bit. Synchronous on s.
+void group_alloc(GroupMem& m, int K) {
+  GLLMG_HIP(hipMalloc((void**)&m.dlt, sizeof(int64_t) * K));
+  GLLMG_HIP(hipMalloc((void**)&m.act, sizeof(int) * K));
+  GLLMG_HIP(hipMalloc((void**)&m.sc, sizeof(double) * 4 * K));
+  GLLMG_HIP(hipHostMalloc((void**)&m.hact, sizeof(int) * K, hipHostMallocDefault));
+  GLLMG_HIP(hipHostMalloc((void**)&m.hsc, sizeof(double) * 4 * K, hipHostMallocDefault));
+}
+
+// m: buffers from group_alloc for G.size() problems
+void group_solve(const std::vector<gllmg_problem*>& G, const std::vector<const double*>& bu,
+                 const std::vector<double*>& xu, double rtol, int maxit, hipStream_t s,
+                 GroupMem& m, std::vector<GroupOut>& out) {
+  const int K = (int)G.size();
+  gllmg_problem* P0 = G[0];
+  const int64_t N = P0->L[0].g.N;
+  std::vector<int64_t> hd(K);
+  for (int k = 0; k < K; ++k) hd[k] = G[k]->ws - P0->ws;
+  GLLMG_HIP(hipMemcpyAsync(m.dlt, hd.data(), sizeof(int64_t) * K, hipMemcpyHostToDevice, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+  // b and x in workspace vectors unused by the FP64 solve on level 0 (every buffer a group
+  // kernel touches must lie in the workspaces)
+  double* bw = (double*)P0->L[0].vb[0];
+  double* xw = (double*)P0->L[0].vx[0];
+  for (int k = 0; k < K; ++k) {
+    GLLMG_HIP(hipMemcpyAsync((char*)bw + hd[k], bu[k], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+    GLLMG_HIP(hipMemcpyAsync((char*)xw + hd[k], xu[k], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  }
+  out.assign(K, GroupOut{});
+  std::vector<char> on(K, 1);
+  auto any = [](const std::vector<char>& v) { return std::find(v.begin(), v.end(), 1) != v.end(); };
+  {
+    const LaunchGroup lg{{m.dlt, m.act}, K};
+    GroupScope scope(&lg);
+    auto set_act = [&](const std::vector<char>& a) {
+      GLLMG_HIP(hipStreamSynchronize(s));  // the pinned image is no longer being read
+      for (int k = 0; k < K; ++k) m.hact[k] = a[k];
+      GLLMG_HIP(hipMemcpyAsync(m.act, m.hact, sizeof(int) * K, hipMemcpyHostToDevice, s));
+    };
+    auto collect = [&](int src, int cnt) {
+      collect_scalars(P0->scal + src, cnt, m.sc, s);
+      GLLMG_HIP(hipMemcpyAsync(m.hsc, m.sc, sizeof(double) * cnt * K, hipMemcpyDeviceToHost, s));
+      GLLMG_HIP(hipStreamSynchronize(s));
+    };
+    // the first problem's product counters advance once per launch; each phase's count goes
+    // to the problems that took part in it
+    std::vector<int64_t> c0(P0->L.size());
+    auto mark = [&]() {
+      for (size_t l = 0; l < P0->L.size(); ++l) c0[l] = P0->L[l].applies;
+    };
+    auto credit = [&](const std::vector<char>& who) {
+      for (size_t l = 0; l < P0->L.size(); ++l) {
+        const int64_t d = P0->L[l].applies - c0[l];
+        P0->L[l].applies = c0[l];
+        for (int k = 0; k < K; ++k)
+          if (who[k]) G[k]->L[l].applies += d;
+      }
+    };
+    set_act(on);
+    mark();
+    residual(P0, 0, 0, bw, xw, P0->pr, s);
+    dot(0, N, P0->pr, P0->pr, P0->part, P0->scal + S_RR, s);
+    credit(on);
+    collect(S_RR, 1);
+    for (int k = 0; k < K; ++k) {
+      GroupOut& o = out[k];
+      o.n0 = o.nr = std::sqrt(m.hsc[k]);
+      o.hist.assign(1, o.n0);
+      o.conv = o.n0 == 0.0;
+      o.breakdown = !std::isfinite(o.n0);
+      if (o.conv || o.breakdown) on[k] = 0;
+    }
+    int g = S_G0;
+    if (any(on)) {
+      set_act(on);
+      mark();
+      precond_eager(P0, P0->pr, P0->pz, s);
+      dot(0, N, P0->pz, P0->pr, P0->part, P0->scal + S_G0, s);
+      vec_copy(0, N, P0->pz, P0->pp, s);
+      credit(on);
+    }
+    while (any(on)) {
+      mark();
+      apply_level(P0, 0, 0, 0, P0->pp, P0->ph, s);
+      dot(0, N, P0->pp, P0->ph, P0->part, P0->scal + S_PH, s);
+      pcg_update_xr(N, P0->scal, g, S_PH, xw, P0->pr, P0->pp, P0->ph, P0->part, P0->scal + S_RR, s);
+      credit(on);
+      collect(S_RR, 2);
+      for (int k = 0; k < K; ++k) {
+        if (!on[k]) continue;
+        GroupOut& o = out[k];
+        const double rr = m.hsc[2 * k], ph = m.hsc[2 * k + 1];
+        ++o.iters;
+        o.nr = std::sqrt(rr);
+        o.hist.push_back(o.nr);
+        if (!(ph > 0.0) || !std::isfinite(o.nr)) {
+          o.breakdown = true;
+          on[k] = 0;
+        } else if (o.nr <= rtol * o.n0) {
+          o.conv = true;
+          on[k] = 0;
+        } else if (o.iters >= maxit) {
+          on[k] = 0;
+        }
+      }
+      if (!any(on)) break;
+      set_act(on);
+      mark();
+      precond_eager(P0, P0->pr, P0->pz, s);
+      const int gn = g == S_G0 ? S_G1 : S_G0;
+      dot(0, N, P0->pz, P0->pr, P0->part, P0->scal + gn, s);
+      pcg_update_p(N, P0->scal, gn, g, P0->pp, P0->pz, s);
+      credit(on);
+      g = gn;
+    }
+    // the true residual b - A x of every problem with a finite, nonzero initial residual
+    std::vector<char> fin(K);
+    for (int k = 0; k < K; ++k) fin[k] = out[k].n0 > 0.0 && std::isfinite(out[k].n0);
+    if (any(fin)) {
+      set_act(fin);
+      mark();
+      residual(P0, 0, 0, bw, xw, P0->pt, s);
+      dot(0, N, P0->pt, P0->pt, P0->part, P0->scal + S_B, s);
+      credit(fin);
+      collect(S_B, 1);
+      for (int k = 0; k < K; ++k)
+        if (fin[k]) out[k].rt = std::sqrt(m.hsc[k]) / out[k].n0;
+    }
+  }
+  for (int k = 0; k < K; ++k)
+    GLLMG_HIP(hipMemcpyAsync(xu[k], (char*)xw + hd[k], sizeof(double) * N, hipMemcpyDeviceToDevice, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+}
+
 thread_local std::string g_err;
 
 template <class Fn>
@@ -911,6 +1145,10 @@ void check_ptr(const void* p, size_t align, const char* what) {
 }
 
 }  // namespace
+
+const LaunchGroup* launch_group() { return g_launch_group; }
+void set_launch_group(const LaunchGroup* g) { g_launch_group = g; }
+
 }  // namespace gllmg
 
 extern "C" {
@@ -996,6 +1234,7 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
     GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
     GLLMG_HIP(hipHostMalloc((void**)&P->bhost, sizeof(BatchProblem), hipHostMallocDefault));
     setup_impl(P.get(), map, mu, s);
+    fill_ctab(P.get(), s);
     if (P->L.back().Ainv64) {
       // capture the solve's V-cycle now, while nothing else of this problem is in flight
       try {
@@ -1054,6 +1293,8 @@ gllmg_status gllmg_set_lmax(gllmg_problem* P, int32_t level, double lmax) {
     GLLMG_CHECK(lmax > 0.0 && std::isfinite(lmax), GLLMG_EINVAL, "lmax must be positive");
     P->L[level].lmax = lmax;
     drop_graph(P);  // the captured V-cycle holds the old Chebyshev coefficients
+    if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
+    fill_ctab(P, P->xs);
     return GLLMG_OK;
   });
 }
@@ -1281,6 +1522,33 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       pers[i] = 1;
       groups[P->L[0].n].push_back(i);
     }
+    // problems of one shape (two or more, not taken by the persistent solver): solved in
+    // lockstep by launch groups, one group at a time on the first problem's internal stream
+    // (overlapping the persistent launches); their buffers are allocated before any launch
+    std::vector<std::vector<int>> shapes;
+    if (args_ok && mode == GLLMG_MODE_PCG) {
+      for (int i = 0; i < count; ++i) {
+        gllmg_problem* P = probs[i];
+        if (pers[i] || P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
+        if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
+        bool placed = false;
+        for (auto& sh : shapes)
+          if (same_shape(probs[sh[0]], P)) {
+            sh.push_back(i);
+            placed = true;
+            break;
+          }
+        if (!placed) shapes.push_back({i});
+      }
+      shapes.erase(std::remove_if(shapes.begin(), shapes.end(),
+                                  [](const std::vector<int>& v) { return v.size() < 2; }),
+                   shapes.end());
+    }
+    std::vector<std::unique_ptr<GroupMem>> gmem;
+    for (const auto& sh : shapes) {
+      gmem.emplace_back(new GroupMem);
+      group_alloc(*gmem.back(), (int)sh.size());
+    }
     for (int n0 = 2; n0 <= 17; ++n0) {
       const auto& idx = groups[n0];
       for (size_t c0 = 0; c0 < idx.size(); c0 += kBatchMaxProbs) {
@@ -1311,9 +1579,62 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
                                      sizeof(double) * (size_t)(maxit + 1),
                                  hipMemcpyDeviceToHost, cs));
       }
+    std::vector<char> grouped(count, 0);
+    std::vector<hipStream_t> gstreams;
+    for (size_t q = 0; q < shapes.size(); ++q) {
+      const auto& sh = shapes[q];
+      {
+        gllmg_problem* P0 = probs[sh[0]];
+        if (!P0->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P0->xs, hipStreamNonBlocking));
+        GLLMG_HIP(hipStreamWaitEvent(P0->xs, start, 0));
+        std::vector<gllmg_problem*> G;
+        std::vector<const double*> gb;
+        std::vector<double*> gx;
+        std::vector<std::vector<int64_t>> a0;
+        for (int i : sh) {
+          G.push_back(probs[i]);
+          gb.push_back(b[i]);
+          gx.push_back(x[i]);
+          a0.emplace_back();
+          for (auto& L : probs[i]->L) a0.back().push_back(L.applies);
+        }
+        std::vector<GroupOut> res;
+        group_solve(G, gb, gx, rtol, maxit, P0->xs, *gmem[q], res);
+        gstreams.push_back(P0->xs);
+        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (size_t k = 0; k < sh.size(); ++k) {
+          const int i = sh[k];
+          grouped[i] = 1;
+          const GroupOut& o = res[k];
+          if (stats) {
+            gllmg_solve_stats& st = stats[i];
+            st.iters = o.iters;
+            st.converged = o.conv ? 1 : 0;
+            st.relres = o.n0 > 0.0 ? o.nr / o.n0 : 0.0;
+            st.relres_true = o.rt;
+            st.t_solve_s = el;
+            for (int l = 0; l < 16; ++l)
+              st.applies[l] = l < (int)G[k]->L.size() ? G[k]->L[l].applies - a0[k][l] : 0;
+            if (st.history)
+              for (size_t j = 0; j < o.hist.size() && j <= (size_t)maxit; ++j) st.history[j] = o.hist[j];
+          }
+          const gllmg_status si = o.breakdown ? GLLMG_EBREAKDOWN : (o.conv ? GLLMG_OK : GLLMG_ENOTCONV);
+          if (status) status[i] = si;
+          if (si != GLLMG_OK) fail(i, si);
+          if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
+        }
+      }
+    }
+    for (hipStream_t gs : gstreams) {
+      hipEvent_t e = nullptr;
+      GLLMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      GLLMG_HIP(hipEventRecord(e, gs));
+      GLLMG_HIP(hipStreamWaitEvent(cs, e, 0));
+      (void)hipEventDestroy(e);
+    }
     // the others: their own streams, iteration-level interleaving
     for (int i = 0; i < count; ++i) {
-      if (pers[i]) continue;
+      if (pers[i] || grouped[i]) continue;
       gllmg_problem* P = probs[i];
       if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
       GLLMG_HIP(hipStreamWaitEvent(P->xs, start, 0));

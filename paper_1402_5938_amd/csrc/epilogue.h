@@ -53,18 +53,6 @@ __device__ inline bool grp_begin(const Grp& g, int64_t* d) {
   return true;
 }
 
-// Entry of a kernel instantiated for launch groups (GR) or for one problem (no group code at
-// all: d = 0 and nothing is read, so single-problem launches pay no latency for groups).
-template <bool GR>
-__device__ inline bool grp_enter(const Grp& g, int64_t* d) {
-  if constexpr (GR) {
-    return grp_begin(g, d);
-  } else {
-    *d = 0;
-    return true;
-  }
-}
-
 // the epilogue of problem k (offset d): its pointers and, from its table, its coefficients
 template <typename T>
 __device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
@@ -81,13 +69,6 @@ __device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
     e.c2 = (T)c[1];
   }
   return e;
-}
-template <bool GR, typename T>
-__device__ inline EpiT<T> shift_epi(const EpiT<T>& e, int64_t d) {
-  if constexpr (GR)
-    return shift(e, d);
-  else
-    return e;
 }
 
 // acc = (A xin)_g, xin = the input vector's value at g

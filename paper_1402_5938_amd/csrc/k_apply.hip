@@ -23,12 +23,14 @@ template <int N, typename T, int EPB, bool GR>
 __global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  x = shift(x, dk);
-  F = shift(F, dk);
-  G = shift(G, dk);
-  Dm = shift(Dm, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    x = shift(x, dk);
+    F = shift(F, dk);
+    G = shift(G, dk);
+    Dm = shift(Dm, dk);
+  }
   // one LDS array with D first: D's addresses are then small enough for the immediate offset
   // of an LDS instruction (no address register per D entry)
   __shared__ T lds[N * N + 2 * EPB * N * N * N];
@@ -43,12 +45,14 @@ template <int N, typename T, int EPB, bool GR>
 __global__ void __launch_bounds__(EPB * N * N)
 k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  x = shift(x, dk);
-  F = shift(F, dk);
-  G = shift(G, dk);
-  Dm = shift(Dm, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    x = shift(x, dk);
+    F = shift(F, dk);
+    G = shift(G, dk);
+    Dm = shift(Dm, dk);
+  }
   __shared__ T sA[EPB * N * N];
   __shared__ T sB[EPB * N * N];
   elem2d<N, T, EPB>(x, F, G, Dm, g, neumann, blockIdx.x * EPB, threadIdx.x, sA, sB);
@@ -58,11 +62,17 @@ template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
 k_apply_p1(const T* __restrict__ x, const T* __restrict__ G, const T* __restrict__ Dm, Grid g,
            int neumann, EpiT<T> ep, const T* __restrict__ zero, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    x = shift(x, dk);
+    G = shift(G, dk);
+    Dm = shift(Dm, dk);
+    ep = shift(ep, dk);
+    zero = shift(zero, dk);
+  }
   // 2^d N may pass 2^32
-  p1_lanes<DIM, T>(shift(x, dk), shift(G, dk), shift(Dm, dk), g, neumann, shift_epi<GR>(ep, dk),
-                   shift(zero, dk), (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  p1_lanes<DIM, T>(x, G, Dm, g, neumann, ep, zero, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 constexpr int kGT = 256;
@@ -71,11 +81,16 @@ template <int N, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(kGT)
 k_gather(const T* __restrict__ F, const T* __restrict__ xin, Grid g, int neumann, EpiT<T> ep,
          Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    F = shift(F, dk);
+    xin = shift(xin, dk);
+    ep = shift(ep, dk);
+  }
   const uint32_t t = xcd_block(blockIdx.x, gridDim.x) * (uint32_t)kGT + threadIdx.x;
   if (t >= (uint32_t)g.N) return;
-  gather_node<N, DIM, T>(shift(F, dk), shift(xin, dk), g, neumann, shift_epi<GR>(ep, dk), t);
+  gather_node<N, DIM, T>(F, xin, g, neumann, ep, t);
 }
 
 template <int N, typename T>

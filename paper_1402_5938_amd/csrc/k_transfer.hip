@@ -30,12 +30,14 @@ template <int MF, int NCH, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(XEpb<MF>::v * MF * MF)
 k_prolong(const T* __restrict__ xc, T* __restrict__ xf, const T* __restrict__ Pl, Grid gf,
           Grid gc, int add, const T* __restrict__ zero, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  xc = shift(xc, dk);
-  xf = shift(xf, dk);
-  Pl = shift(Pl, dk);
-  zero = shift(zero, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    xc = shift(xc, dk);
+    xf = shift(xf, dk);
+    Pl = shift(Pl, dk);
+    zero = shift(zero, dk);
+  }
   using L = ProlongLds<MF, NCH, DIM, T>;
   __shared__ T s1[L::EPB * L::S1];
   __shared__ T s2[L::EPB * L::S2];
@@ -48,12 +50,14 @@ template <int MF, int NCH, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(XEpb<MF>::v * MF * MF)
 k_restrict(const T* __restrict__ rf, T* __restrict__ R, const T* __restrict__ Pl, Grid gf,
            Grid gc, const T* __restrict__ zero, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  rf = shift(rf, dk);
-  R = shift(R, dk);
-  Pl = shift(Pl, dk);
-  zero = shift(zero, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    rf = shift(rf, dk);
+    R = shift(R, dk);
+    Pl = shift(Pl, dk);
+    zero = shift(zero, dk);
+  }
   using L = RestrictLds<MF, NCH, DIM, T>;
   __shared__ T su[L::EPB * L::SU];
   __shared__ T s1[L::EPB * L::S1];
@@ -65,17 +69,25 @@ k_restrict(const T* __restrict__ rf, T* __restrict__ R, const T* __restrict__ Pl
 template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
 k_restrict_p1h(const T* __restrict__ rf, Grid gf, Grid gc, EpiT<T> ep, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  restrict_p1h_node<DIM, T>(shift(rf, dk), gf, gc, shift_epi<GR>(ep, dk), blockIdx.x * blockDim.x + threadIdx.x);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    rf = shift(rf, dk);
+    ep = shift(ep, dk);
+  }
+  restrict_p1h_node<DIM, T>(rf, gf, gc, ep, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(256)
 k_prolong_p1h(const T* __restrict__ xc, T* __restrict__ xf, Grid gf, Grid gc, int add, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  prolong_p1h_node<DIM, T>(shift(xc, dk), shift(xf, dk), gf, gc, add, blockIdx.x * blockDim.x + threadIdx.x);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    xc = shift(xc, dk);
+    xf = shift(xf, dk);
+  }
+  prolong_p1h_node<DIM, T>(xc, xf, gf, gc, add, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 template <int MF, int NCH, typename T>

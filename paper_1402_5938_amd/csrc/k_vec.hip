@@ -16,11 +16,13 @@ template <typename T, bool GR>
 __global__ void __launch_bounds__(kT)
 k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* __restrict__ x,
          Grid g, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  Ainv = shift(Ainv, dk);
-  b = shift(b, dk);
-  x = shift(x, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    Ainv = shift(Ainv, dk);
+    b = shift(b, dk);
+    x = shift(x, dk);
+  }
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= g.N) return;
   const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
@@ -44,17 +46,21 @@ k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* _
 
 // ------------------------------------------------------------------ elementwise
 template <typename T, bool GR> __global__ void k_copy(int64_t n, const T* a, T* o, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  a = shift(a, dk);
-  o = shift(o, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    a = shift(a, dk);
+    o = shift(o, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = a[i];
 }
 template <typename T, bool GR> __global__ void k_zero(int64_t n, T* o, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  o = shift(o, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    o = shift(o, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = T(0);
 }
@@ -63,10 +69,12 @@ template <typename T> __global__ void k_sub(int64_t n, const T* a, const T* b, T
   if (i < n) o[i] = a[i] - b[i];
 }
 template <typename T, bool GR> __global__ void k_axpy(int64_t n, T al, const T* x, T* y, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  x = shift(x, dk);
-  y = shift(y, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    x = shift(x, dk);
+    y = shift(y, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = y[i] + al * x[i];
 }
@@ -76,19 +84,23 @@ template <typename T> __global__ void k_scale_mul(int64_t n, T al, const T* a, c
 }
 template <bool GR>
 __global__ void k_c6432(int64_t n, const double* a, float* o, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  a = shift(a, dk);
-  o = shift(o, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    a = shift(a, dk);
+    o = shift(o, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = (float)a[i];
 }
 template <bool GR>
 __global__ void k_c3264(int64_t n, const float* a, double* o, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  a = shift(a, dk);
-  o = shift(o, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    a = shift(a, dk);
+    o = shift(o, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = (double)a[i];
 }
@@ -118,14 +130,16 @@ __global__ void k_set_unit(int64_t n, int64_t idx, double* v) {
 template <typename T, bool GR>
 __global__ void k_cheb_start(int64_t n, const T* b, const T* t, const T* dinv, T theta, T* r, T* d,
                              const double* th, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  b = shift(b, dk);
-  t = shift(t, dk);
-  dinv = shift(dinv, dk);
-  r = shift(r, dk);
-  d = shift(d, dk);
-  if (GR && th) theta = (T)shift(th, dk)[0];
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    b = shift(b, dk);
+    t = shift(t, dk);
+    dinv = shift(dinv, dk);
+    r = shift(r, dk);
+    d = shift(d, dk);
+    if (th) theta = (T)shift(th, dk)[0];
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   T ri = b[i];
@@ -153,12 +167,14 @@ __global__ void k_cheb_step(int64_t n, int from_zero, T* x, const T* rin, T* r, 
 template <typename T, bool GR>
 __global__ void k_jacobi(int64_t n, int from_zero, T* x, const T* b, const T* t, const T* dinv, T om,
                          Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  x = shift(x, dk);
-  b = shift(b, dk);
-  t = shift(t, dk);
-  dinv = shift(dinv, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    x = shift(x, dk);
+    b = shift(b, dk);
+    t = shift(t, dk);
+    dinv = shift(dinv, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (from_zero)
@@ -185,11 +201,13 @@ __device__ inline double block_sum(double v) {
 template <typename T, bool GR>
 __global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const T* b, double* part,
                                                      Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  a = shift(a, dk);
-  b = shift(b, dk);
-  part = shift(part, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    a = shift(a, dk);
+    b = shift(b, dk);
+    part = shift(part, dk);
+  }
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT)
     acc += (double)a[i] * (double)b[i];
@@ -199,10 +217,12 @@ __global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const
 
 template <bool GR>
 __global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  part = shift(part, dk);
-  out = shift(out, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    part = shift(part, dk);
+    out = shift(out, dk);
+  }
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += kT) acc += part[i];
   const double s = block_sum(acc);
@@ -226,14 +246,16 @@ template <bool GR>
 __global__ void __launch_bounds__(kT)
 k_pcg_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r, const double* p,
          const double* h, double* part, Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  scal = shift(scal, dk);
-  x = shift(x, dk);
-  r = shift(r, dk);
-  p = shift(p, dk);
-  h = shift(h, dk);
-  part = shift(part, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    scal = shift(scal, dk);
+    x = shift(x, dk);
+    r = shift(r, dk);
+    p = shift(p, dk);
+    h = shift(h, dk);
+    part = shift(part, dk);
+  }
   const double al = scal[inum] / scal[iden];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
@@ -250,11 +272,13 @@ k_pcg_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r
 template <bool GR>
 __global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, double* p, const double* z,
                         Grp gp) {
-  int64_t dk;
-  if (!grp_enter<GR>(gp, &dk)) return;
-  scal = shift(scal, dk);
-  p = shift(p, dk);
-  z = shift(z, dk);
+  if constexpr (GR) {
+    int64_t dk;
+    if (!grp_begin(gp, &dk)) return;
+    scal = shift(scal, dk);
+    p = shift(p, dk);
+    z = shift(z, dk);
+  }
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const double be = scal[inum] / scal[iden];

@@ -13,6 +13,8 @@
 // (store, residual, Jacobi or Chebyshev update), so a smoothing step is two kernels and
 // never materializes A x.
 // Dirichlet data: boundary entries of x are read as 0 and A x is 0 at boundary nodes.
+#include <cstdint>
+
 #include "dev_apply.h"
 
 namespace gllmg {
@@ -76,6 +78,8 @@ k_apply_p1(const T* __restrict__ x, const T* __restrict__ G, const T* __restrict
 }
 
 constexpr int kGT = 256;
+
+constexpr int64_t kP1MaxNodes64 = 16384, kP1MaxNodes32 = 65536;
 
 template <int N, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(kGT)
@@ -213,7 +217,13 @@ void apply_p1(const Level& L, int neumann, const void* x, const Epi& epi, hipStr
 
 template <typename T>
 void apply_t(const Level& L, int neumann, const void* x, const Epi& ep, void* F, hipStream_t s) {
-  if (L.n == 2 && ep.mode != EPI_JACOBI) return apply_p1<T>(L, neumann, x, ep, s);
+  // order 1: the one-kernel product where launch latency dominates (small levels); on large
+  // 3D levels the element kernel and gather, whose F round trip costs less than the one-kernel
+  // form's 8 lanes per node. Measured crossover (3D): between 4913 and 35,937 nodes in FP64,
+  // between 35,937 and 274,625 in FP32; at 17M nodes the two kernels are 3x faster. In 2D the
+  // two forms are within 10% up to 17M nodes.
+  const int64_t p1_max = L.g.dim == 2 ? INT64_MAX : (sizeof(T) == 8 ? kP1MaxNodes64 : kP1MaxNodes32);
+  if (L.n == 2 && ep.mode != EPI_JACOBI && L.g.N <= p1_max) return apply_p1<T>(L, neumann, x, ep, s);
   switch (L.n) {
 #define GLLMG_CASE(NV) \
   case NV:             \

@@ -57,6 +57,28 @@ def test_apply_fp32(dim, ne, p):
     G.close()
 
 
+@pytest.mark.parametrize("ne,prec", [((28, 27, 26), "f64"), ((41, 41, 40), "f32")])
+def test_apply_order1_large_levels(ne, prec):
+    """3D order-1 levels above the one-kernel product's size limit (16,384 nodes in FP64,
+    65,536 in FP32) take the element kernel and gather: the same bar against the oracle's
+    operator (built alone: a one-level oracle hierarchy would factor a dense coarse matrix)."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
+    G = gllmg.Problem(gllmg.make_config(3, ne, 1, "p", max_levels=1, vcycle_prec=prec), mp, mu)
+    op = fem.LevelOperator(fem.Mesh(3, ne, 1, mp, mu))
+    assert G.nnodes(0) > (16384 if prec == "f64" else 65536)
+    x = random_vec(G.nnodes(0), 13)
+    if prec == "f64":
+        y = to_np(G.apply(to_dev(x)))
+        ok, e = fp64_close(y, op.apply(x), op.apply_abs(x))
+        assert ok, e
+    else:
+        y32 = to_np(G.apply(to_dev(x, torch.float32)))
+        assert rel_err(y32, op.apply(x)) <= 2e-5
+    G.close()
+
+
 def test_rhs_and_fields():
     import torch
     prob = inputs.poisson2d_manufactured()

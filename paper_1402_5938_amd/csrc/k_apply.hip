@@ -44,7 +44,7 @@ k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
 }
 
 template <int N, typename T, int EPB, bool GR>
-__global__ void __launch_bounds__(EPB * N * N)
+__global__ void __launch_bounds__(EPB * N)
 k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
   if constexpr (GR) {
@@ -55,9 +55,12 @@ k_apply2d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
     G = shift(G, dk);
     Dm = shift(Dm, dk);
   }
-  __shared__ T sA[EPB * N * N];
-  __shared__ T sB[EPB * N * N];
-  elem2d<N, T, EPB>(x, F, G, Dm, g, neumann, blockIdx.x * EPB, threadIdx.x, sA, sB);
+  __shared__ T lds[N * N + 2 * EPB * N * N];
+  T* sD = lds;
+  T* sA = lds + N * N;
+  T* sB = sA + EPB * N * N;
+  elem2d_col<N, T, EPB>(x, F, G, Dm, g, neumann, xcd_block(blockIdx.x, gridDim.x) * EPB,
+                        threadIdx.x, sA, sB, sD);
 }
 
 template <int DIM, typename T, bool GR>
@@ -185,8 +188,10 @@ void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F
   else
     with_gr([&](auto gr) {
       constexpr bool GR = decltype(gr)::value;
-      hipLaunchKernelGGL((k_apply2d<N, T, EPB, GR>), dim3(nb, grp_count()), dim3(EPB * N * N), 0, s,
-                       (const T*)x, (T*)F, G, D, L.g, neumann, cur_grp());
+      constexpr int EPB2 = Epb2<N>::v;
+      const unsigned nb2 = (unsigned)((L.g.E + EPB2 - 1) / EPB2);
+      hipLaunchKernelGGL((k_apply2d<N, T, EPB2, GR>), dim3(nb2, grp_count()), dim3(EPB2 * N), 0, s,
+                         (const T*)x, (T*)F, G, D, L.g, neumann, cur_grp());
     });
   GLLMG_HIP(hipGetLastError());
   launch_gather<N, T>((const T*)F, (const T*)x, L.g, neumann, typed<T>(epi), s);

@@ -186,7 +186,7 @@ def workload_batch(a):
 
 
 def workload_serve(a):
-    """Poisson-arrival stream (mean a.serve_rate req/s, 200 by default) of mixed 2D/3D solves to
+    """Poisson-arrival stream (mean a.serve_rate req/s, 100 by default, below the measured capacity of about 110) of mixed 2D/3D solves to
     1e-8 under an HBM budget; p50/p99 latency and solves/s over the first a.serve_s seconds of
     arrivals."""
     from paper_1402_5938_amd import inputs
@@ -305,7 +305,7 @@ def main():
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
-    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-rate", type=float, default=100.0)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)

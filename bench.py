@@ -186,9 +186,9 @@ def workload_batch(a):
 
 
 def workload_serve(a):
-    """Poisson-arrival stream (mean a.serve_rate req/s, 100 by default, below the measured capacity of about 110) of mixed 2D/3D solves to
-    1e-8 under an HBM budget; p50/p99 latency and solves/s over the first a.serve_s seconds of
-    arrivals."""
+    """Poisson-arrival stream (mean a.serve_rate req/s; 100 by default, below the measured
+    capacity of about 110) of mixed 2D/3D solves to 1e-8 under an HBM budget; p50/p99 latency
+    and solves/s over the first a.serve_s seconds of arrivals."""
     from paper_1402_5938_amd import inputs
     from paper_1402_5938_amd.serve import Server
     trace = inputs.serving_trace(seed=0, rate=a.serve_rate, duration_s=a.serve_s)

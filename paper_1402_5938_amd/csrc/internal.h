@@ -252,6 +252,14 @@ void dot(int prec, int64_t n, const void* a, const void* b, double* partials, do
 // scalar(s) in device memory for the PCG iteration
 void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* x, double* r,
                    const double* p, const double* h, double* partials, double* rr, hipStream_t s);
+// Lanczos: w -= V (V^T w) against the c basis vectors V_v = V + v ld (one classical
+// Gram-Schmidt pass: all coefficients from the same w, fixed-order sums). part holds
+// c kMdBlocks doubles, coef c.
+constexpr int kMdBlocks = 256;
+void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
+                         double* coef, hipStream_t s);
+void vec_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* out, hipStream_t s);  // a / sqrt(*n2)
+void vec_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y, hipStream_t s);  // y -= sqrt(*n2) x
 // dst[k cnt + i] = scal[i] (src = the first problem's scalars) for every active problem k of
 // the current launch group (dst is not shifted: one buffer for the group)
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s);

@@ -234,6 +234,67 @@ inline int dot_grid(int64_t n) {
   return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
 }
 
+// ------------------------------------------------------------------ Lanczos building blocks
+// Block-Gram-Schmidt against the basis V_0..V_{c-1} (columns of V with leading dimension ld):
+// all c coefficients in one pass over w, then one update of w; every sum in a fixed order.
+constexpr int kMdChunk = 8;
+
+// part[v kMdBlocks + b] = the strided partial of V_v . w of block b, v = kMdChunk blockIdx.y + q
+__global__ void __launch_bounds__(kT)
+k_multidot(int64_t n, const double* V, int64_t ld, int c, const double* w, double* part) {
+  __shared__ double sh[kT];
+  const int v0 = blockIdx.y * kMdChunk;
+  double acc[kMdChunk];
+#pragma unroll
+  for (int q = 0; q < kMdChunk; ++q) acc[q] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const double wi = w[i];
+#pragma unroll
+    for (int q = 0; q < kMdChunk; ++q)
+      if (v0 + q < c) acc[q] += V[(int64_t)(v0 + q) * ld + i] * wi;
+  }
+#pragma unroll
+  for (int q = 0; q < kMdChunk; ++q) {
+    sh[threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int h = kT / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0 && v0 + q < c) part[(int64_t)(v0 + q) * kMdBlocks + blockIdx.x] = sh[0];
+    __syncthreads();
+  }
+}
+
+// coef[v] = sum over blocks of part[v kMdBlocks + b] (block v)
+__global__ void __launch_bounds__(kT) k_md_final(const double* part, double* coef) {
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < kMdBlocks; b += kT) acc += part[(int64_t)blockIdx.x * kMdBlocks + b];
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) coef[blockIdx.x] = s;
+}
+
+// w -= sum_v coef[v] V_v (v ascending)
+__global__ void k_md_sub(int64_t n, const double* V, int64_t ld, int c, const double* coef, double* w) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double wi = w[i];
+  for (int v = 0; v < c; ++v) wi = wi - coef[v] * V[(int64_t)v * ld + i];
+  w[i] = wi;
+}
+
+// o = a / sqrt(*n2)
+__global__ void k_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* o) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) o[i] = a[i] / sqrt(n2[0]);
+}
+
+// y -= sqrt(*n2) x
+__global__ void k_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = y[i] + (-sqrt(n2[0])) * x[i];
+}
+
 // dst[k cnt + i] = src[i] of problem k (blockIdx.y): a launch group's scalars side by side
 __global__ void k_collect(const double* src, int cnt, double* dst, Grp gp) {
   int64_t dk;
@@ -489,6 +550,28 @@ void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x,
     constexpr bool GR = decltype(gr)::value;
     hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, rr, cur_grp());
   });
+  GLLMG_HIP(hipGetLastError());
+}
+void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
+                         double* coef, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  GLLMG_CHECK(c >= 1, GLLMG_EINVAL, "empty basis");
+  hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks, (c + kMdChunk - 1) / kMdChunk), dim3(kT), 0, s, n, V,
+                     ld, c, (const double*)w, part);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_md_final, dim3(c), dim3(kT), 0, s, (const double*)part, coef);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_md_sub, dim3(nb(n)), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* o, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_div_sqrt_dev, dim3(nb(n)), dim3(kT), 0, s, n, a, n2, o);
+  GLLMG_HIP(hipGetLastError());
+}
+void vec_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_axpy_sqrt_dev, dim3(nb(n)), dim3(kT), 0, s, n, n2, x, y);
   GLLMG_HIP(hipGetLastError());
 }
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s) {

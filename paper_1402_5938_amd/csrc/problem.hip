@@ -232,7 +232,8 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   int64_t maxN = 0;
   for (auto& L : P->L) maxN = std::max(maxN, L.g.N);
   const size_t setup = sizeof(double) * (size_t)std::max<int64_t>(
-                                            (int64_t)c.eig_steps * maxN + 4 * maxN,
+                                            (int64_t)c.eig_steps * maxN + 4 * maxN +
+                                                (int64_t)(c.eig_steps + 1) * (3 + kMdBlocks),
                                             P->L[0].npts + maxN) + 4096;
   if (setup > steady) A.take(setup - steady);
   P->scratch_bytes = A.used - before;
@@ -321,7 +322,8 @@ void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
 }
 
 // lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
-// S = D^{-1/2} A D^{-1/2} with full reorthogonalization (two modified Gram-Schmidt passes),
+// S = D^{-1/2} A D^{-1/2} with full reorthogonalization (two classical Gram-Schmidt passes,
+// each one multi-dot and one update against the whole basis),
 // m = min(eig_steps, interior unknowns) steps, SplitMix64 start vector; breakdown when
 // beta <= 1e-14 ||T||. Returns the largest eigenvalue of the tridiagonal T_m.
 double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
@@ -331,39 +333,46 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
   double* base = (double*)P->scratch;
   std::vector<double*> V(m + 1);
   for (int i = 0; i <= m; ++i) V[i] = base + (size_t)i * N;
-  // m+1 basis vectors, w, t and sqrt(dinv): (m + 4) N doubles <= the setup scratch
+  // m+1 basis vectors, w, t and sqrt(dinv): (m + 4) N doubles, then the per-step scalars
+  // alpha_j, |w_j|^2 and the orthogonalization's coefficients and partial sums
   double* w = base + (size_t)(m + 1) * N;
   double* t = w + N;
   double* sqd = t + N;
+  double* alpha = sqd + N;
+  double* n2 = alpha + (m + 1);
+  double* coef = n2 + (m + 1);
+  double* part = coef + (m + 1);
   vec_sqrt(N, L.dinv64, sqd, s);
   start_vector(L.g, P->cfg.eig_seed, l, V[0], s);
   dot(0, N, V[0], V[0], P->part, P->scal + 8, s);
-  const double nrm0 = std::sqrt(read_scalar(P, 8, s));
-  vec_div(N, V[0], nrm0, V[0], s);
-  std::vector<double> al, be;
-  double tnorm = 0.0;
+  vec_div_sqrt_dev(N, V[0], P->scal + 8, V[0], s);
+  // The whole recurrence is enqueued without reading anything back: beta_j = |w_j| stays on
+  // the device. A breakdown (|w_j| ~ 0) is found afterwards on the host, where the
+  // coefficients past it are discarded.
   for (int j = 0; j < m; ++j) {
     vec_scale_mul(0, N, 1.0, sqd, V[j], t, s);
     apply_level(P, l, 0, 0, t, w, s);
     vec_scale_mul(0, N, 1.0, sqd, w, w, s);
-    dot(0, N, V[j], w, P->part, P->scal + 9, s);
-    vec_axpy_dev(N, P->scal + 9, -1.0, V[j], w, s);
-    if (j > 0) vec_axpy(0, N, -be.back(), V[j - 1], w, s);
-    for (int pass = 0; pass < 2; ++pass)
-      for (int i = 0; i <= j; ++i) {
-        dot(0, N, V[i], w, P->part, P->scal + 10, s);
-        vec_axpy_dev(N, P->scal + 10, -1.0, V[i], w, s);
-      }
-    dot(0, N, w, w, P->part, P->scal + 11, s);
-    double sc[3];
-    read_scalars(P, 9, 3, sc, s);
-    const double a = sc[0];
-    const double bn = std::sqrt(sc[2]);
+    dot(0, N, V[j], w, P->part, alpha + j, s);
+    vec_axpy_dev(N, alpha + j, -1.0, V[j], w, s);
+    if (j > 0) vec_axpy_sqrt_dev(N, n2 + (j - 1), V[j - 1], w, s);
+    for (int pass = 0; pass < 2; ++pass) block_orthogonalize(N, V[0], N, j + 1, w, part, coef, s);
+    dot(0, N, w, w, P->part, n2 + j, s);
+    if (j + 1 < m) vec_div_sqrt_dev(N, w, n2 + j, V[j + 1], s);
+  }
+  std::vector<double> ha(m), hn(m);
+  GLLMG_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  GLLMG_HIP(hipMemcpyAsync(hn.data(), n2, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+  GLLMG_HIP(hipStreamSynchronize(s));
+  std::vector<double> al, be;
+  double tnorm = 0.0;
+  for (int j = 0; j < m; ++j) {
+    const double a = ha[j];
+    const double bn = std::sqrt(hn[j]);
     al.push_back(a);
     tnorm = std::max(tnorm, std::fabs(a) + (be.empty() ? 0.0 : be.back()) + bn);
     if (j == m - 1 || bn <= 1e-14 * tnorm) break;
     be.push_back(bn);
-    vec_div(N, w, bn, V[j + 1], s);
   }
   be.resize(al.size() - 1);
   return tridiag_max_eig(al, be);

@@ -14,12 +14,9 @@ namespace {
 __host__ __device__ inline int nloc_of(int n, int dim) { return dim == 3 ? n * n * n : n * n; }
 
 // Elements per workgroup so that a workgroup has about 256 threads (n^2 threads per element).
-#ifndef GLLMG_EPB_THREADS
-#define GLLMG_EPB_THREADS 256
-#endif
 template <int N>
 struct Epb {
-  static constexpr int v = (N * N >= GLLMG_EPB_THREADS / 2) ? 1 : (GLLMG_EPB_THREADS / (N * N));
+  static constexpr int v = (N * N >= 128) ? 1 : (256 / (N * N));
 };
 
 // An opaque use that makes the compiler compute v at this point (and not later, where it is
@@ -32,17 +29,12 @@ __device__ __forceinline__ void pin(T& v) {
 // ------------------------------------------------------------------ 3D element kernel
 // Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
 // y-contractions read the element tile from LDS, the z-contraction works in registers.
-// High orders keep a long register column per thread: allow up to 256 VGPRs (at most two
-// waves per SIMD) instead of spilling to scratch.
+// Occupancy range given to the compiler (waves per SIMD): no minimum above 1, which would
+// force spills (measured slower), and at most 4 for the high-order pass, whose LDS tile
+// allows few workgroups per CU anyway.
 template <int N>
 struct Waves {
-#ifndef GLLMG_APPLY_MINWAVES
-#define GLLMG_APPLY_MINWAVES 1
-#endif
-#ifndef GLLMG_APPLY_MINWAVES_HP
-#define GLLMG_APPLY_MINWAVES_HP 1
-#endif
-  static constexpr int min = N >= 12 ? GLLMG_APPLY_MINWAVES_HP : GLLMG_APPLY_MINWAVES;
+  static constexpr int min = 1;
   static constexpr int max = N >= 12 ? 4 : 8;
 };
 
@@ -79,14 +71,10 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
   // Every global load of the first phase is issued before any is consumed (all addresses are
   // in bounds: an out-of-range element reads element 0, thread t reads D[t mod n^2]): the x
   // column, the first PF planes of geometric factors (PF bounded by a register budget) and D.
-#ifdef GLLMG_APPLY_PF
-  constexpr int PF = GLLMG_APPLY_PF < N ? GLLMG_APPLY_PF : N;
-#else
   // measured on the 2.1M-node products: all planes for n <= 6; beyond, 4 planes in FP64 and
-  // 2 in FP32 and at n > 12 (more registers for prefetch cost occupancy, or spill, for less
-  // latency saved)
-  constexpr int PF = N <= 6 ? N : (sizeof(T) == 8 && N <= 12 ? 4 : 2);
-#endif
+  // 2 in FP32 (more registers for prefetch cost occupancy, or spill, for less latency saved;
+  // in FP32, 1 to 9 planes measured within noise at n = 5..11)
+  constexpr int PF = N <= 6 ? N : (sizeof(T) == 8 ? 4 : 2);
   T xr[N];
 #pragma unroll
   for (int k = 0; k < N; ++k) xr[k] = x[gb + sxy * k];
@@ -227,11 +215,7 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
 
   // loads issued before use (all in bounds, as in elem3d): the x column, the geometric factors
   // of the first PF planes (a ring refilled PF planes ahead) and D
-#ifdef GLLMG_HP_PF
-  constexpr int PF = GLLMG_HP_PF;
-#else
   constexpr int PF = 2;
-#endif
   const T* Ge = G + (int64_t)ee * (6 * NNN) + ij;
   T gp[PF][6];
 #pragma unroll

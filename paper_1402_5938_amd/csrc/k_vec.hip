@@ -1,5 +1,7 @@
 // Streaming kernels: the coarsest-level dense solve, the fused smoother updates, deterministic
 // dot products and the PCG vector updates.
+#include <algorithm>
+
 #include "epilogue.h"
 
 namespace gllmg {
@@ -266,10 +268,10 @@ k_multidot(int64_t n, const double* V, int64_t ld, int c, const double* w, doubl
   }
 }
 
-// coef[v] = sum over blocks of part[v kMdBlocks + b] (block v)
-__global__ void __launch_bounds__(kT) k_md_final(const double* part, double* coef) {
+// coef[v] = sum over the np blocks of part[v kMdBlocks + b] (block v)
+__global__ void __launch_bounds__(kT) k_md_final(const double* part, int np, double* coef) {
   double acc = 0.0;
-  for (int b = threadIdx.x; b < kMdBlocks; b += kT) acc += part[(int64_t)blockIdx.x * kMdBlocks + b];
+  for (int b = threadIdx.x; b < np; b += kT) acc += part[(int64_t)blockIdx.x * kMdBlocks + b];
   const double s = block_sum(acc);
   if (threadIdx.x == 0) coef[blockIdx.x] = s;
 }
@@ -556,10 +558,12 @@ void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* 
                          double* coef, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   GLLMG_CHECK(c >= 1, GLLMG_EINVAL, "empty basis");
-  hipLaunchKernelGGL(k_multidot, dim3(kMdBlocks, (c + kMdChunk - 1) / kMdChunk), dim3(kT), 0, s, n, V,
-                     ld, c, (const double*)w, part);
+  // as many blocks as the vector fills, at most kMdBlocks (a function of n alone: same sums)
+  const int g = (int)std::min<int64_t>(kMdBlocks, std::max<int64_t>(1, (n + kT - 1) / kT));
+  hipLaunchKernelGGL(k_multidot, dim3(g, (c + kMdChunk - 1) / kMdChunk), dim3(kT), 0, s, n, V, ld, c,
+                     (const double*)w, part);
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_md_final, dim3(c), dim3(kT), 0, s, (const double*)part, coef);
+  hipLaunchKernelGGL(k_md_final, dim3(c), dim3(kT), 0, s, (const double*)part, g, coef);
   GLLMG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_md_sub, dim3(nb(n)), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w);
   GLLMG_HIP(hipGetLastError());

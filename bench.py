@@ -316,8 +316,8 @@ def main():
     ap.add_argument("--order", type=int, default=8)
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported by this build "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported: the solver and "
+              "its benchmarks use a single device", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -226,21 +226,24 @@ gllmg_status gllmg_solve_poll(gllmg_problem* prob, int32_t* done);
 gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
 
 /* Solve `count` independent problems (any mix of dimension, mesh, order and precision), all
- * ordered after `stream`; the call returns when every solve has finished. Small problems (3D,
- * FP32 V-cycle, at most 10,000 fine-level nodes and 16 levels, an exact coarse solve,
- * maxit < 1024, persistent mode not switched off) are solved by one persistent kernel launch
- * per finest order on `stream`, one workgroup per problem, each stopping on its own: the same
- * steps, smoothers and transfers as gllmg_solve, with the workgroup's dot products summed in
- * another fixed order (iterates agree to rounding, not bitwise). In PCG mode, two or more of
- * the others that share one shape (dimension, elements, order, hierarchy, smoother, degrees and
- * V-cycle precision; coefficients and maps may differ) form a launch group: one lockstep PCG
- * in which every kernel is launched once for all of them, each problem leaving the launches
- * when its own solve ends; each result equals gllmg_solve's bit for bit. A group copies b and
- * x through level-0 workspace vectors that its solve does not use otherwise, allocates a small
- * device and pinned buffer (a few bytes per problem) for the call, and runs on the first
- * problem's internal stream, concurrently with the persistent launch. The remaining problems
- * run on their own internal streams, advanced iteration by iteration from the host thread.
- * stats and status may be NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
+ * ordered after `stream`; the call returns when every solve has finished. Three paths:
+ * - In PCG mode, two or more problems that share one shape (dimension, elements, order,
+ *   hierarchy, smoother, degrees and V-cycle precision; coefficients and maps may differ) form a
+ *   launch group: one lockstep PCG in which every kernel is launched once for all of them, each
+ *   problem leaving the launches when its own solve ends; each result equals gllmg_solve's bit
+ *   for bit. A group copies b and x through level-0 workspace vectors that its solve does not
+ *   use otherwise, allocates a small device and pinned buffer (a few bytes per problem) for the
+ *   call, and runs on the first problem's internal stream, driven by a host thread of its own
+ *   (groups run concurrently with each other and with the other paths).
+ * - Small problems without a same-shape partner (3D, FP32 V-cycle, at most 10,000 fine-level
+ *   nodes and 16 levels, an exact coarse solve, maxit < 1024) are solved by one persistent
+ *   kernel launch per finest order on `stream`, one workgroup per problem, each stopping on its
+ *   own: the same steps, smoothers and transfers as gllmg_solve, with the workgroup's dot
+ *   products summed in another fixed order (iterates agree to rounding, not bitwise).
+ * - The remaining problems run on their own internal streams, advanced iteration by iteration
+ *   from the host thread.
+ * gllmg_set_persistent(prob, 0) sends a problem to its own stream. stats and status may be
+ * NULL, else arrays of `count`. Every handle must be non-NULL and appear once (checked before
  * any solve starts: EINVAL). Returns GLLMG_OK if every solve converged, else the first error
  * other than ENOTCONV if any, else ENOTCONV (status[i] holds each problem's own status; a
  * problem that fails does not stop the others). */

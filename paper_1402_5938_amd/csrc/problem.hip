@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <thread>
 
@@ -1518,27 +1519,18 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       GLLMG_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), GLLMG_EINVAL,
                   "a problem appears twice in the batch");
     }
-    // small problems: one persistent launch per finest order, one workgroup per problem, on
-    // the caller's stream
     const auto t0 = std::chrono::steady_clock::now();
-    std::vector<char> pers(count, 0);
-    std::vector<int> groups[18];
     const bool args_ok = (mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG) && rtol > 0.0 && maxit >= 1;
-    for (int i = 0; i < count; ++i) {
-      gllmg_problem* P = probs[i];
-      if (!args_ok || P->sv.active || !batch_eligible(P, maxit)) continue;
-      if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
-      pers[i] = 1;
-      groups[P->L[0].n].push_back(i);
-    }
-    // problems of one shape (two or more, not taken by the persistent solver): solved in
-    // lockstep by launch groups, one group at a time on the first problem's internal stream
-    // (overlapping the persistent launches); their buffers are allocated before any launch
+    // Problems of one shape (two or more) are solved in lockstep by launch groups, one group at
+    // a time on the first problem's internal stream; measured faster than the one-workgroup
+    // solver at every size of the 4^3-element batch (729 nodes: 3.7 vs 4.4 ms for 65 problems;
+    // 4913 nodes: 6.0 vs 21.8 ms for 67). Their buffers are allocated before any launch.
     std::vector<std::vector<int>> shapes;
+    std::vector<char> in_group(count, 0);
     if (args_ok && mode == GLLMG_MODE_PCG) {
       for (int i = 0; i < count; ++i) {
         gllmg_problem* P = probs[i];
-        if (pers[i] || P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
+        if (P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
         if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
         bool placed = false;
         for (auto& sh : shapes)
@@ -1552,6 +1544,19 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       shapes.erase(std::remove_if(shapes.begin(), shapes.end(),
                                   [](const std::vector<int>& v) { return v.size() < 2; }),
                    shapes.end());
+      for (const auto& sh : shapes)
+        for (int i : sh) in_group[i] = 1;
+    }
+    // small problems without a same-shape partner: one persistent launch per finest order, one
+    // workgroup per problem, on the caller's stream (overlapping the groups)
+    std::vector<char> pers(count, 0);
+    std::vector<int> groups[18];
+    for (int i = 0; i < count; ++i) {
+      gllmg_problem* P = probs[i];
+      if (in_group[i] || !args_ok || P->sv.active || !batch_eligible(P, maxit)) continue;
+      if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
+      pers[i] = 1;
+      groups[P->L[0].n].push_back(i);
     }
     std::vector<std::unique_ptr<GroupMem>> gmem;
     for (const auto& sh : shapes) {
@@ -1588,59 +1593,52 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
                                      sizeof(double) * (size_t)(maxit + 1),
                                  hipMemcpyDeviceToHost, cs));
       }
-    std::vector<char> grouped(count, 0);
-    std::vector<hipStream_t> gstreams;
+    // each group on a host thread of its own (its launches on its own stream), concurrently
+    // with each other, the persistent launch and the streams below
+    struct GroupRun {
+      std::vector<gllmg_problem*> G;
+      std::vector<const double*> gb;
+      std::vector<double*> gx;
+      std::vector<std::vector<int64_t>> a0;
+      std::vector<GroupOut> res;
+      hipStream_t s = nullptr;
+      double el = 0.0;
+      std::exception_ptr err;
+    };
+    std::vector<GroupRun> runs(shapes.size());
     for (size_t q = 0; q < shapes.size(); ++q) {
-      const auto& sh = shapes[q];
-      {
-        gllmg_problem* P0 = probs[sh[0]];
-        if (!P0->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P0->xs, hipStreamNonBlocking));
-        GLLMG_HIP(hipStreamWaitEvent(P0->xs, start, 0));
-        std::vector<gllmg_problem*> G;
-        std::vector<const double*> gb;
-        std::vector<double*> gx;
-        std::vector<std::vector<int64_t>> a0;
-        for (int i : sh) {
-          G.push_back(probs[i]);
-          gb.push_back(b[i]);
-          gx.push_back(x[i]);
-          a0.emplace_back();
-          for (auto& L : probs[i]->L) a0.back().push_back(L.applies);
-        }
-        std::vector<GroupOut> res;
-        group_solve(G, gb, gx, rtol, maxit, P0->xs, *gmem[q], res);
-        gstreams.push_back(P0->xs);
-        const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        for (size_t k = 0; k < sh.size(); ++k) {
-          const int i = sh[k];
-          grouped[i] = 1;
-          const GroupOut& o = res[k];
-          if (stats) {
-            gllmg_solve_stats& st = stats[i];
-            st.iters = o.iters;
-            st.converged = o.conv ? 1 : 0;
-            st.relres = o.n0 > 0.0 ? o.nr / o.n0 : 0.0;
-            st.relres_true = o.rt;
-            st.t_solve_s = el;
-            for (int l = 0; l < 16; ++l)
-              st.applies[l] = l < (int)G[k]->L.size() ? G[k]->L[l].applies - a0[k][l] : 0;
-            if (st.history)
-              for (size_t j = 0; j < o.hist.size() && j <= (size_t)maxit; ++j) st.history[j] = o.hist[j];
-          }
-          const gllmg_status si = o.breakdown ? GLLMG_EBREAKDOWN : (o.conv ? GLLMG_OK : GLLMG_ENOTCONV);
-          if (status) status[i] = si;
-          if (si != GLLMG_OK) fail(i, si);
-          if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
-        }
+      GroupRun& r = runs[q];
+      gllmg_problem* P0 = probs[shapes[q][0]];
+      if (!P0->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P0->xs, hipStreamNonBlocking));
+      GLLMG_HIP(hipStreamWaitEvent(P0->xs, start, 0));
+      r.s = P0->xs;
+      for (int i : shapes[q]) {
+        r.G.push_back(probs[i]);
+        r.gb.push_back(b[i]);
+        r.gx.push_back(x[i]);
+        r.a0.emplace_back();
+        for (auto& L : probs[i]->L) r.a0.back().push_back(L.applies);
       }
     }
-    for (hipStream_t gs : gstreams) {
-      hipEvent_t e = nullptr;
-      GLLMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      GLLMG_HIP(hipEventRecord(e, gs));
-      GLLMG_HIP(hipStreamWaitEvent(cs, e, 0));
-      (void)hipEventDestroy(e);
-    }
+    std::vector<std::thread> workers;
+    for (size_t q = 0; q < runs.size(); ++q)
+      workers.emplace_back([&, q]() {
+        GroupRun& r = runs[q];
+        try {
+          group_solve(r.G, r.gb, r.gx, rtol, maxit, r.s, *gmem[q], r.res);
+        } catch (...) {
+          r.err = std::current_exception();
+        }
+        r.el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      });
+    struct Joiner {
+      std::vector<std::thread>& w;
+      ~Joiner() {
+        for (auto& t : w)
+          if (t.joinable()) t.join();
+      }
+    } joiner{workers};
+    const std::vector<char>& grouped = in_group;
     // the others: their own streams, iteration-level interleaving
     for (int i = 0; i < count; ++i) {
       if (pers[i] || grouped[i]) continue;
@@ -1689,6 +1687,37 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       GLLMG_HIP(hipEventRecord(probs[i]->sv.ev, probs[i]->xs));
       GLLMG_HIP(hipStreamWaitEvent(cs, probs[i]->sv.ev, 0));
     }
+    for (auto& t : workers) t.join();
+    for (size_t q = 0; q < runs.size(); ++q) {
+      GroupRun& r = runs[q];
+      if (r.err) std::rethrow_exception(r.err);
+      for (size_t k = 0; k < r.G.size(); ++k) {
+        const int i = shapes[q][k];
+        const GroupOut& o = r.res[k];
+        if (stats) {
+          gllmg_solve_stats& st = stats[i];
+          st.iters = o.iters;
+          st.converged = o.conv ? 1 : 0;
+          st.relres = o.n0 > 0.0 ? o.nr / o.n0 : 0.0;
+          st.relres_true = o.rt;
+          st.t_solve_s = r.el;
+          for (int l = 0; l < 16; ++l)
+            st.applies[l] = l < (int)r.G[k]->L.size() ? r.G[k]->L[l].applies - r.a0[k][l] : 0;
+          if (st.history)
+            for (size_t j = 0; j < o.hist.size() && j <= (size_t)maxit; ++j) st.history[j] = o.hist[j];
+        }
+        const gllmg_status si = o.breakdown ? GLLMG_EBREAKDOWN : (o.conv ? GLLMG_OK : GLLMG_ENOTCONV);
+        if (status) status[i] = si;
+        if (si != GLLMG_OK) fail(i, si);
+        if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
+      }
+      hipEvent_t e = nullptr;
+      GLLMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      GLLMG_HIP(hipEventRecord(e, r.s));
+      GLLMG_HIP(hipStreamWaitEvent(cs, e, 0));
+      (void)hipEventDestroy(e);
+    }
+
     if (std::find(pers.begin(), pers.end(), 1) != pers.end()) {
       GLLMG_HIP(hipStreamSynchronize(cs));
       const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -174,13 +174,14 @@ def test_persistent_batch_matches_stream_path(mode):
 
 
 def test_persistent_batch_failures_are_per_problem():
-    """maxit reached and a NaN right-hand side end only their own problem's solve."""
+    """maxit reached and a NaN right-hand side end only their own problem's solve (three
+    shapes, so that no two problems form a launch group and all take the persistent solver)."""
     import torch
     from paper_1402_5938_amd import gllmg
     mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
     probs, bs = [], []
-    for k in range(3):
-        cfg = gllmg.make_config(3, (2, 2, 2), 4, "p", vcycle_prec="f32")
+    for k, ne in enumerate([(2, 2, 2), (2, 2, 3), (3, 2, 2)]):
+        cfg = gllmg.make_config(3, ne, 4, "p", vcycle_prec="f32")
         P = gllmg.Problem(cfg, mp, mu)
         b = P.rhs(torch.from_numpy(inputs.uniform_nodal(k, P.nnodes(0))).cuda())
         if k == 1:

@@ -136,6 +136,10 @@ struct gllmg_problem {
   // state of the solve in progress (gllmg_solve_begin / _poll / _end)
   struct Solve {
     bool active = false, done = false, conv = false, breakdown = false;
+    // a V-cycle for the next iteration enqueued before the current residual norm was known, and
+    // the products it added to the per-level counts (taken back if it goes unused)
+    bool spec = false;
+    std::vector<int64_t> spec_applies;
     int mode = 0, maxit = 0, iters = 0, g = 0, phase = 0;
     const double* b = nullptr;
     double* x = nullptr;
@@ -712,6 +716,30 @@ void enqueue_iteration(gllmg_problem* P) {
   }
   post_scalars(P, S_RR, 2, 0);
   v.phase = PH_ITER;
+  // PCG: unless this iteration may well be the last (its residual norm, extrapolated from the
+  // last two, within 10x of the target, or maxit next), the next V-cycle is enqueued now, so
+  // that the GPU does not wait for the host to read the norm; the same kernels in the same
+  // order as without it. If the solve ends here after all, its result is simply not used.
+  v.spec = false;
+  const size_t h = v.hist.size();
+  if (v.mode == GLLMG_MODE_PCG && v.iters + 1 < v.maxit && h >= 2 && v.hist[h - 2] > 0.0) {
+    const double pred = v.hist[h - 1] * (v.hist[h - 1] / v.hist[h - 2]);
+    if (std::isfinite(pred) && pred > 10.0 * v.rtol * v.n0) {
+      v.spec_applies.resize(P->L.size());
+      for (size_t l = 0; l < P->L.size(); ++l) v.spec_applies[l] = P->L[l].applies;
+      precond(P, P->pr, P->pz, v.s);
+      for (size_t l = 0; l < P->L.size(); ++l) v.spec_applies[l] = P->L[l].applies - v.spec_applies[l];
+      v.spec = true;
+    }
+  }
+}
+
+// the speculative V-cycle goes unused: its products leave the counts
+void drop_spec(gllmg_problem* P) {
+  auto& v = P->sv;
+  if (!v.spec) return;
+  for (size_t l = 0; l < P->L.size() && l < v.spec_applies.size(); ++l) P->L[l].applies -= v.spec_applies[l];
+  v.spec = false;
 }
 
 void enqueue_final(gllmg_problem* P) {
@@ -798,15 +826,19 @@ bool solve_poll_impl(gllmg_problem* P) {
       v.hist.push_back(v.nr);
       if ((v.mode == GLLMG_MODE_PCG && !(ph > 0.0)) || !std::isfinite(v.nr)) {
         v.breakdown = true;
+        drop_spec(P);
         enqueue_final(P);
       } else if (v.nr <= v.rtol * v.n0) {
         v.conv = true;
+        drop_spec(P);
         enqueue_final(P);
       } else if (v.iters >= v.maxit) {
+        drop_spec(P);
         enqueue_final(P);
       } else {
         if (v.mode == GLLMG_MODE_PCG) {
-          precond(P, P->pr, P->pz, v.s);
+          if (!v.spec) precond(P, P->pr, P->pz, v.s);
+          v.spec = false;
           const int gn = v.g == S_G0 ? S_G1 : S_G0;
           dot(0, N, P->pz, P->pr, P->part, P->scal + gn, v.s);
           pcg_update_p(N, P->scal, gn, v.g, P->pp, P->pz, v.s);

@@ -521,7 +521,9 @@ __device__ __forceinline__ void p1_lanes(const T* __restrict__ x, const T* __res
         const bool m = ev && (neumann || !bnd(cx, cy, cz));
         xe[c][b][a] = *(m ? x + (cx + (int64_t)nx * (cy + (int64_t)ny * cz)) : zero);
       }
-  const T xin = x[t];
+  // the epilogue's operands, by the lane that applies it
+  EpiIn<T> in{T(0), T(0), T(0), T(0), T(0)};
+  if (live && k == 0 && !bnode) in = epilogue_load(ep, t, x);
   // the node's local coordinates in the element (runtime bits: every access below that depends
   // on them is a select, so that all values stay in registers)
   const int lx = 1 - kx, ly = 1 - ky, lz = DIM == 3 ? 1 - kz : 0;
@@ -579,7 +581,7 @@ __device__ __forceinline__ void p1_lanes(const T* __restrict__ x, const T* __res
   if (bnode)
     epilogue_zero(ep, t);
   else
-    epilogue(ep, t, contrib, xin);
+    epilogue(ep, t, contrib, in);
 }
 
 // ------------------------------------------------------------------ gather
@@ -654,9 +656,9 @@ __device__ __forceinline__ void gather_at(const T* __restrict__ F, const T* __re
     epilogue_zero(ep, t);
     return;
   }
+  const EpiIn<T> in = epilogue_load(ep, t, xin);
   const T acc = gather_sum<N, DIM, T>(F, g, gx, gy, gz);
-  const T xv = (ep.mode == EPI_JACOBI || ep.mode == EPI_CHEB) ? xin[t] : T(0);
-  epilogue(ep, t, acc, xv);
+  epilogue(ep, t, acc, in);
 }
 
 // One node per thread in node order (t < N): consecutive threads walk a grid row, so a wave

@@ -322,6 +322,7 @@ __device__ __forceinline__ void restrict_p1h_node(const T* __restrict__ rf, cons
     epilogue_zero(ep, t);
     return;
   }
+  const EpiIn<T> in = epilogue_load(ep, t, (const T*)nullptr);
   // an interior coarse node's stencil lies inside the fine grid, off its boundary
   T acc = T(0);
 #pragma unroll
@@ -334,7 +335,7 @@ __device__ __forceinline__ void restrict_p1h_node(const T* __restrict__ rf, cons
         const int fx = 2 * Ix + sx, fy = 2 * Iy + sy, fz = DIM == 3 ? 2 * Iz + sz : 0;
         acc += w * rf[fx + (int64_t)gf.nn[0] * (fy + (int64_t)gf.nn[1] * fz)];
       }
-  epilogue(ep, t, acc, T(0));
+  epilogue(ep, t, acc, in);
 }
 
 template <int DIM, typename T>

@@ -71,37 +71,76 @@ __device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
   return e;
 }
 
-// acc = (A xin)_g, xin = the input vector's value at g
+// The operands that the epilogue of ep.mode reads at node g, besides the sum: loaded before the
+// sum's own loads, so that both come in one memory round trip. xin is the product's input
+// vector (read by the Jacobi and Chebyshev steps).
 template <typename T>
-__device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, T xin) {
+struct EpiIn {
+  T b, x, rin, dinv, xin;
+};
+
+template <typename T>
+__device__ inline EpiIn<T> epilogue_load(const EpiT<T>& ep, int64_t g, const T* xin) {
+  EpiIn<T> in{T(0), T(0), T(0), T(0), T(0)};
+  switch (ep.mode) {
+    case EPI_STORE:
+      break;
+    case EPI_RESIDUAL:
+      in.b = ep.b[g];
+      break;
+    case EPI_JACOBI:
+      in.xin = xin[g];
+      in.b = ep.b[g];
+      in.dinv = ep.dinv[g];
+      break;
+    case EPI_CHEB_START:
+      in.b = ep.b[g];
+      in.dinv = ep.dinv[g];
+      break;
+    case EPI_STORE_CHEB0:
+    case EPI_STORE_JACOBI0:
+      in.dinv = ep.dinv[g];
+      break;
+    default:  // EPI_CHEB
+      in.xin = xin[g];
+      if (!ep.from_zero) in.x = ep.x[g];
+      in.rin = ep.rin[g];
+      in.dinv = ep.dinv[g];
+  }
+  return in;
+}
+
+// acc = (A xin)_g; in = epilogue_load at g
+template <typename T>
+__device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, const EpiIn<T>& in) {
   switch (ep.mode) {
     case EPI_STORE:
       ep.y[g] = acc;
       break;
     case EPI_RESIDUAL:
-      ep.r[g] = ep.b[g] - acc;
+      ep.r[g] = in.b - acc;
       break;
     case EPI_JACOBI:
-      ep.x[g] = xin + (ep.om * ep.dinv[g]) * (ep.b[g] - acc);
+      ep.x[g] = in.xin + (ep.om * in.dinv) * (in.b - acc);
       break;
     case EPI_CHEB_START: {  // r = b - A x, d = dinv r / theta (theta in c1)
-      const T ri = ep.b[g] - acc;
+      const T ri = in.b - acc;
       ep.r[g] = ri;
-      ep.d[g] = ep.dinv[g] * ri / ep.c1;
+      ep.d[g] = in.dinv * ri / ep.c1;
       break;
     }
     case EPI_STORE_CHEB0:
       ep.y[g] = acc;
-      ep.d[g] = ep.dinv[g] * acc / ep.c1;
+      ep.d[g] = in.dinv * acc / ep.c1;
       break;
     case EPI_STORE_JACOBI0:
       ep.y[g] = acc;
-      ep.x[g] = (ep.om * ep.dinv[g]) * acc;
+      ep.x[g] = (ep.om * in.dinv) * acc;
       break;
     default: {  // EPI_CHEB, input vector is d
-      const T xo = ep.from_zero ? xin : ep.x[g] + xin;
-      const T ri = ep.rin[g] - acc;
-      const T dn = ep.c1 * xin + (ep.c2 * ep.dinv[g]) * ri;
+      const T xo = ep.from_zero ? in.xin : in.x + in.xin;
+      const T ri = in.rin - acc;
+      const T dn = ep.c1 * in.xin + (ep.c2 * in.dinv) * ri;
       if (ep.last) {  // the polynomial's final step: x = (x + d) + d_next, r and d not needed
         ep.x[g] = xo + dn;
       } else {

@@ -38,23 +38,49 @@ struct Waves {
   static constexpr int max = N >= 12 ? 4 : 8;
 };
 
-// One pass of the 3D element kernel over the EPB elements ebase.. by the threads t of a
-// workgroup: t < EPB n^2 own a column, others only join the barriers. sA and sB hold EPB n^3
-// values, sD n^2. Consecutive calls that share the LDS must be separated by a barrier.
-template <int N, typename T, int EPB>
+// Which elements a pass of the element kernel works on, and where each one's element vector
+// goes. ERange: elements ebase + le, the vector at F + e n^d (the level's element vectors).
+struct ERange {
+  __device__ bool elem(uint32_t ebase, int le, const Grid& g, uint32_t* e) const {
+    *e = ebase + (uint32_t)le;
+    return *e < (uint32_t)g.E;
+  }
+  __device__ int64_t out(uint32_t e, int, int nloc) const { return (int64_t)e * nloc; }
+};
+
+// EBox: the elements (e0 + l) of an EB^3 box, le = lx + EB (ly + EB lz), those outside the mesh
+// left out; the vector of box element le at F + le n^d (a tile in LDS).
+template <int EB>
+struct EBox {
+  int e0[3];
+  __device__ bool elem(uint32_t, int le, const Grid& g, uint32_t* e) const {
+    const int lx = le % EB, ly = (le / EB) % EB, lz = le / (EB * EB);
+    const int ex = e0[0] + lx, ey = e0[1] + ly, ez = e0[2] + lz;
+    const bool ok = ex >= 0 && ex < g.ne[0] && ey >= 0 && ey < g.ne[1] && ez >= 0 && ez < g.ne[2];
+    *e = ok ? (uint32_t)ex + (uint32_t)g.ne[0] * ((uint32_t)ey + (uint32_t)g.ne[1] * (uint32_t)ez) : 0u;
+    return ok;
+  }
+  __device__ int64_t out(uint32_t, int le, int nloc) const { return (int64_t)le * nloc; }
+};
+
+// One pass of the 3D element kernel over EPB elements (those of `map`, by default ebase..) by
+// the threads t of a workgroup: t < EPB n^2 own a column, others only join the barriers. sA and
+// sB hold EPB n^3 values, sD n^2. Consecutive calls that share the LDS must be separated by a
+// barrier.
+template <int N, typename T, int EPB, class Map = ERange>
 __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ F,
                                        const T* __restrict__ G, const T* __restrict__ Dm,
                                        const Grid& g, int neumann, uint32_t ebase, int t,
                                        T* __restrict__ sA, T* __restrict__ sB,
-                                       T* __restrict__ sD) {
+                                       T* __restrict__ sD, const Map& map = Map{}) {
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
   const bool act = t < EPB * NN;
   const int tt = act ? t : 0;
   const int le = tt / NN;
   const int ij = tt - le * NN;
   const int i = ij % N, j = ij / N;
-  const uint32_t e = ebase + le;
-  const bool valid = act && e < (uint32_t)g.E;
+  uint32_t e = 0u;
+  const bool valid = act && map.elem(ebase, le, g, &e);
   const uint32_t ee = valid ? e : 0u;
   const uint32_t nexy = (uint32_t)g.ne[0] * (uint32_t)g.ne[1];
   const int ez = (int)(ee / nexy);
@@ -155,7 +181,7 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
     DiT[l] = sD[l * N + i];
     DjT[l] = sD[l * N + j];
   }
-  T* Fe = F + (int64_t)e * NNN + ij;
+  T* Fe = F + map.out(e, le, NNN) + ij;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T acc = T(0);
@@ -685,6 +711,103 @@ __device__ __forceinline__ void gather_row(const T* __restrict__ F, const T* __r
   const int64_t rbase = (int64_t)g.nn[0] * row;
   for (int gx = lane; gx < g.nn[0]; gx += nlanes)
     gather_at<N, DIM, T>(F, xin, g, neumann, ep, rbase + gx, gx, gy, gz);
+}
+
+// ------------------------------------------------------------------ one-kernel product of small levels
+// Workgroup b owns the nodes of a box of TB p nodes per axis (the last box along an axis also
+// the mesh's last node) and computes, into LDS, the element vectors of every element that
+// contains one of them: the (TB + 1)^3 elements from b TB - 1 on along each axis (those shared
+// with neighbouring boxes are computed by each). Each owned node then sums its elements'
+// values and applies the epilogue. The element pass is the element kernel's and the sum runs in
+// the gather's order, so the result is that of the two launches to the bit, in one launch and
+// one memory round trip: for levels where latency, not bytes, sets the time.
+template <int N, int TB>
+struct Box {
+  static constexpr int P = N - 1, S = TB * P, EB = TB + 1, EPB = EB * EB * EB;
+  static constexpr int NNN = N * N * N;
+  static constexpr int OWN = S + 1;  // owned nodes per axis, at most
+  static constexpr int NT = (EPB * N * N + 63) / 64 * 64;
+  static constexpr int NPT = (OWN * OWN * OWN + NT - 1) / NT;
+  static constexpr int LDS = N * N + 3 * EPB * NNN;  // sD, sA, sB, sF
+};
+
+// boxes along an axis of nn nodes: the last one also takes the final node
+__host__ __device__ inline int box_count(int nn, int S) { return nn - 1 > S ? (nn - 2) / S + 1 : 1; }
+
+// Sum over the elements of the box tile sF containing node (gx, gy, gz): gather_sum's order.
+template <int N, int EB, typename T>
+__device__ __forceinline__ T box_sum(const T* __restrict__ sF, const Grid& g, int gx, int gy,
+                                     int gz, const int* e0) {
+  constexpr int P = N - 1, NNN = N * N * N;
+  int cex[2], clx[2], cey[2], cly[2], cez[2], clz[2];
+  const int cx = axis_cands(gx, P, g.ne[0], cex, clx);
+  const int cy = axis_cands(gy, P, g.ne[1], cey, cly);
+  const int cz = axis_cands(gz, P, g.ne[2], cez, clz);
+  T acc = T(0);
+#pragma unroll
+  for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+    for (int ky = 0; ky < 2; ++ky)
+#pragma unroll
+      for (int kx = 0; kx < 2; ++kx)
+        if (kz < cz && ky < cy && kx < cx) {
+          const int le = (cex[kx] - e0[0]) + EB * ((cey[ky] - e0[1]) + EB * (cez[kz] - e0[2]));
+          acc += sF[le * NNN + clx[kx] + N * (cly[ky] + N * clz[kz])];
+        }
+  return acc;
+}
+
+// Box b of the level (b < product of box_count over the axes), threads t < Box::NT; sA, sB and
+// sF hold Box::EPB n^3 values, sD n^2.
+template <int N, int TB, typename T>
+__device__ __forceinline__ void apply_box(const T* __restrict__ x, const T* __restrict__ G,
+                                          const T* __restrict__ Dm, const Grid& g, int neumann,
+                                          const EpiT<T>& ep, uint32_t b, int t,
+                                          T* __restrict__ sA, T* __restrict__ sB,
+                                          T* __restrict__ sF, T* __restrict__ sD) {
+  using B = Box<N, TB>;
+  const int nbx = box_count(g.nn[0], B::S), nby = box_count(g.nn[1], B::S);
+  const int bz = (int)(b / (uint32_t)(nbx * nby));
+  const int rb = (int)(b - (uint32_t)bz * (uint32_t)(nbx * nby));
+  const int by = rb / nbx, bx = rb - by * nbx;
+  const int nbz = box_count(g.nn[2], B::S);
+  const int o[3] = {bx * B::S, by * B::S, bz * B::S};
+  const int c[3] = {bx == nbx - 1 ? g.nn[0] - o[0] : B::S, by == nby - 1 ? g.nn[1] - o[1] : B::S,
+                    bz == nbz - 1 ? g.nn[2] - o[2] : B::S};
+  const int e0[3] = {bx * TB - 1, by * TB - 1, bz * TB - 1};
+  // this thread's owned nodes and their epilogue operands, loaded with the element pass's
+  int64_t tn[B::NPT];
+  int gn[B::NPT][3];
+  bool own[B::NPT], zero[B::NPT];
+  EpiIn<T> in[B::NPT];
+#pragma unroll
+  for (int q = 0; q < B::NPT; ++q) {
+    const int sl = t + q * B::NT;
+    const int u = sl % B::OWN, v = (sl / B::OWN) % B::OWN, w = sl / (B::OWN * B::OWN);
+    own[q] = sl < B::OWN * B::OWN * B::OWN && u < c[0] && v < c[1] && w < c[2];
+    gn[q][0] = o[0] + u;
+    gn[q][1] = o[1] + v;
+    gn[q][2] = o[2] + w;
+    const bool bnd = gn[q][0] == 0 || gn[q][0] == g.nn[0] - 1 || gn[q][1] == 0 ||
+                     gn[q][1] == g.nn[1] - 1 || gn[q][2] == 0 || gn[q][2] == g.nn[2] - 1;
+    zero[q] = bnd && !neumann;
+    tn[q] = own[q] ? gn[q][0] + (int64_t)g.nn[0] * (gn[q][1] + (int64_t)g.nn[1] * gn[q][2]) : 0;
+    in[q] = EpiIn<T>{T(0), T(0), T(0), T(0), T(0)};
+    if (own[q] && !zero[q]) in[q] = epilogue_load(ep, tn[q], x);
+  }
+  elem3d<N, T, B::EPB, EBox<B::EB>>(x, sF, G, Dm, g, neumann, 0u, t, sA, sB, sD,
+                                    EBox<B::EB>{{e0[0], e0[1], e0[2]}});
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < B::NPT; ++q) {
+    if (!own[q]) continue;
+    if (zero[q]) {
+      epilogue_zero(ep, tn[q]);
+      continue;
+    }
+    const T acc = box_sum<N, B::EB, T>(sF, g, gn[q][0], gn[q][1], gn[q][2], e0);
+    epilogue(ep, tn[q], acc, in[q]);
+  }
 }
 
 }  // namespace

@@ -79,6 +79,30 @@ def test_apply_order1_large_levels(ne, prec):
     G.close()
 
 
+@pytest.mark.parametrize("ne,prec", [((7, 5, 9), "f64"), ((17, 16, 15), "f64"), ((9, 1, 6), "f32"),
+                                     ((41, 40, 23), "f64")])
+def test_apply_order2_levels(ne, prec):
+    """3D order-2 levels up to 65,536 nodes take the one-kernel box product (boxes of 2^3
+    owned elements, partial boxes at odd element counts); the last case, above that size, takes
+    the element kernel and gather. Dirichlet and Neumann products against the oracle's
+    operator."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
+    G = gllmg.Problem(gllmg.make_config(3, ne, 2, "p", max_levels=1, vcycle_prec=prec), mp, mu)
+    op = fem.LevelOperator(fem.Mesh(3, ne, 2, mp, mu))
+    x = random_vec(G.nnodes(0), 17)
+    for neu in (False, True):
+        if prec == "f64":
+            y = to_np(G.apply(to_dev(x), neumann=neu))
+            ok, e = fp64_close(y, op.apply(x, neumann=neu), op.apply_abs(x, neumann=neu))
+            assert ok, e
+        else:
+            y32 = to_np(G.apply(to_dev(x, torch.float32), neumann=neu))
+            assert rel_err(y32, op.apply(x, neumann=neu)) <= 2e-5
+    G.close()
+
+
 def test_rhs_and_fields():
     import torch
     prob = inputs.poisson2d_manufactured()

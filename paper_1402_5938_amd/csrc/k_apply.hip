@@ -21,8 +21,16 @@ namespace gllmg {
 
 namespace {
 
+// threads of the 3D element kernel: EPB n^2, rounded up to whole waves for the FP32 high-order
+// pass (whose cross-lane reads need every lane of a wave present)
+template <int N, typename T, int EPB>
+struct Threads3d {
+  static constexpr int v =
+      (N >= GLLMG_HIGHP_N && sizeof(T) == 4) ? (EPB * N * N + 63) / 64 * 64 : EPB * N * N;
+};
+
 template <int N, typename T, int EPB, bool GR>
-__global__ void __launch_bounds__(EPB * N * N) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
+__global__ void __launch_bounds__((Threads3d<N, T, EPB>::v)) __attribute__((amdgpu_waves_per_eu(Waves<N>::min, Waves<N>::max)))
 k_apply3d(const T* __restrict__ x, T* __restrict__ F, const T* __restrict__ G,
           const T* __restrict__ Dm, Grid g, int neumann, Grp gp) {
   if constexpr (GR) {
@@ -211,7 +219,7 @@ void apply_n(const Level& L, int neumann, const void* x, const Epi& epi, void* F
   if (L.g.dim == 3)
     with_gr([&](auto gr) {
       constexpr bool GR = decltype(gr)::value;
-      hipLaunchKernelGGL((k_apply3d<N, T, EPB, GR>), dim3(nb, grp_count()), dim3(EPB * N * N), 0, s,
+      hipLaunchKernelGGL((k_apply3d<N, T, EPB, GR>), dim3(nb, grp_count()), dim3(Threads3d<N, T, EPB>::v), 0, s,
                        (const T*)x, (T*)F, G, D, L.g, neumann, cur_grp());
     });
   else

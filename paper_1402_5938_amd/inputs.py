@@ -1,4 +1,4 @@
-"""Seeded synthetic inputs shared by the tests, the benchmark and the server driver.
+"""Seeded synthetic inputs shared by the tests, the benchmark and the serving loop.
 
 This module holds problem descriptions (mesh, order, the coefficient and map families with
 their parameters) and every random draw the workloads need. It contains none of the

@@ -579,7 +579,7 @@ __device__ __forceinline__ void p1_lanes(const T* __restrict__ x, const T* __res
         xe[c][b][a] = *(m ? x + (cx + (int64_t)nx * (cy + (int64_t)ny * cz)) : zero);
       }
   // the epilogue's operands, by the lane that applies it
-  EpiIn<T> in{T(0), T(0), T(0), T(0), T(0)};
+  EpiIn<T> in{};
   if (live && k == 0 && !bnode) in = epilogue_load(ep, t, x);
   // the node's local coordinates in the element (runtime bits: every access below that depends
   // on them is a select, so that all values stay in registers)
@@ -823,7 +823,7 @@ __device__ __forceinline__ void apply_box(const T* __restrict__ x, const T* __re
                      gn[q][1] == g.nn[1] - 1 || gn[q][2] == 0 || gn[q][2] == g.nn[2] - 1;
     zero[q] = bnd && !neumann;
     tn[q] = own[q] ? gn[q][0] + (int64_t)g.nn[0] * (gn[q][1] + (int64_t)g.nn[1] * gn[q][2]) : 0;
-    in[q] = EpiIn<T>{T(0), T(0), T(0), T(0), T(0)};
+    in[q] = EpiIn<T>{};
     if (own[q] && !zero[q]) in[q] = epilogue_load(ep, tn[q], x);
   }
   elem3d<N, T, B::EPB, EBox<B::EB>>(x, sF, G, Dm, g, neumann, 0u, t, sA, sB, sD,

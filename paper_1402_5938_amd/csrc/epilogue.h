@@ -28,6 +28,8 @@ struct EpiT {
   T* r;
   T* d;
   const T* dinv;
+  const T* e0;
+  const T* e1;
   T c1, c2, om;
   const double* cc;
 };
@@ -35,7 +37,8 @@ struct EpiT {
 template <typename T>
 __host__ __device__ EpiT<T> typed(const Epi& e) {
   return EpiT<T>{e.mode, e.from_zero, e.last, (T*)e.y, (const T*)e.b, (T*)e.x, (const T*)e.rin, (T*)e.r,
-                 (T*)e.d, (const T*)e.dinv, (T)e.c1, (T)e.c2, (T)e.om, e.cc};
+                 (T*)e.d, (const T*)e.dinv, (const T*)e.e0, (const T*)e.e1, (T)e.c1, (T)e.c2,
+                 (T)e.om, e.cc};
 }
 
 // ------------------------------------------------------------------ launch groups
@@ -63,6 +66,8 @@ __device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
   e.r = shift(e.r, d);
   e.d = shift(e.d, d);
   e.dinv = shift(e.dinv, d);
+  e.e0 = shift(e.e0, d);
+  e.e1 = shift(e.e1, d);
   if (e.cc) {
     const double* c = shift(e.cc, d);
     e.c1 = (T)c[0];
@@ -76,12 +81,12 @@ __device__ inline EpiT<T> shift(EpiT<T> e, int64_t d) {
 // vector (read by the Jacobi and Chebyshev steps).
 template <typename T>
 struct EpiIn {
-  T b, x, rin, dinv, xin;
+  T b, x, rin, dinv, xin, e0, e1;
 };
 
 template <typename T>
 __device__ inline EpiIn<T> epilogue_load(const EpiT<T>& ep, int64_t g, const T* xin) {
-  EpiIn<T> in{T(0), T(0), T(0), T(0), T(0)};
+  EpiIn<T> in{};
   switch (ep.mode) {
     case EPI_STORE:
       break;
@@ -99,6 +104,19 @@ __device__ inline EpiIn<T> epilogue_load(const EpiT<T>& ep, int64_t g, const T* 
       break;
     case EPI_STORE_CHEB0:
     case EPI_STORE_JACOBI0:
+      in.dinv = ep.dinv[g];
+      break;
+    case EPI_CHEB_D:
+      in.xin = xin[g];
+      in.rin = ep.rin[g];
+      in.dinv = ep.dinv[g];
+      break;
+    case EPI_CHEB_SUM:
+      in.xin = xin[g];
+      if (!ep.from_zero) in.x = ep.x[g];
+      in.e0 = ep.e0[g];
+      if (ep.e1) in.e1 = ep.e1[g];
+      in.rin = ep.rin[g];
       in.dinv = ep.dinv[g];
       break;
     default:  // EPI_CHEB
@@ -137,6 +155,20 @@ __device__ inline void epilogue(const EpiT<T>& ep, int64_t g, T acc, const EpiIn
       ep.y[g] = acc;
       ep.x[g] = (ep.om * in.dinv) * acc;
       break;
+    case EPI_CHEB_D: {
+      const T ri = in.rin - acc;
+      ep.r[g] = ri;
+      ep.d[g] = ep.c1 * in.xin + (ep.c2 * in.dinv) * ri;
+      break;
+    }
+    case EPI_CHEB_SUM: {
+      T xs = ep.from_zero ? in.e0 : in.x + in.e0;
+      if (ep.e1) xs = xs + in.e1;
+      const T ri = in.rin - acc;
+      const T dn = ep.c1 * in.xin + (ep.c2 * in.dinv) * ri;
+      ep.x[g] = (xs + in.xin) + dn;
+      break;
+    }
     default: {  // EPI_CHEB, input vector is d
       const T xo = ep.from_zero ? in.xin : in.x + in.xin;
       const T ri = in.rin - acc;
@@ -175,6 +207,13 @@ __device__ inline void epilogue_zero(const EpiT<T>& ep, int64_t g) {
       break;
     case EPI_STORE_JACOBI0:
       ep.y[g] = T(0);
+      ep.x[g] = T(0);
+      break;
+    case EPI_CHEB_D:
+      ep.r[g] = T(0);
+      ep.d[g] = T(0);
+      break;
+    case EPI_CHEB_SUM:
       ep.x[g] = T(0);
       break;
     default:

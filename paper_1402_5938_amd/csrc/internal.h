@@ -80,6 +80,7 @@ struct Level {
   void* vr[2] = {nullptr, nullptr};
   void* vd[2] = {nullptr, nullptr};
   void* vd2[2] = {nullptr, nullptr};  // Chebyshev directions alternate between vd and vd2
+  void* vd3[2] = {nullptr, nullptr};  // degree 4: the third direction, kept to the last step
   // transfer to the next coarser level (if any)
   bool has_coarse = false;
   Xfer tp;  // to the next coarser level
@@ -142,6 +143,10 @@ void launch_dinv(const Grid& g, const double* diag, double* dinv64, float* dinv3
 //  CHEB_START: r = b - A x, d = dinv r / c1                    (c1 = theta)
 //  CHEB:     with t = A d: x = x + d (or x = d), r = rin - t,
 //            d = c1 d + (c2 dinv) r                             (in place; the input is d)
+//  CHEB_D:   CHEB without the x update (r and the next d only)
+//  CHEB_SUM: the polynomial's last step with the x updates of the CHEB_D steps before it:
+//            x = (((x + e0) + e1) + d) + (c1 d + (c2 dinv) (rin - t)), the terms in the order
+//            of the step-by-step updates (x omitted when from_zero, e1 when null)
 // and, for sums that are not products (the restriction's gather, s = the summed value):
 //  STORE_CHEB0:   y = s, d = dinv s / c1      (first Chebyshev step from x = 0, c1 = theta)
 //  STORE_JACOBI0: y = s, x = (om dinv) s      (first Jacobi step from x = 0)
@@ -153,7 +158,9 @@ enum EpiMode {
   EPI_CHEB = 3,
   EPI_CHEB_START = 4,
   EPI_STORE_CHEB0 = 5,
-  EPI_STORE_JACOBI0 = 6
+  EPI_STORE_JACOBI0 = 6,
+  EPI_CHEB_D = 7,
+  EPI_CHEB_SUM = 8
 };
 struct Epi {
   int mode = EPI_STORE;
@@ -166,6 +173,8 @@ struct Epi {
   void* r = nullptr;
   void* d = nullptr;
   const void* dinv = nullptr;
+  const void* e0 = nullptr;  // CHEB_SUM: earlier directions
+  const void* e1 = nullptr;
   double c1 = 0, c2 = 0, om = 0;
   // when set: c1, c2 are read on the device from cc[0], cc[1] (per problem in a launch group)
   const double* cc = nullptr;

@@ -147,7 +147,7 @@ def test_smoother(smoother, dim, ne, p):
     lv = H.levels[0]
     b = random_vec(lv.mesh.N, 5) * lv.mesh.interior
     x0 = random_vec(lv.mesh.N, 6) * lv.mesh.interior
-    for k in (1, 2, 4):
+    for k in (1, 2, 3, 4):  # 3 and 4: the deferred x updates
         for zero in (True, False):
             xg = to_dev(x0.copy())
             G.smooth(to_dev(b), xg, k, 0, zero_guess=zero)

@@ -120,8 +120,10 @@ const char* gllmg_last_error(void);
  * 10 eigen steps, FP64 V-cycle. dim/nelem/order are left for the caller. */
 void gllmg_config_default(gllmg_config* cfg);
 
-/* Number of levels and device bytes a setup of cfg needs (the whole footprint: no device
- * memory is allocated by any later call). */
+/* Number of levels and device bytes a setup of cfg needs: the whole device footprint. After
+ * gllmg_setup no call allocates device or pinned host memory, streams or events (they are all
+ * made by gllmg_setup, so admission by this figure is exact); the only exception is the V-cycle
+ * graph that gllmg_set_lmax and gllmg_set_graphs(1) capture again. */
 gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* device_bytes);
 
 /* Build the hierarchy: per level the geometric factors G = w mu detJ J^{-1} J^{-T} at every
@@ -144,13 +146,16 @@ gllmg_status gllmg_level_info(const gllmg_problem* prob, int32_t level, int64_t*
                               int64_t* ninterior, int32_t* order, int32_t nelem[3],
                               double* lmax);
 
-/* Replace a level's lambda_max (for example to use an externally computed bound). */
+/* Replace a level's lambda_max (for example to use an externally computed bound). The level's
+ * Chebyshev coefficients are recomputed and the solve's V-cycle graph is captured again here
+ * (synchronously), so that the next solve replays it. */
 gllmg_status gllmg_set_lmax(gllmg_problem* prob, int32_t level, double lmax);
 
 /* Replay the solve's V-cycle from a HIP graph captured on first use (enable = 1, the
  * default) or launch its kernels one by one (enable = 0). Both execute the same kernels in
  * the same order and give bitwise identical results; the graph removes host launch gaps.
- * The graph is rebuilt after gllmg_set_lmax. */
+ * The graph is captured at setup, again by gllmg_set_lmax, and by this call if enable = 1 and
+ * none exists. */
 gllmg_status gllmg_set_graphs(gllmg_problem* prob, int32_t enable);
 
 /* Whether gllmg_batch_solve may solve this problem with the persistent solver or in a launch
@@ -232,9 +237,10 @@ gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
  *   launch group: one lockstep PCG in which every kernel is launched once for all of them, each
  *   problem leaving the launches when its own solve ends; each result equals gllmg_solve's bit
  *   for bit. A group copies b and x through level-0 workspace vectors that its solve does not
- *   use otherwise, allocates a small device and pinned buffer (a few bytes per problem) for the
- *   call, and runs on the first problem's internal stream, driven by a host thread of its own
- *   (groups run concurrently with each other and with the other paths).
+ *   use otherwise, keeps its per-problem offsets, flags and scalars in the first problem's
+ *   workspace (at most 256 problems per group; more of one shape form several groups), and runs
+ *   on the first problem's internal stream, driven by a host thread of its own (groups run
+ *   concurrently with each other and with the other paths). Nothing is allocated by the call.
  * - Small problems without a same-shape partner (3D, FP32 V-cycle, at most 10,000 fine-level
  *   nodes and 16 levels, an exact coarse solve, maxit < 1024) are solved by one persistent
  *   kernel launch per finest order on `stream`, one workgroup per problem, each stopping on its

@@ -96,6 +96,9 @@ Grid make_grid(int dim, const LevelSpec& s) {
 }
 
 constexpr int64_t kMaxCoarse = 4096;
+// problems in one launch group of gllmg_batch_solve (the group's buffers sit in the first
+// problem's workspace; a shape with more problems forms several groups)
+constexpr int kGroupMax = 256;
 
 }  // namespace
 
@@ -154,6 +157,16 @@ struct gllmg_problem {
   BatchProblem* bdev = nullptr;   // descriptor of the persistent batched solver (workspace)
   BatchProblem* bhost = nullptr;  // its pinned host image
   bool persistent = true;         // gllmg_batch_solve may use the persistent solver
+  // a launch group led by this problem (gllmg_batch_solve): per member k its workspace offset,
+  // active flag and collected scalars in the workspace, their pinned host images, and the
+  // events that order the batch's streams; all made at setup, so a batch allocates nothing
+  int64_t* gdlt = nullptr;
+  int* gact = nullptr;
+  double* gsc = nullptr;
+  int* ghact = nullptr;
+  double* ghsc = nullptr;
+  hipEvent_t bev = nullptr;  // the batch's start, recorded on the caller's stream
+  hipEvent_t gev = nullptr;  // the end of the group this problem leads
 };
 
 namespace gllmg {
@@ -212,6 +225,9 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   P->scal = (double*)A.take(sizeof(double) * 64);
   P->part = (double*)A.take(sizeof(double) * kDotBlocks);
   P->flag = (int*)A.take(sizeof(int) * 4);
+  P->gdlt = (int64_t*)A.take(sizeof(int64_t) * kGroupMax);
+  P->gact = (int*)A.take(sizeof(int) * kGroupMax);
+  P->gsc = (double*)A.take(sizeof(double) * 4 * kGroupMax);
   P->map_modes = (double*)A.take(sizeof(double) * 5 * GLLMG_MAX_MODES);
   P->mu_modes = (double*)A.take(sizeof(double) * 5 * GLLMG_MAX_MODES);
   // scratch: solve vectors in steady state, setup temporaries during setup
@@ -667,7 +683,7 @@ void drop_graph(gllmg_problem* P) {
 // threads of the process (a server's setup thread, say) may keep issuing synchronous HIP
 // calls while the capture is open.
 void capture_vcycle(gllmg_problem* P) {
-  if (!P->cap) GLLMG_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+  GLLMG_CHECK(P->cap != nullptr, GLLMG_EDEVICE, "no capture stream");
   std::vector<int64_t> a0;
   for (auto& L : P->L) a0.push_back(L.applies);
   GLLMG_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
@@ -692,21 +708,23 @@ void capture_vcycle(gllmg_problem* P) {
   }
 }
 
+// (Re)capture the V-cycle graph if the problem uses one; if capture fails the same kernels are
+// launched one by one instead.
+void recapture(gllmg_problem* P) {
+  drop_graph(P);
+  if (!P->use_graph || !P->L.back().Ainv64) return;
+  try {
+    capture_vcycle(P);
+  } catch (const Error&) {
+    (void)hipGetLastError();
+    P->use_graph = false;
+  }
+}
+
 void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
-  if (!P->use_graph || r != P->pr || z != P->pz) {
+  if (!P->use_graph || !P->vexec || r != P->pr || z != P->pz) {
     precond_eager(P, r, z, s);
     return;
-  }
-  if (!P->vexec) {
-    try {
-      capture_vcycle(P);
-    } catch (const Error&) {
-      // the same kernels are launched one by one instead
-      (void)hipGetLastError();
-      P->use_graph = false;
-      precond_eager(P, r, z, s);
-      return;
-    }
   }
   GLLMG_HIP(hipGraphLaunch(P->vexec, s));
   for (size_t l = 0; l < P->L.size(); ++l) P->L[l].applies += P->vapplies[l];
@@ -783,8 +801,7 @@ void solve_begin(gllmg_problem* P, int mode, const double* b, double* x, double 
                  hipStream_t s) {
   auto& v = P->sv;
   GLLMG_CHECK(!v.active, GLLMG_EINVAL, "a solve is already in progress on this problem");
-  hipEvent_t ev = v.ev;
-  if (!ev) GLLMG_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  hipEvent_t ev = v.ev;  // made at setup
   v = gllmg_problem::Solve{};
   v.ev = ev;
   v.active = true;
@@ -1016,22 +1033,6 @@ struct GroupOut {
   std::vector<double> hist;
 };
 
-// Device and pinned buffers of one group solve.
-struct GroupMem {
-  int64_t* dlt = nullptr;
-  int* act = nullptr;
-  double* sc = nullptr;
-  int* hact = nullptr;
-  double* hsc = nullptr;
-  ~GroupMem() {
-    if (dlt) (void)hipFree(dlt);
-    if (act) (void)hipFree(act);
-    if (sc) (void)hipFree(sc);
-    if (hact) (void)hipHostFree(hact);
-    if (hsc) (void)hipHostFree(hsc);
-  }
-};
-
 // Makes a launch group current for this thread while it lives.
 struct GroupScope {
   explicit GroupScope(const LaunchGroup* g) { set_launch_group(g); }
@@ -1042,21 +1043,22 @@ struct GroupScope {
 // lockstep: every kernel of an iteration runs once for all problems still iterating (a
 // problem leaves the launches when it has converged, broken down or reached maxit). Each
 // problem follows exactly the arithmetic of its own solve (same kernels, same reduction
-// trees), so the results equal gllmg_solve's bit for bit. Synchronous on s.
-void group_alloc(GroupMem& m, int K) {
-  GLLMG_HIP(hipMalloc((void**)&m.dlt, sizeof(int64_t) * K));
-  GLLMG_HIP(hipMalloc((void**)&m.act, sizeof(int) * K));
-  GLLMG_HIP(hipMalloc((void**)&m.sc, sizeof(double) * 4 * K));
-  GLLMG_HIP(hipHostMalloc((void**)&m.hact, sizeof(int) * K, hipHostMallocDefault));
-  GLLMG_HIP(hipHostMalloc((void**)&m.hsc, sizeof(double) * 4 * K, hipHostMallocDefault));
-}
-
-// m: buffers from group_alloc for G.size() problems
+// trees), so the results equal gllmg_solve's bit for bit. The group's buffers are the first
+// problem's (its workspace and pinned images, made at setup), so at most kGroupMax problems.
+// Synchronous on s.
 void group_solve(const std::vector<gllmg_problem*>& G, const std::vector<const double*>& bu,
                  const std::vector<double*>& xu, double rtol, int maxit, hipStream_t s,
-                 GroupMem& m, std::vector<GroupOut>& out) {
+                 std::vector<GroupOut>& out) {
   const int K = (int)G.size();
   gllmg_problem* P0 = G[0];
+  GLLMG_CHECK(K >= 1 && K <= kGroupMax, GLLMG_EINVAL, "launch group size out of range");
+  struct {
+    int64_t* dlt;
+    int* act;
+    double* sc;
+    int* hact;
+    double* hsc;
+  } m{P0->gdlt, P0->gact, P0->gsc, P0->ghact, P0->ghsc};
   const int64_t N = P0->L[0].g.N;
   std::vector<int64_t> hd(K);
   for (int k = 0; k < K; ++k) hd[k] = G[k]->ws - P0->ws;
@@ -1194,6 +1196,28 @@ gllmg_status guard(Fn&& fn) {
   }
 }
 
+// Everything gllmg_setup made besides the host object itself.
+void release_resources(gllmg_problem* P) {
+  drop_graph(P);
+  if (P->cap) (void)hipStreamDestroy(P->cap);
+  if (P->xs) (void)hipStreamDestroy(P->xs);
+  if (P->sv.ev) (void)hipEventDestroy(P->sv.ev);
+  if (P->bev) (void)hipEventDestroy(P->bev);
+  if (P->gev) (void)hipEventDestroy(P->gev);
+  if (P->owns_ws) (void)hipFree(P->ws);
+  if (P->hbuf) (void)hipHostFree(P->hbuf);
+  if (P->bhost) (void)hipHostFree(P->bhost);
+  if (P->ghact) (void)hipHostFree(P->ghact);
+  if (P->ghsc) (void)hipHostFree(P->ghsc);
+  P->cap = P->xs = nullptr;
+  P->sv.ev = P->bev = P->gev = nullptr;
+  P->hbuf = nullptr;
+  P->bhost = nullptr;
+  P->ghact = nullptr;
+  P->ghsc = nullptr;
+  if (P->owns_ws) P->ws = nullptr;
+}
+
 const Level& level_of(const gllmg_problem* P, int l) {
   GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
   GLLMG_CHECK(l >= 0 && l < (int)P->L.size(), GLLMG_EINVAL, "level out of range");
@@ -1291,28 +1315,28 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
       gllmg_problem* p;
       bool armed = true;
       ~Free() {
-        if (armed && p->owns_ws) (void)hipFree(p->ws);
-        if (armed && p->hbuf) (void)hipHostFree(p->hbuf);
-        if (armed && p->bhost) (void)hipHostFree(p->bhost);
+        if (armed) release_resources(p);
       }
     } guard_free{P.get()};
     Arena A;
     A.base = P->ws;
     A.size = P->ws_bytes;
     layout(P.get(), specs, A);
+    // every host-side resource of the problem's later calls (pinned images, internal streams,
+    // events) is made here: no later call allocates
     GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
     GLLMG_HIP(hipHostMalloc((void**)&P->bhost, sizeof(BatchProblem), hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&P->ghact, sizeof(int) * kGroupMax, hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&P->ghsc, sizeof(double) * 4 * kGroupMax, hipHostMallocDefault));
+    GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
+    GLLMG_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+    GLLMG_HIP(hipEventCreateWithFlags(&P->sv.ev, hipEventDisableTiming));
+    GLLMG_HIP(hipEventCreateWithFlags(&P->bev, hipEventDisableTiming));
+    GLLMG_HIP(hipEventCreateWithFlags(&P->gev, hipEventDisableTiming));
     setup_impl(P.get(), map, mu, s);
     fill_ctab(P.get(), s);
-    if (P->L.back().Ainv64) {
-      // capture the solve's V-cycle now, while nothing else of this problem is in flight
-      try {
-        capture_vcycle(P.get());
-      } catch (const Error&) {
-        (void)hipGetLastError();
-        P->use_graph = false;
-      }
-    }
+    // capture the solve's V-cycle now, while nothing else of this problem is in flight
+    recapture(P.get());
     guard_free.armed = false;
     *out = P.release();
     return GLLMG_OK;
@@ -1322,13 +1346,7 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
 gllmg_status gllmg_destroy(gllmg_problem* P) {
   return guard([&]() {
     if (!P) return GLLMG_OK;
-    drop_graph(P);
-    if (P->cap) (void)hipStreamDestroy(P->cap);
-    if (P->xs) (void)hipStreamDestroy(P->xs);
-    if (P->sv.ev) (void)hipEventDestroy(P->sv.ev);
-    if (P->owns_ws) (void)hipFree(P->ws);
-    if (P->hbuf) (void)hipHostFree(P->hbuf);
-    if (P->bhost) (void)hipHostFree(P->bhost);
+    release_resources(P);
     delete P;
     return GLLMG_OK;
   });
@@ -1361,9 +1379,10 @@ gllmg_status gllmg_set_lmax(gllmg_problem* P, int32_t level, double lmax) {
     level_of(P, level);
     GLLMG_CHECK(lmax > 0.0 && std::isfinite(lmax), GLLMG_EINVAL, "lmax must be positive");
     P->L[level].lmax = lmax;
-    drop_graph(P);  // the captured V-cycle holds the old Chebyshev coefficients
-    if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
     fill_ctab(P, P->xs);
+    // the captured V-cycle holds the old Chebyshev coefficients: capture it again now, so that
+    // the next solve replays a graph without building one
+    recapture(P);
     return GLLMG_OK;
   });
 }
@@ -1381,6 +1400,7 @@ gllmg_status gllmg_set_graphs(gllmg_problem* P, int32_t enable) {
     GLLMG_CHECK(P != nullptr, GLLMG_EINVAL, "problem is NULL");
     P->use_graph = enable != 0;
     if (!P->use_graph) drop_graph(P);
+    else if (!P->vexec) recapture(P);
     return GLLMG_OK;
   });
 }
@@ -1562,9 +1582,7 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
   return guard([&]() {
     GLLMG_CHECK(count >= 0 && (count == 0 || (probs && b && x)), GLLMG_EINVAL, "NULL argument");
     hipStream_t cs = (hipStream_t)stream;
-    hipEvent_t start = nullptr;
-    GLLMG_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    GLLMG_HIP(hipEventRecord(start, cs));
+    if (count == 0) return GLLMG_OK;
     std::vector<int> live;
     gllmg_status worst = GLLMG_OK;
     auto fail = [&](int i, gllmg_status st) {
@@ -1578,12 +1596,15 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       GLLMG_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), GLLMG_EINVAL,
                   "a problem appears twice in the batch");
     }
+    hipEvent_t start = probs[0]->bev;
+    GLLMG_HIP(hipEventRecord(start, cs));
     const auto t0 = std::chrono::steady_clock::now();
     const bool args_ok = (mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG) && rtol > 0.0 && maxit >= 1;
     // Problems of one shape (two or more) are solved in lockstep by launch groups, one group at
     // a time on the first problem's internal stream; measured faster than the one-workgroup
     // solver at every size of the 4^3-element batch (729 nodes: 3.7 vs 4.4 ms for 65 problems;
-    // 4913 nodes: 6.0 vs 21.8 ms for 67). Their buffers are allocated before any launch.
+    // 4913 nodes: 6.0 vs 21.8 ms for 67). A shape with more than kGroupMax problems forms
+    // several groups.
     std::vector<std::vector<int>> shapes;
     std::vector<char> in_group(count, 0);
     if (args_ok && mode == GLLMG_MODE_PCG) {
@@ -1593,7 +1614,7 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
         if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
         bool placed = false;
         for (auto& sh : shapes)
-          if (same_shape(probs[sh[0]], P)) {
+          if ((int)sh.size() < kGroupMax && same_shape(probs[sh[0]], P)) {
             sh.push_back(i);
             placed = true;
             break;
@@ -1616,11 +1637,6 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
       pers[i] = 1;
       groups[P->L[0].n].push_back(i);
-    }
-    std::vector<std::unique_ptr<GroupMem>> gmem;
-    for (const auto& sh : shapes) {
-      gmem.emplace_back(new GroupMem);
-      group_alloc(*gmem.back(), (int)sh.size());
     }
     for (int n0 = 2; n0 <= 17; ++n0) {
       const auto& idx = groups[n0];
@@ -1668,7 +1684,6 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
     for (size_t q = 0; q < shapes.size(); ++q) {
       GroupRun& r = runs[q];
       gllmg_problem* P0 = probs[shapes[q][0]];
-      if (!P0->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P0->xs, hipStreamNonBlocking));
       GLLMG_HIP(hipStreamWaitEvent(P0->xs, start, 0));
       r.s = P0->xs;
       for (int i : shapes[q]) {
@@ -1684,7 +1699,7 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       workers.emplace_back([&, q]() {
         GroupRun& r = runs[q];
         try {
-          group_solve(r.G, r.gb, r.gx, rtol, maxit, r.s, *gmem[q], r.res);
+          group_solve(r.G, r.gb, r.gx, rtol, maxit, r.s, r.res);
         } catch (...) {
           r.err = std::current_exception();
         }
@@ -1702,7 +1717,6 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
     for (int i = 0; i < count; ++i) {
       if (pers[i] || grouped[i]) continue;
       gllmg_problem* P = probs[i];
-      if (!P->xs) GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
       GLLMG_HIP(hipStreamWaitEvent(P->xs, start, 0));
       const gllmg_status st = gllmg_solve_begin(P, mode, b[i], x[i], rtol, maxit, P->xs);
       if (st != GLLMG_OK) {
@@ -1770,11 +1784,9 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
         if (si != GLLMG_OK) fail(i, si);
         if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
       }
-      hipEvent_t e = nullptr;
-      GLLMG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      hipEvent_t e = r.G[0]->gev;
       GLLMG_HIP(hipEventRecord(e, r.s));
       GLLMG_HIP(hipStreamWaitEvent(cs, e, 0));
-      (void)hipEventDestroy(e);
     }
 
     if (std::find(pers.begin(), pers.end(), 1) != pers.end()) {
@@ -1802,7 +1814,6 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
         if (si == GLLMG_EBREAKDOWN) g_err = "breakdown: non-finite residual or p^T A p <= 0";
       }
     }
-    (void)hipEventDestroy(start);
     if (worst == GLLMG_ENOTCONV) g_err = "maximum number of iterations reached in a problem";
     return worst;
   });

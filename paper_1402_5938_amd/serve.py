@@ -83,8 +83,11 @@ class Record:
 
 class Server:
     def __init__(self, hbm_budget: int, max_active: int = 64, nstreams: int = 8,
-                 keep_solutions: bool = False, setup_threads: int = 6):
+                 keep_solutions: bool = False, setup_threads: int = 6, host_rhs: bool = False):
+        """host_rhs: a request's nodal f is drawn on the host (numpy, the same values as
+        Problem.nodal_rhs) and uploaded, instead of drawn on the device."""
         import torch
+        self.host_rhs = host_rhs
         self.ledger = HbmLedger(hbm_budget)
         self.max_active = max_active
         self.streams = [torch.cuda.Stream() for _ in range(nstreams)]
@@ -115,7 +118,10 @@ class Server:
                 with torch.cuda.stream(s):
                     P = gllmg.Problem(request_config(req.problem), req.problem.map,
                                       req.problem.mu, stream=s)
-                    f = req.problem.nodal_rhs_device()
+                    if self.host_rhs and req.problem.f_seed is not None:
+                        f = torch.from_numpy(req.problem.nodal_rhs()).to("cuda")
+                    else:
+                        f = req.problem.nodal_rhs_device()
                     if f is None:
                         f = P.eval_field(req.problem.f, stream=s)
                     b = P.rhs(f, stream=s)

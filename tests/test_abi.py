@@ -71,3 +71,45 @@ def test_binding_shares_torchs_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def _function_bodies(src):
+    """(name, body) of every top-level function definition in a C++ source (brace matching)."""
+    out = []
+    for m in re.finditer(r"\n(?:[A-Za-z_][\w:<>,*& ]*\s+)?([A-Za-z_]\w*)\s*\([^;{)]*(?:\)[^;{]*)?\)\s*(?:const\s*)?\{", src):
+        depth, i = 1, m.end()
+        while depth and i < len(src):
+            depth += {"{": 1, "}": -1}.get(src[i], 0)
+            i += 1
+        out.append((m.group(1), src[m.end():i]))
+    return out
+
+
+def test_no_allocation_after_setup():
+    """Device or pinned memory, streams and events are made only by gllmg_setup; the V-cycle
+    graph is instantiated only by the capture helper (called at setup, by gllmg_set_lmax and
+    by gllmg_set_graphs). So gllmg_plan's footprint is exact and a batch allocates nothing."""
+    csrc = os.path.join(ROOT, "paper_1402_5938_amd", "csrc")
+    allowed = {"hipMalloc": {"gllmg_setup"}, "hipHostMalloc": {"gllmg_setup"},
+               "hipExtMallocWithFlags": set(), "hipMallocAsync": set(), "hipMallocManaged": set(),
+               "hipStreamCreateWithFlags": {"gllmg_setup"}, "hipStreamCreate": set(),
+               "hipEventCreateWithFlags": {"gllmg_setup"}, "hipEventCreate": set(),
+               "hipGraphInstantiate": {"capture_vcycle"}}
+    found = {}
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith((".hip", ".h")):
+            continue
+        src = open(os.path.join(csrc, fn)).read()
+        src = re.sub(r"//[^\n]*", "", src)
+        for call in allowed:
+            for m in re.finditer(r"\b%s\s*\(" % call, src):
+                # the innermost enclosing function: the last definition starting before m
+                owner = None
+                for name, body in _function_bodies(src):
+                    start = src.find(body)
+                    if start <= m.start() < start + len(body):
+                        owner = name
+                found.setdefault(call, set()).add(owner)
+    for call, owners in found.items():
+        assert owners <= allowed[call], (call, owners)
+    assert found.get("hipMalloc") == {"gllmg_setup"}

@@ -18,9 +18,10 @@ from paper_1402_5938_amd import inputs
 pytestmark = pytest.mark.gpu
 
 
-def test_fp32_vcycle_pieces_against_oracle():
+@pytest.mark.parametrize("p", [8, 12])
+def test_fp32_vcycle_pieces_against_oracle(p):
     import torch
-    G, H = build_pair(3, (2, 2, 2), 8, hierarchy="p", vcycle_prec="f32")
+    G, H = build_pair(3, (2, 2, 2), p, hierarchy="p", vcycle_prec="f32")
     for l, lv in enumerate(H.levels[:-1]):
         G.set_lmax(l, lv.lmax)
     m = H.fine.mesh

@@ -141,6 +141,126 @@ def test_coefficient_integral_converges_spectrally():
     assert all(diffs[i + 1] < 0.2 * diffs[i] for i in range(len(diffs) - 1)), diffs
 
 
+def test_exp_sine_product_values_fixed_by_the_workload():
+    """The 3D workload's coefficient exp(4.6 sx sy sz) (sW = sin 2 pi W): its maximum e^4.6 sits
+    at (1/4, 1/4, 1/4), its minimum e^-4.6 at (3/4, 1/4, 1/4), it is exactly 1 on every plane
+    x_i = 0 or 1/2, so the contrast max/min over any point set containing the two extrema is
+    e^9.2 ~ 9.9e3 (the stated contrast of about 1e4). A phase shifts the extremum to
+    (1/4 - phase). A wrong amplitude, a missing 2 pi or a wrong phase sign fails one of these."""
+    from oracle.fields import eval_scalar
+    mu = inputs.mu_exp_sine_product(4.6)
+    pts = np.array([[0.25, 0.25, 0.25], [0.75, 0.25, 0.25], [0.25, 0.75, 0.75]])
+    np.testing.assert_allclose(eval_scalar(mu, pts), [math.exp(4.6), math.exp(-4.6), math.exp(4.6)],
+                               rtol=1e-14)
+    rng = np.random.default_rng(5)
+    for axis in range(3):
+        for plane in (0.0, 0.5):
+            q = rng.uniform(0, 1, (50, 3))
+            q[:, axis] = plane
+            np.testing.assert_allclose(eval_scalar(mu, q), 1.0, atol=1e-14)
+    # contrast over the nodes of an unwarped 4^3 mesh at p = 2 (nodes on the quarter planes)
+    m = fem.Mesh(3, (4, 4, 4), 2, inputs.map_identity(), mu)
+    v = eval_scalar(mu, m.x)
+    assert abs(v.max() / v.min() - math.exp(9.2)) < 1e-9 * math.exp(9.2)
+    # phases: the maximum moves to 1/4 - phase (2D: two factors)
+    ph = (0.1, 0.3, 0.05)
+    mu3 = inputs.mu_exp_sine_product(2.0, ph)
+    assert abs(eval_scalar(mu3, np.array([[0.15, -0.05, 0.2]]))[0] - math.exp(2.0)) < 1e-13
+    mu2 = inputs.mu_exp_sine_product(1.5, ph[:2])
+    assert abs(eval_scalar(mu2, np.array([[0.15, -0.05]]))[0] - math.exp(1.5)) < 1e-13
+    assert abs(eval_scalar(mu2, np.array([[0.65, -0.05]]))[0] - math.exp(-1.5)) < 1e-13
+
+
+def test_exp_fourier_single_modes_closed_form():
+    """One mode (J = 1): g = sqrt(2) a cos(2 pi k.x + phi). With k = e_axis, phi = pi/2 this is
+    -sqrt(2) a sin(2 pi x_axis): the values at x_axis = 0, 1/4, 3/4 are 1, e^{-sqrt2 a},
+    e^{+sqrt2 a}, and the other coordinates do not matter. A diagonal k = (1, 1, -1) with phi = 0
+    is periodic along (1, -1, 0) and equals e^{sqrt2 a} wherever x + y - z is an integer."""
+    from oracle.fields import eval_scalar
+    rng = np.random.default_rng(1)
+    for axis in range(3):
+        k = [0.0, 0.0, 0.0]
+        k[axis] = 1.0
+        a = 0.8
+        mu = inputs.mu_exp_fourier(np.array([k + [a, math.pi / 2]]))
+        q = rng.uniform(0, 1, (3, 3))
+        q[:, axis] = [0.0, 0.25, 0.75]
+        np.testing.assert_allclose(eval_scalar(mu, q),
+                                   [1.0, math.exp(-math.sqrt(2) * a), math.exp(math.sqrt(2) * a)],
+                                   rtol=1e-14)
+    mu = inputs.mu_exp_fourier(np.array([[1.0, 1.0, -1.0, 0.5, 0.0]]))
+    q = rng.uniform(0, 1, (20, 2))
+    pts = np.stack([q[:, 0], q[:, 1], q[:, 0] + q[:, 1] - 1.0], axis=1)
+    np.testing.assert_allclose(eval_scalar(mu, pts), math.exp(math.sqrt(2) * 0.5), rtol=1e-13)
+
+
+def test_exp_fourier_batch_field_is_standard_normal_and_mean_free():
+    """The batched workload's log-coefficient g = sqrt(2/J) sum_j a_j cos(2 pi k_j.x + phi_j),
+    a_j ~ N(0,1), phi_j ~ U[0, 2 pi), is N(0,1) at every point over the draws: across the 256
+    problems' spawned seeds ln mu at a fixed point has sample mean ~ 0 (standard error 1/16)
+    and sample variance ~ 1 (standard error ~0.09). Every k_j is a nonzero integer vector, so
+    each draw's g integrates to exactly 0 over the unit cube (checked by high-order GLL
+    quadrature). A wrong sqrt(2/J), a missing 2 pi or a non-integer frequency fails."""
+    from oracle.fields import eval_scalar
+    probs = inputs.batched_problems(seed=0, count=256)
+    pts = np.array([[0.1, 0.2, 0.3], [0.5, 0.5, 0.5], [0.9, 0.35, 0.65], [0.0, 0.0, 0.0]])
+    L = np.array([np.log(eval_scalar(pb.mu, pts)) for pb in probs])     # (256, npts)
+    for j in range(pts.shape[0]):
+        assert abs(L[:, j].mean()) < 0.25, (j, L[:, j].mean())
+        assert abs(L[:, j].var() - 1.0) < 0.3, (j, L[:, j].var())
+    assert abs(L.mean()) < 0.15 and abs(L.var() - 1.0) < 0.2
+    m = fem.Mesh(3, (2, 2, 2), 12, inputs.map_identity(), inputs.field_const(1.0))
+    _, wdet, _, _ = m.geometry()
+    for pb in probs[:8]:
+        _, _, mu, _ = fem.Mesh(3, (2, 2, 2), 12, inputs.map_identity(), pb.mu).geometry()
+        assert abs(np.sum(wdet * np.log(mu))) < 1e-9
+
+
+def test_warp_map_values_and_jacobian():
+    """Cyclic sine warp, a = 0.05: Phi(1/4,1/4,1/4) = (1/4 + a)(1,1,1) and Phi(3/4,1/4,1/4) moves
+    y and z by -a and x by +a; on the face X = 0 only x moves (by a sY sZ); 2D: Phi(1/4,3/4) =
+    (1/4 - a, 3/4 + a). The oracle's isoparametric detJ at p = 12 agrees with central
+    differences of the map to the interpolation error of the degree-12 geometry."""
+    a = 0.05
+    P = eval_map(inputs.map_warp_sine(a), np.array([[0.25, 0.25, 0.25], [0.75, 0.25, 0.25]]))
+    np.testing.assert_allclose(P, [[0.25 + a] * 3, [0.75 + a, 0.25 - a, 0.25 - a]], atol=1e-15)
+    q = np.random.default_rng(2).uniform(0, 1, (10, 3))
+    q[:, 0] = 0.0
+    P = eval_map(inputs.map_warp_sine(a), q)
+    np.testing.assert_allclose(P[:, 1:], q[:, 1:], atol=1e-15)
+    np.testing.assert_allclose(P[:, 0], a * np.sin(2 * math.pi * q[:, 1]) * np.sin(2 * math.pi * q[:, 2]),
+                               atol=1e-15)
+    P2 = eval_map(inputs.map_warp_sine(a), np.array([[0.25, 0.75]]))
+    np.testing.assert_allclose(P2, [[0.25 - a, 0.75 + a]], atol=1e-15)
+    m = fem.Mesh(3, (1, 1, 1), 12, inputs.map_warp_sine(a), inputs.field_const(1.0))
+    detJ = m.geometry()[3].reshape(-1)        # element-local points, z slowest, x fastest
+    h = 1e-6
+    xi, _ = gll.gll(12)
+    Z, Y, Xg = np.meshgrid((xi + 1) / 2, (xi + 1) / 2, (xi + 1) / 2, indexing="ij")
+    ref = np.stack([Xg.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    J = np.zeros((ref.shape[0], 3, 3))
+    for b in range(3):
+        e = np.zeros(3)
+        e[b] = h
+        J[:, :, b] = (eval_map(inputs.map_warp_sine(a), ref + e) - eval_map(inputs.map_warp_sine(a), ref - e)) / (2 * h)
+    det_fd = np.linalg.det(J) / 8.0          # reference element [-1,1]^3 -> [0,1]^3
+    # degree-12 interpolation of one full sine period per element: ~5e-7 relative
+    np.testing.assert_allclose(detJ, det_fd, rtol=2e-6)
+    assert np.ptp(det_fd) * 8 > 0.15             # the warp really varies the Jacobian
+
+
+def test_sin_product_and_cos2_sum_values():
+    """sin_product: amp at the centre, 0 on the boundary; cos2_sum (the paper's coefficient form
+    1 + 1e6 sum cos^2(2 pi x_i)): c0 + d c1 at the origin and c0 where every 2 pi x_i = pi/2."""
+    from oracle.fields import eval_scalar
+    f = inputs.f_sin_product(3.0, 1.0)
+    np.testing.assert_allclose(eval_scalar(f, np.array([[0.5, 0.5], [0.0, 0.3], [0.7, 1.0]])),
+                               [3.0, 0.0, 0.0], atol=1e-15)
+    c = inputs.mu_cos2_sum(1.0, 1e6, 2.0)
+    v = eval_scalar(c, np.array([[0.0, 0.0, 0.0], [0.25, 0.75, 0.25], [0.25, 0.5, 0.75]]))
+    np.testing.assert_allclose(v, [1.0 + 3e6, 1.0, 1.0 + 1e6], rtol=1e-12)
+
+
 def test_geometry_rejects_folded_map():
     with pytest.raises(ValueError):
         m = fem.Mesh(2, (2, 2), 2, inputs.map_warp_sine(0.5), inputs.field_const(1.0))

@@ -212,16 +212,13 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 //   (FP32 n = 17, FP64 n = 12, 13), else from a register copy of x;
 // * the x-flux goes to the second LDS tile, still unused, as soon as it is formed, the
 //   y-flux once every thread has finished reading the input tile;
-// * the contractions run in chunks of HP_CHUNK terms, software-pipelined: the LDS reads of
+// * the contractions run in chunks of C terms, software-pipelined: the LDS reads of
 //   chunk s+1 are issued before the products of chunk s, with a scheduling barrier between
 //   chunks so that the compiler does not hoist all reads of a plane (which is what fills the
 //   registers otherwise).
 // The sums are formed in the same order as in elem3d.
 // chunk length: measured best 1 in FP64 and 2 in FP32 (n = 13, 15, 17; FP64 with 1 against 3:
 // 12-19% faster)
-#ifndef GLLMG_HP_CHUNK
-#define GLLMG_HP_CHUNK (sizeof(T) == 8 ? 1 : 2)
-#endif
 template <int N, typename T, int EPB>
 __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict__ F,
                                           const T* __restrict__ G, const T* __restrict__ Dm,
@@ -229,7 +226,7 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
                                           T* __restrict__ sA, T* __restrict__ sB,
                                           T* __restrict__ sD) {
   constexpr int NN = N * N, NNN = N * N * N, P = N - 1;
-  constexpr int C = GLLMG_HP_CHUNK, NC = (N + C - 1) / C, S = N * NC;
+  constexpr int C = sizeof(T) == 8 ? 1 : 2, NC = (N + C - 1) / C, S = N * NC;
   const bool act = t < EPB * NN;
   const int tt = act ? t : 0;
   const int le = tt / NN;
@@ -408,17 +405,15 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
   }
 }
 
-// elem3d or, from n = GLLMG_HIGHP_N on, elem3d_hp
-#ifndef GLLMG_HIGHP_N
-#define GLLMG_HIGHP_N 12
-#endif
+// elem3d or, from n = kHighpN on, elem3d_hp
+constexpr int kHighpN = 12;
 template <int N, typename T, int EPB>
 __device__ __forceinline__ void elem3d_any(const T* __restrict__ x, T* __restrict__ F,
                                            const T* __restrict__ G, const T* __restrict__ Dm,
                                            const Grid& g, int neumann, uint32_t ebase, int t,
                                            T* __restrict__ sA, T* __restrict__ sB,
                                            T* __restrict__ sD) {
-  if constexpr (N >= GLLMG_HIGHP_N)
+  if constexpr (N >= kHighpN)
     elem3d_hp<N, T, EPB>(x, F, G, Dm, g, neumann, ebase, t, sA, sB, sD);
   else
     elem3d<N, T, EPB>(x, F, G, Dm, g, neumann, ebase, t, sA, sB, sD);

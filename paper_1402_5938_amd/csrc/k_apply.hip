@@ -26,7 +26,7 @@ namespace {
 template <int N, typename T, int EPB>
 struct Threads3d {
   static constexpr int v =
-      (N >= GLLMG_HIGHP_N && sizeof(T) == 4) ? (EPB * N * N + 63) / 64 * 64 : EPB * N * N;
+      (N >= kHighpN && sizeof(T) == 4) ? (EPB * N * N + 63) / 64 * 64 : EPB * N * N;
 };
 
 template <int N, typename T, int EPB, bool GR>
@@ -116,10 +116,7 @@ k_apply_box(const T* __restrict__ x, const T* __restrict__ G, const T* __restric
 }
 
 constexpr int64_t kP1MaxNodes64 = 16384, kP1MaxNodes32 = 65536;
-#ifndef GLLMG_BOX_MAX_NODES
-#define GLLMG_BOX_MAX_NODES 65536
-#endif
-constexpr int64_t kBoxMaxNodes = GLLMG_BOX_MAX_NODES;
+constexpr int64_t kBoxMaxNodes = 65536;
 
 template <int N, int DIM, typename T, bool GR>
 __global__ void __launch_bounds__(kGT)

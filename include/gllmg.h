@@ -183,6 +183,21 @@ gllmg_status gllmg_diag(const gllmg_problem* prob, int32_t level, gllmg_prec pre
 gllmg_status gllmg_apply(const gllmg_problem* prob, int32_t level, gllmg_prec prec, int32_t neumann,
                          const void* x, void* y, void* stream);
 
+/* The product of gllmg_apply for callers that cannot allocate device memory at any point of
+ * their run (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation). Same arguments, kernels and results (bit for bit) as gllmg_apply; the element
+ * vectors that the two-kernel product passes from its element pass to its node-order sum are
+ * kept in a static device array of the library (32 MiB per device, 33,554,432 bytes, present
+ * from the moment the library is loaded on a device) instead of the problem's workspace.
+ * Limit: E * (p+1)^d * sizeof(element) <= 33,554,432 bytes on the level (for example 16^3
+ * hexes at p = 8 or 8^3 at p = 16 in FP64); a larger level returns EINVAL and enqueues nothing.
+ * Every call on one device shares that device's array: calls that overlap in time on one
+ * device (different streams, different problems or threads) race and give wrong results, so
+ * the caller orders them (one stream, or events). The array keeps the last call's contents;
+ * nothing in it needs to start at zero. Asynchronous. */
+gllmg_status gllmg_apply_noalloc(const gllmg_problem* prob, int32_t level, gllmg_prec prec,
+                                 int32_t neumann, const void* x, void* y, void* stream);
+
 /* `steps` Jacobi sweeps (omega) or one Chebyshev polynomial of degree `steps` on
  * [cheb_lo lambda, lambda] of D^{-1} A (§3.2), updating x in place. zero_guess = 1 treats x as
  * 0 on entry (one product fewer). Uses the level's internal scratch. Asynchronous. */

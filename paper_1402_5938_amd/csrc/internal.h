@@ -216,6 +216,12 @@ void launch_apply(const Level& L, int prec, int neumann, const void* x, const Ep
                   hipStream_t s);
 size_t face_buffer_elems(const Level& L);
 
+// The allocation-free product's element-vector buffer: a file-scope device array of this many
+// bytes (one per device, shared by every call on that device). static_scratch(dev) returns its
+// device address on device dev, looked up once per device.
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+void* static_scratch(int dev);
+
 // Node-order sum of element vectors R (layout [e][k][j][i] on level L) followed by the epilogue.
 void launch_gather_epi(const Level& L, int prec, const void* R, const Epi& ep, hipStream_t s);
 

@@ -167,6 +167,8 @@ struct gllmg_problem {
   double* ghsc = nullptr;
   hipEvent_t bev = nullptr;  // the batch's start, recorded on the caller's stream
   hipEvent_t gev = nullptr;  // the end of the group this problem leads
+  int dev = -1;                 // the device current at setup
+  void* sscratch = nullptr;     // that device's static scratch (gllmg_apply_noalloc)
 };
 
 namespace gllmg {
@@ -1333,6 +1335,8 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
     GLLMG_HIP(hipEventCreateWithFlags(&P->sv.ev, hipEventDisableTiming));
     GLLMG_HIP(hipEventCreateWithFlags(&P->bev, hipEventDisableTiming));
     GLLMG_HIP(hipEventCreateWithFlags(&P->gev, hipEventDisableTiming));
+    GLLMG_HIP(hipGetDevice(&P->dev));
+    P->sscratch = static_scratch(P->dev);
     setup_impl(P.get(), map, mu, s);
     fill_ctab(P.get(), s);
     // capture the solve's V-cycle now, while nothing else of this problem is in flight
@@ -1464,6 +1468,29 @@ gllmg_status gllmg_apply(const gllmg_problem* P, int32_t level, gllmg_prec prec,
     check_ptr(y, pr == 0 ? 8 : 4, "y");
     GLLMG_CHECK(x != y, GLLMG_EINVAL, "x and y must not alias");
     apply_level(const_cast<gllmg_problem*>(P), level, pr, neumann ? 1 : 0, x, y, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
+gllmg_status gllmg_apply_noalloc(const gllmg_problem* P, int32_t level, gllmg_prec prec,
+                                 int32_t neumann, const void* x, void* y, void* stream) {
+  return guard([&]() {
+    const Level& L = level_of(P, level);
+    const int pr = prec_index(P, prec);
+    check_ptr(x, pr == 0 ? 8 : 4, "x");
+    check_ptr(y, pr == 0 ? 8 : 4, "y");
+    GLLMG_CHECK(x != y, GLLMG_EINVAL, "x and y must not alias");
+    const size_t need = face_buffer_elems(L) * (pr == 0 ? sizeof(double) : sizeof(float));
+    GLLMG_CHECK(need <= kStaticScratchBytes, GLLMG_EINVAL,
+                "the level's element vectors (" + std::to_string(need) +
+                    " bytes) exceed the static scratch of gllmg_apply_noalloc (" +
+                    std::to_string(kStaticScratchBytes) + " bytes)");
+    GLLMG_CHECK(P->sscratch != nullptr, GLLMG_EDEVICE, "no static scratch on the problem's device");
+    Epi ep;
+    ep.y = y;
+    Level& Lw = const_cast<gllmg_problem*>(P)->L[level];
+    launch_apply(Lw, pr, neumann ? 1 : 0, x, ep, P->sscratch, (hipStream_t)stream);
+    ++Lw.applies;
     return GLLMG_OK;
   });
 }

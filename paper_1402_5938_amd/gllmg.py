@@ -61,7 +61,7 @@ EXPORTS = ["gllmg_last_error", "gllmg_config_default", "gllmg_plan", "gllmg_setu
            "gllmg_destroy", "gllmg_num_levels", "gllmg_level_info", "gllmg_set_lmax",
            "gllmg_set_graphs", "gllmg_set_persistent",
            "gllmg_node_coords", "gllmg_eval_field", "gllmg_rhs", "gllmg_diag", "gllmg_apply",
-           "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve",
+           "gllmg_apply_noalloc", "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve",
            "gllmg_solve_begin", "gllmg_solve_poll", "gllmg_solve_end", "gllmg_batch_solve"]
 
 
@@ -96,6 +96,7 @@ def lib():
     L.gllmg_rhs.argtypes = [vp, vp, vp, vp]
     L.gllmg_diag.argtypes = [vp, i32, i32, vp, vp]
     L.gllmg_apply.argtypes = [vp, i32, i32, i32, vp, vp, vp]
+    L.gllmg_apply_noalloc.argtypes = [vp, i32, i32, i32, vp, vp, vp]
     L.gllmg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp]
     L.gllmg_prolong.argtypes = [vp, i32, i32, vp, vp, vp]
     L.gllmg_restrict.argtypes = [vp, i32, i32, vp, vp, vp]
@@ -298,6 +299,14 @@ class Problem:
         y = torch.empty_like(x) if y is None else y
         _check(lib().gllmg_apply(self.h, l, prec, 1 if neumann else 0, _ptr(x), _ptr(y),
                                  _stream(stream)))
+        return y
+
+    def apply_noalloc(self, x, y, l=0, prec=None, neumann=False, stream=None):
+        """gllmg_apply_noalloc: the product with the library's static element-vector buffer;
+        y must be given (this call allocates nothing)."""
+        prec = _prec_of(x) if prec is None else prec
+        _check(lib().gllmg_apply_noalloc(self.h, l, prec, 1 if neumann else 0, _ptr(x), _ptr(y),
+                                         _stream(stream)))
         return y
 
     def smooth(self, b, x, steps, l=0, zero_guess=False, stream=None):

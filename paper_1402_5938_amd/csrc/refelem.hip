@@ -6,8 +6,8 @@
 // symmetric tridiagonal Jacobi matrix of P^{(1,1)} (Golub-Welsch): zero diagonal and
 // off-diagonal b_k = sqrt(k (k+2) / ((2k+1)(2k+3))), k = 1..p-2. They are found by Sturm
 // bisection and polished by Newton's method on P_{p-1} - x P_p. Weights: 2 / (p (p+1) P_p^2).
-// Derivative matrix (Deville, Fischer and Mund, cited in §1): D_ij = P_p(x_i) / (P_p(x_j)
-// (x_i - x_j)) for i != j, D_00 = -p(p+1)/4, D_pp = p(p+1)/4, D_ii = 0 otherwise.
+// Derivative matrix D_ij = l_j'(x_i) in barycentric form from the computed nodes (off-diagonal
+// (lam_j / lam_i) / (x_i - x_j), diagonal minus the row's other entries; see ref_element).
 #include <algorithm>
 #include <cmath>
 

@@ -18,6 +18,8 @@ operators), written plainly and without blocking, fusion or reordering:
                  (§2.1, §2.3)
 * ``transfer``   prolongation P_ij = phi_j^{k-1}(p_i) by direct evaluation, restriction P^T
                  (§2.2, Eq. (Pstencil))
+* ``relax``      multicolor SSOR, l1-Jacobi and element block-Jacobi smoothers (§3.2, §4.3,
+                 §4.4.3) on the assembled interior matrix
 * ``mg``         Jacobi and Chebyshev-Jacobi smoothers, the Lanczos/Arnoldi lambda_max
                  estimate, the h-/p-hierarchy, the V-cycle, multigrid as solver and the
                  multigrid-preconditioned CG of Algorithm 1 (§3, §4.2-§4.3)

@@ -15,8 +15,10 @@ Test infrastructure only (see the package docstring).
   takes p -> ceil(p/2) down to 1 and then halves the elements; every level is rediscretized
   with its own mesh, order and mu at its own quadrature points (§2.3). A coarser level is
   added only while it keeps at least one interior unknown.
-* V-cycle with zero initial guess, nu pre- and post-smoothing steps per level, restriction
-  P^T, exact (dense Cholesky) solve on the coarsest level.
+* V-cycle with zero initial guess, nu_pre pre- and nu_post post-smoothing steps per level,
+  restriction P^T, exact (dense Cholesky) solve on the coarsest level.
+* The other smoothers the paper compares (multicolor SSOR, l1-Jacobi, element block Jacobi,
+  §3.2, §4.3, §4.4.3) are in ``relax``.
 * Multigrid as solver: x <- x + V(b - A x). PCG: Algorithm 1 with one V-cycle per iteration.
   Both stop when ||r||_2 <= rtol ||r_0||_2 (§4.3: the discrete residual norm); the count is
   the number of V-cycles applied to update x.
@@ -32,6 +34,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .fem import LevelOperator, Mesh, load_vector, nodal_field
+from .relax import BlockJacobi, ColoredSSOR, jacobi_type, l1_row_sums
 from .splitmix import start_vector
 from .transfer import Transfer
 
@@ -134,13 +137,22 @@ class Level:
     to_coarse: Optional[Transfer] = None     # transfer between this level and the next coarser
     chol: object = None                      # coarsest level: Cholesky factor of A_II
     idx: Optional[np.ndarray] = None
+    relax: object = None                     # SSOR sweeps or block inverses (those smoothers)
+    l1inv: Optional[np.ndarray] = None       # l1-Jacobi: 1 / sum_j |A_ij|
 
 
 class Hierarchy:
     def __init__(self, dim, nelem, p, map_desc, mu_desc, hierarchy="p", max_levels=0,
-                 smoother="chebyshev", nu=4, omega=2.0 / 3.0, cheb_lo=0.25, cheb_safety=1.0,
-                 eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False):
-        self.smoother, self.nu, self.omega = smoother, nu, omega
+                 smoother="chebyshev", nu=4, omega=None, cheb_lo=0.25, cheb_safety=1.0,
+                 eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False,
+                 nu_post=None):
+        if smoother not in ("jacobi", "chebyshev", "ssor", "l1jacobi", "blockjacobi"):
+            raise ValueError(f"unknown smoother {smoother!r}")
+        if omega is None:
+            omega = 1.0 if smoother == "ssor" else 2.0 / 3.0
+        self.smoother, self.omega = smoother, omega
+        self.nu = self.nu_pre = nu
+        self.nu_post = nu if nu_post is None else nu_post
         self.cheb_lo, self.cheb_safety = cheb_lo, cheb_safety
         self.plan = plan_levels(dim, nelem, p, hierarchy, max_levels)
         self.levels: List[Level] = []
@@ -161,6 +173,15 @@ class Hierarchy:
                 v0 = start_vector(eig_seed, li, lv.mesh.N)
                 lam, _, _ = lanczos_lmax(lv.op, lv.dinv, v0, eig_steps)
                 lv.lmax = cheb_safety * lam
+        for lv in self.levels[:-1]:
+            if smoother == "ssor":
+                lv.relax = ColoredSSOR(lv.op, lv.dinv)
+            elif smoother == "blockjacobi":
+                lv.relax = BlockJacobi(lv.op)
+            elif smoother == "l1jacobi":
+                s1 = l1_row_sums(lv.op)
+                lv.l1inv = np.zeros_like(s1)
+                lv.l1inv[lv.mesh.interior] = 1.0 / s1[lv.mesh.interior]
         last = self.levels[-1]
         Ad, idx = last.op.dense_interior()
         last.idx = idx
@@ -173,11 +194,19 @@ class Hierarchy:
     def apply(self, li, x):
         return self.levels[li].op.apply(x)
 
-    def smooth(self, li, b, x, steps=None):
+    def smooth(self, li, b, x, steps=None, post=False):
+        """Pre-smoothing (nu_pre steps) or, with post, post-smoothing (nu_post steps); steps
+        overrides the count. x = None means a zero initial guess."""
         lv = self.levels[li]
-        k = self.nu if steps is None else steps
+        k = (self.nu_post if post else self.nu_pre) if steps is None else steps
         if self.smoother == "jacobi":
             return jacobi(lv.op, lv.dinv, b, x, k, self.omega)
+        if self.smoother == "ssor":
+            return lv.relax.ssor(b, x, k, self.omega)
+        if self.smoother == "l1jacobi":
+            return jacobi_type(lv.op, lambda r: lv.l1inv * r, b, x, k, self.omega)
+        if self.smoother == "blockjacobi":
+            return jacobi_type(lv.op, lv.relax.apply_inverse, b, x, k, self.omega)
         return chebyshev(lv.op, lv.dinv, lv.lmax, b, x, k, self.cheb_lo)
 
     def coarse_solve(self, b):
@@ -196,7 +225,7 @@ class Hierarchy:
         res = r - lv.op.apply(x)
         ec = self.vcycle(lv.to_coarse.restrict(res), li + 1)
         x = x + lv.to_coarse.prolong(ec)
-        return self.smooth(li, r, x)
+        return self.smooth(li, r, x, post=True)
 
     def applies(self):
         return [lv.op.applies for lv in self.levels]
@@ -269,7 +298,8 @@ def build_problem(prob, **kw):
     """Hierarchy and right-hand side for a problem description from the seeded inputs."""
     H = Hierarchy(prob.dim, prob.nelem, prob.order, prob.map, prob.mu,
                   hierarchy=prob.hierarchy, max_levels=prob.max_levels,
-                  smoother=prob.smoother, nu=prob.nu, eig_seed=prob.eig_seed, **kw)
+                  smoother=prob.smoother, nu=prob.nu, nu_post=prob.nu_post,
+                  eig_seed=prob.eig_seed, **kw)
     fn = prob.nodal_rhs()
     if fn is None:
         fn = nodal_field(H.fine.mesh, prob.f)

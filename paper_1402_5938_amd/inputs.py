@@ -80,8 +80,9 @@ class Problem:
     f_nodal: Optional[np.ndarray] = None
     f_seed: Optional[int] = None        # nodal f ~ U[-1,1] drawn on demand from this seed
     hierarchy: str = "p"                # "h" (fixed order) or "p" (order halving, then h)
-    smoother: str = "chebyshev"         # "chebyshev" or "jacobi"
-    nu: int = 4                         # Chebyshev degree / Jacobi sweeps, pre and post
+    smoother: str = "chebyshev"         # "chebyshev", "jacobi", "ssor", "l1jacobi", "blockjacobi"
+    nu: int = 4                         # Chebyshev degree / sweeps / SSOR steps, pre-smoothing
+    nu_post: Optional[int] = None       # post-smoothing count (None: the same as nu)
     mode: str = "pcg"                   # "pcg" or "mg"
     vcycle_prec: str = "f64"            # "f64" or "f32"
     rtol: float = 1e-10

@@ -54,7 +54,21 @@ typedef enum {
 typedef enum { GLLMG_F64 = 0, GLLMG_F32 = 1 } gllmg_prec;
 
 enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1 };
-enum { GLLMG_SMOOTH_JACOBI = 0, GLLMG_SMOOTH_CHEBYSHEV = 1 };
+/* Smoothers (§3.2, §4.3, §4.4.3):
+ *   JACOBI        nu sweeps x += omega D^{-1} (b - A x)                    (paper: omega = 2/3)
+ *   CHEBYSHEV     one degree-nu Chebyshev polynomial in D^{-1} A on [cheb_lo lambda, lambda]
+ *   SSOR          nu symmetric Gauss-Seidel steps (a forward and a backward sweep each) in a
+ *                 multicolor order of n^2 colors, n = p + 1: node (gx, gy[, gz]) has color
+ *                 (gx mod n) + n (gy mod n) in 2D, ((gx + gz) mod n) + n ((gy + gz) mod n) in 3D;
+ *                 colors 0..n^2-1 forward, then back; relaxation omega (paper: 1, SSOR(2,1))
+ *   L1_JACOBI     nu sweeps x += omega D_l1^{-1} (b - A x), (D_l1)_ii = sum_j |A_ij| over the
+ *                 interior row (paper: omega = 2/3)
+ *   BLOCK_JACOBI  nu sweeps x += omega B^{-1} (b - A x), B = A restricted to the blocks of
+ *                 element-owned interior nodes (along each axis an element owns its local
+ *                 nodes 0..p-1, the last element also p), inverted exactly at setup
+ *                 (paper: omega = 2/3). */
+enum { GLLMG_SMOOTH_JACOBI = 0, GLLMG_SMOOTH_CHEBYSHEV = 1, GLLMG_SMOOTH_SSOR = 2,
+       GLLMG_SMOOTH_L1_JACOBI = 3, GLLMG_SMOOTH_BLOCK_JACOBI = 4 };
 enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1 };
 
 /* Field families, evaluated on the device at every level's nodes (physical coordinates
@@ -90,10 +104,10 @@ typedef struct {
   int32_t hierarchy;      /* GLLMG_HIER_H: fixed p, halve elements; GLLMG_HIER_P: p -> ceil(p/2)
                              down to 1, then halve elements (§3.1.1, §3.1.2, §4.3)           */
   int32_t max_levels;     /* 0: as many levels as the rule allows; else keep the finest k  */
-  int32_t smoother;       /* GLLMG_SMOOTH_JACOBI or GLLMG_SMOOTH_CHEBYSHEV                  */
-  int32_t nu_pre;         /* Jacobi sweeps / Chebyshev degree before the coarse correction  */
+  int32_t smoother;       /* GLLMG_SMOOTH_*                                                */
+  int32_t nu_pre;         /* sweeps / Chebyshev degree / SSOR steps before the correction   */
   int32_t nu_post;        /* ... and after it                                              */
-  double omega;           /* Jacobi damping (the paper uses 2/3)                           */
+  double omega;           /* Jacobi-type damping (paper 2/3) or SSOR relaxation (paper 1)  */
   double cheb_lo;         /* Chebyshev interval [cheb_lo * lambda, lambda] (paper: 1/4)    */
   double cheb_safety;     /* lambda = cheb_safety x the Ritz estimate                      */
   int32_t eig_steps;      /* Lanczos/Arnoldi steps for lambda_max (paper: 10)             */

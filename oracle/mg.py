@@ -173,7 +173,7 @@ class Hierarchy:
                 v0 = start_vector(eig_seed, li, lv.mesh.N)
                 lam, _, _ = lanczos_lmax(lv.op, lv.dinv, v0, eig_steps)
                 lv.lmax = cheb_safety * lam
-        for lv in self.levels[:-1]:
+        for lv in self.levels:
             if smoother == "ssor":
                 lv.relax = ColoredSSOR(lv.op, lv.dinv)
             elif smoother == "blockjacobi":

@@ -216,6 +216,12 @@ void launch_apply(const Level& L, int prec, int neumann, const void* x, const Ep
                   hipStream_t s);
 size_t face_buffer_elems(const Level& L);
 
+// Multicolor Gauss-Seidel (SSOR smoother): x_i += omega dinv_i (b_i - (A x)_i) at every
+// interior node of one color (0 <= color < n^2); x must be 0 at boundary nodes
+void launch_gs_color(const Level& L, int prec, const void* b, void* x, const void* dinv, int color,
+                     double omega, hipStream_t s);
+void zero_boundary(const Level& L, int prec, void* v, hipStream_t s);
+
 // The allocation-free product's element-vector buffer: a file-scope device array of this many
 // bytes (one per device, shared by every call on that device). static_scratch(dev) returns its
 // device address on device dev, looked up once per device.

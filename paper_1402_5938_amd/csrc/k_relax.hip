@@ -1,0 +1,258 @@
+// Multicolor Gauss-Seidel passes of the SSOR smoother (paper §3.2.1, §4.3 "SSOR(2,1)").
+//
+// Coloring: n^2 colors, n = p + 1. A node with global grid indices (gx, gy[, gz]) has color
+//   2D: (gx mod n) + n (gy mod n)            3D: ((gx + gz) mod n) + n ((gy + gz) mod n).
+// Under collocated GLL quadrature the stiffness couples two nodes only if an element holds
+// both and, in 3D, they share a grid coordinate (the B_a^T G_ab B_b terms reach along the
+// coordinate lines and planes through a node); within one element distinct indices along an
+// axis have distinct residues mod n, so nodes of one color never couple. One launch updates
+// every interior node of one color,
+//   x_i <- x_i + omega dinv_i (b_i - (A x)_i),
+// each thread forming its own row (A x)_i matrix-free from the elements around the node. It
+// reads only nodes of other colors (and its own), so the threads of a launch never read what
+// another writes: a whole color at once is the node-by-node Gauss-Seidel update. A forward
+// sweep launches colors 0..C-1, a backward sweep C-1..0.
+//
+// The row of element e at its local node (i, j, k): with q running along the coordinate line
+// of axis a through the node,
+//   (A_e x)(i,j,k) = sum_a sum_m D[m, i_a] w_a(q_m),   w_a = sum_b G_ab u_b,
+//   u_b(q) = sum_l D[q_b, l] x(q with coordinate b -> l),
+// so a row needs x on the three coordinate planes through the node (3D; the whole element in
+// 2D) and G on the three lines: 9 n^2 + O(n) multiply-adds per element in 3D. The elements
+// around a node are summed lower element first per axis, z outermost. x must be 0 at boundary
+// nodes (the smoother clears them first); boundary rows are not updated.
+#include <cstdint>
+
+#include "internal.h"
+
+namespace gllmg {
+
+namespace {
+
+constexpr int kGsT = 256;
+
+template <int N, typename T>
+__device__ __forceinline__ T row3d(const T* __restrict__ x, const T* __restrict__ Ge,
+                                   const T* __restrict__ sD, int64_t base, int64_t sy, int64_t sz,
+                                   int i, int j, int k) {
+  constexpr int NN = N * N, NNN = N * N * N;
+  auto X = [&](int a, int b, int c) { return x[base + a + sy * b + sz * c]; };
+  T lx[N], ly[N], lz[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    lx[l] = X(l, j, k);
+    ly[l] = X(i, l, k);
+    lz[l] = X(i, j, l);
+  }
+  T acc = T(0);
+  // a = 0: the x-line through the node
+  for (int m = 0; m < N; ++m) {
+    const int q = m + N * j + NN * k;
+    T u0 = T(0), u1 = T(0), u2 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u0 += sD[m * N + l] * lx[l];
+#pragma unroll
+    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(m, l, k);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u2 += sD[k * N + l] * X(m, j, l);
+    const T w = Ge[q] * u0 + Ge[NNN + q] * u1 + Ge[2 * NNN + q] * u2;
+    acc += sD[m * N + i] * w;
+  }
+  // a = 1: the y-line
+  for (int m = 0; m < N; ++m) {
+    const int q = i + N * m + NN * k;
+    T u0 = T(0), u1 = T(0), u2 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, m, k);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u1 += sD[m * N + l] * ly[l];
+#pragma unroll
+    for (int l = 0; l < N; ++l) u2 += sD[k * N + l] * X(i, m, l);
+    const T w = Ge[NNN + q] * u0 + Ge[3 * NNN + q] * u1 + Ge[4 * NNN + q] * u2;
+    acc += sD[m * N + j] * w;
+  }
+  // a = 2: the z-line
+  for (int m = 0; m < N; ++m) {
+    const int q = i + N * j + NN * m;
+    T u0 = T(0), u1 = T(0), u2 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, j, m);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(i, l, m);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u2 += sD[m * N + l] * lz[l];
+    const T w = Ge[2 * NNN + q] * u0 + Ge[4 * NNN + q] * u1 + Ge[5 * NNN + q] * u2;
+    acc += sD[m * N + k] * w;
+  }
+  return acc;
+}
+
+template <int N, typename T>
+__device__ __forceinline__ T row2d(const T* __restrict__ x, const T* __restrict__ Ge,
+                                   const T* __restrict__ sD, int64_t base, int64_t sy, int i,
+                                   int j) {
+  constexpr int NN = N * N;
+  auto X = [&](int a, int b) { return x[base + a + sy * b]; };
+  T lx[N], ly[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    lx[l] = X(l, j);
+    ly[l] = X(i, l);
+  }
+  T acc = T(0);
+  for (int m = 0; m < N; ++m) {
+    const int q = m + N * j;
+    T u0 = T(0), u1 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u0 += sD[m * N + l] * lx[l];
+#pragma unroll
+    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(m, l);
+    const T w = Ge[q] * u0 + Ge[NN + q] * u1;
+    acc += sD[m * N + i] * w;
+  }
+  for (int m = 0; m < N; ++m) {
+    const int q = i + N * m;
+    T u0 = T(0), u1 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, m);
+#pragma unroll
+    for (int l = 0; l < N; ++l) u1 += sD[m * N + l] * ly[l];
+    const T w = Ge[NN + q] * u0 + Ge[2 * NN + q] * u1;
+    acc += sD[m * N + j] * w;
+  }
+  return acc;
+}
+
+// The elements around an interior grid index gi along an axis: the one below first.
+// Returns the count (1 or 2); e[0], loc[0] and e[1], loc[1].
+__device__ __forceinline__ int axis_elems(int gi, int p, int* e, int* loc) {
+  if (gi % p == 0) {
+    e[0] = gi / p - 1;
+    loc[0] = p;
+    e[1] = gi / p;
+    loc[1] = 0;
+    return 2;
+  }
+  e[0] = gi / p;
+  loc[0] = gi - e[0] * p;
+  return 1;
+}
+
+// One color of a Gauss-Seidel sweep. Thread t -> (kx, ky, gz) (2D: gz = 0); the node is
+// (ox + n kx, oy + n ky, gz) with ox, oy the color's residues shifted by gz in 3D.
+template <int N, int DIM, typename T>
+__global__ void __launch_bounds__(kGsT)
+k_gs_color(T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
+           const T* __restrict__ G, const T* __restrict__ Dm, Grid g, int ca, int cb, int cx,
+           int cy, T omega) {
+  __shared__ T sD[N * N];
+  for (int q = threadIdx.x; q < N * N; q += blockDim.x) sD[q] = Dm[q];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * kGsT + threadIdx.x;
+  const int64_t per = (int64_t)cx * cy;
+  if (t >= per * g.nn[2]) return;
+  const int gz = (int)(t / per);
+  const int rem = (int)(t - (int64_t)gz * per);
+  const int ky = rem / cx, kx = rem - ky * cx;
+  const int ox = DIM == 3 ? ((ca - gz) % N + N) % N : ca;
+  const int oy = DIM == 3 ? ((cb - gz) % N + N) % N : cb;
+  const int gx = ox + kx * N, gy = oy + ky * N;
+  if (gx <= 0 || gx >= g.nn[0] - 1 || gy <= 0 || gy >= g.nn[1] - 1) return;
+  if (DIM == 3 && (gz <= 0 || gz >= g.nn[2] - 1)) return;
+  const int p = N - 1;
+  const int64_t sy = g.nn[0], sz = (int64_t)g.nn[0] * g.nn[1];
+  const int64_t node = gx + sy * gy + sz * gz;
+  int exs[2], lxs[2], eys[2], lys[2], ezs[2], lzs[2];
+  const int nx = axis_elems(gx, p, exs, lxs);
+  const int ny = axis_elems(gy, p, eys, lys);
+  const int nz = DIM == 3 ? axis_elems(gz, p, ezs, lzs) : 1;
+  if (DIM == 2) {
+    ezs[0] = 0;
+    lzs[0] = 0;
+  }
+  constexpr int NLOC = DIM == 3 ? N * N * N : N * N;
+  constexpr int NC = DIM == 3 ? 6 : 3;
+  T acc = T(0);
+  for (int c = 0; c < nz; ++c)
+    for (int bb = 0; bb < ny; ++bb)
+      for (int a = 0; a < nx; ++a) {
+        const int ex = exs[a], ey = eys[bb], ez = ezs[c];
+        const int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
+        const int64_t base = (int64_t)ex * p + sy * ((int64_t)ey * p) + sz * ((int64_t)ez * p);
+        const T* Ge = G + e * (NC * NLOC);
+        if constexpr (DIM == 3)
+          acc += row3d<N, T>(x, Ge, sD, base, sy, sz, lxs[a], lys[bb], lzs[c]);
+        else
+          acc += row2d<N, T>(x, Ge, sD, base, sy, lxs[a], lys[bb]);
+      }
+  x[node] = x[node] + omega * dinv[node] * (b[node] - acc);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_boundary(T* __restrict__ v, Grid g) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const int gx = (int)(t % g.nn[0]);
+  const int gy = (int)((t / g.nn[0]) % g.nn[1]);
+  const int gz = (int)(t / ((int64_t)g.nn[0] * g.nn[1]));
+  bool bnd = gx == 0 || gx == g.nn[0] - 1 || gy == 0 || gy == g.nn[1] - 1;
+  if (g.dim == 3) bnd = bnd || gz == 0 || gz == g.nn[2] - 1;
+  if (bnd) v[t] = T(0);
+}
+
+template <int N, typename T>
+void gs_color_n(const Level& L, const T* G, const T* D, const void* b, void* x, const void* dinv,
+                int color, double omega, hipStream_t s) {
+  const Grid& g = L.g;
+  const int ca = color % N, cb = color / N;
+  const int cx = (g.nn[0] + N - 1) / N, cy = (g.nn[1] + N - 1) / N;
+  const int64_t threads = (int64_t)cx * cy * g.nn[2];
+  const unsigned nb = (unsigned)((threads + kGsT - 1) / kGsT);
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_gs_color<N, 3, T>), dim3(nb), dim3(kGsT), 0, s, (T*)x, (const T*)b,
+                       (const T*)dinv, G, D, g, ca, cb, cx, cy, (T)omega);
+  else
+    hipLaunchKernelGGL((k_gs_color<N, 2, T>), dim3(nb), dim3(kGsT), 0, s, (T*)x, (const T*)b,
+                       (const T*)dinv, G, D, g, ca, cb, cx, cy, (T)omega);
+  GLLMG_HIP(hipGetLastError());
+}
+
+template <typename T>
+void gs_color_t(const Level& L, const void* b, void* x, const void* dinv, int color, double omega,
+                hipStream_t s) {
+  const T* G = std::is_same<T, double>::value ? (const T*)L.G64 : (const T*)L.G32;
+  const T* D = std::is_same<T, double>::value ? (const T*)L.D64 : (const T*)L.D32;
+  switch (L.n) {
+#define GLLMG_CASE(NV) \
+  case NV:             \
+    return gs_color_n<NV, T>(L, G, D, b, x, dinv, color, omega, s);
+    GLLMG_CASE(2) GLLMG_CASE(3) GLLMG_CASE(4) GLLMG_CASE(5) GLLMG_CASE(6) GLLMG_CASE(7)
+    GLLMG_CASE(8) GLLMG_CASE(9) GLLMG_CASE(10) GLLMG_CASE(11) GLLMG_CASE(12) GLLMG_CASE(13)
+    GLLMG_CASE(14) GLLMG_CASE(15) GLLMG_CASE(16) GLLMG_CASE(17)
+#undef GLLMG_CASE
+    default:
+      throw Error(GLLMG_EINVAL, "unsupported order");
+  }
+}
+
+}  // namespace
+
+void launch_gs_color(const Level& L, int prec, const void* b, void* x, const void* dinv, int color,
+                     double omega, hipStream_t s) {
+  GLLMG_CHECK(color >= 0 && color < L.n * L.n, GLLMG_EINVAL, "color out of range");
+  if (prec == 0)
+    gs_color_t<double>(L, b, x, dinv, color, omega, s);
+  else
+    gs_color_t<float>(L, b, x, dinv, color, omega, s);
+}
+
+void zero_boundary(const Level& L, int prec, void* v, hipStream_t s) {
+  const unsigned nb = (unsigned)((L.g.N + 255) / 256);
+  if (prec == 0)
+    hipLaunchKernelGGL(k_zero_boundary<double>, dim3(nb), dim3(256), 0, s, (double*)v, L.g);
+  else
+    hipLaunchKernelGGL(k_zero_boundary<float>, dim3(nb), dim3(256), 0, s, (float*)v, L.g);
+  GLLMG_HIP(hipGetLastError());
+}
+
+}  // namespace gllmg

@@ -35,7 +35,8 @@ void validate(const gllmg_config& c) {
                 "nelem out of range");
   GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P, GLLMG_EINVAL,
               "hierarchy must be GLLMG_HIER_H or GLLMG_HIER_P");
-  GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV,
+  GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
+                  c.smoother == GLLMG_SMOOTH_SSOR,
               GLLMG_EINVAL, "unknown smoother");
   GLLMG_CHECK(c.nu_pre >= 0 && c.nu_post >= 0 && c.nu_pre <= 64 && c.nu_post <= 64, GLLMG_EINVAL,
               "smoothing steps out of range");
@@ -534,6 +535,20 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
   void* d = L.vd[pr];
   void* d2 = L.vd2[pr];
   const void* dinv = dinv_of(L, pr);
+  if (P->cfg.smoother == GLLMG_SMOOTH_SSOR) {
+    // k SSOR steps: colors 0..C-1, then C-1..0, each a launch updating its nodes in place
+    if (zero)
+      vec_zero(pr, N, x, s);
+    else
+      zero_boundary(L, pr, x, s);
+    const int C = L.n * L.n;
+    for (int it = 0; it < k; ++it) {
+      for (int c = 0; c < C; ++c) launch_gs_color(L, pr, b, x, dinv, c, P->cfg.omega, s);
+      for (int c = C - 1; c >= 0; --c) launch_gs_color(L, pr, b, x, dinv, c, P->cfg.omega, s);
+      L.applies += 2;  // a forward and a backward sweep: about two products' arithmetic
+    }
+    return;
+  }
   if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
     for (int it = 0; it < k; ++it) {
       if (it == 0 && zero) {
@@ -642,7 +657,10 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
   // b_c = P^T r, and with it the coarse level's first smoothing step from x_c = 0
   Epi ep;
   ep.y = C.vb[pr];
-  const bool fuse = C.has_coarse && P->cfg.nu_pre > 0;
+  // the coarse level's first pre-smoothing step from zero rides on the restriction's gather
+  // (Jacobi and Chebyshev; the Gauss-Seidel sweeps start from a cleared vector instead)
+  const bool fuse = C.has_coarse && P->cfg.nu_pre > 0 &&
+                    (P->cfg.smoother == GLLMG_SMOOTH_JACOBI || P->cfg.smoother == GLLMG_SMOOTH_CHEBYSHEV);
   if (fuse && P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
     ep.mode = EPI_STORE_JACOBI0;
     ep.x = C.vx[pr];
@@ -932,6 +950,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
 // n0 or at 2), and maxit below the history capacity.
 bool batch_eligible(const gllmg_problem* P, int maxit) {
   if (!P->persistent || P->cfg.dim != 3 || P->vprec != 1) return false;
+  if (P->cfg.smoother != GLLMG_SMOOTH_JACOBI && P->cfg.smoother != GLLMG_SMOOTH_CHEBYSHEV) return false;
   if (P->L.size() > (size_t)kBatchMaxLevels || !P->L.back().Ainv64) return false;
   if (maxit >= kBatchHist || P->L[0].g.N > kBatchMaxNodes) return false;
   const int n0 = P->L[0].n;
@@ -998,6 +1017,11 @@ void batch_fill(const gllmg_problem* P, BatchProblem& d) {
 thread_local const LaunchGroup* g_launch_group = nullptr;
 
 // ------------------------------------------------------------------ launch groups of a batch
+// Smoothers whose kernels take launch groups (the Gauss-Seidel passes do not).
+bool groupable_smoother(int sm) {
+  return sm == GLLMG_SMOOTH_JACOBI || sm == GLLMG_SMOOTH_CHEBYSHEV;
+}
+
 // Problems that a launch group can take together: the same levels, smoother and V-cycle
 // precision, and every device buffer at the same offset in its workspace (the layout is a
 // function of the configuration, so equal configurations give equal offsets).
@@ -1503,7 +1527,7 @@ gllmg_status gllmg_smooth(const gllmg_problem* P, int32_t level, gllmg_prec prec
     check_ptr(b, pr == 0 ? 8 : 4, "b");
     check_ptr(x, pr == 0 ? 8 : 4, "x");
     GLLMG_CHECK(steps >= 0 && steps <= 64, GLLMG_EINVAL, "steps out of range");
-    GLLMG_CHECK(P->cfg.smoother == GLLMG_SMOOTH_JACOBI || P->L[level].lmax > 0.0,
+    GLLMG_CHECK(P->cfg.smoother != GLLMG_SMOOTH_CHEBYSHEV || P->L[level].lmax > 0.0,
                 GLLMG_EUNSUPPORTED, "no Chebyshev bound on this level (coarsest level)");
     smooth_impl(const_cast<gllmg_problem*>(P), level, pr, b, x, steps, zero_guess != 0,
                 (hipStream_t)stream);
@@ -1638,6 +1662,7 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       for (int i = 0; i < count; ++i) {
         gllmg_problem* P = probs[i];
         if (P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
+        if (!groupable_smoother(P->cfg.smoother)) continue;
         if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
         bool placed = false;
         for (auto& sh : shapes)

@@ -20,7 +20,9 @@ LIB_PATH = os.environ.get("GLLMG_LIB", os.path.join(HERE, "libgllmg.so"))
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EUNSUPPORTED = range(7)
 F64, F32 = 0, 1
 HIER_H, HIER_P = 0, 1
-SMOOTH_JACOBI, SMOOTH_CHEBYSHEV = 0, 1
+SMOOTH_JACOBI, SMOOTH_CHEBYSHEV, SMOOTH_SSOR, SMOOTH_L1_JACOBI, SMOOTH_BLOCK_JACOBI = 0, 1, 2, 3, 4
+SMOOTHERS = {"jacobi": SMOOTH_JACOBI, "chebyshev": SMOOTH_CHEBYSHEV, "ssor": SMOOTH_SSOR,
+             "l1jacobi": SMOOTH_L1_JACOBI, "blockjacobi": SMOOTH_BLOCK_JACOBI}
 MODE_PCG, MODE_MG = 0, 1
 
 KINDS = {"identity": 0, "warp_sine": 1, "affine": 2, "const": 10, "exp_sine_product": 11,
@@ -136,7 +138,7 @@ def make_field(desc: dict):
 
 
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
-                vcycle_prec="f64", max_levels=0, omega=2.0 / 3.0, cheb_lo=0.25,
+                vcycle_prec="f64", max_levels=0, omega=None, cheb_lo=0.25,
                 cheb_safety=1.0, eig_steps=10, eig_seed=0) -> Config:
     c = Config()
     lib().gllmg_config_default(C.byref(c))
@@ -146,7 +148,11 @@ def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu
         c.nelem[a] = int(ne[a])
     c.order = order
     c.hierarchy = HIER_P if hierarchy == "p" else HIER_H
-    c.smoother = SMOOTH_CHEBYSHEV if smoother == "chebyshev" else SMOOTH_JACOBI
+    if smoother not in SMOOTHERS:
+        raise ValueError(f"unknown smoother {smoother!r}")
+    c.smoother = SMOOTHERS[smoother]
+    if omega is None:   # the paper's damping: 1 for SSOR, 2/3 for the Jacobi smoothers
+        omega = 1.0 if smoother == "ssor" else 2.0 / 3.0
     c.nu_pre = nu
     c.nu_post = nu if nu_post is None else nu_post
     c.vcycle_prec = F32 if vcycle_prec == "f32" else F64

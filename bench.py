@@ -206,6 +206,53 @@ def workload_serve(a):
                         f"budget {a.hbm_gb} GiB", **rep}
 
 
+SMOOTHER_CASES = {"chebyshev": (4, 4), "jacobi": (3, 3), "ssor": (2, 1), "l1jacobi": (3, 3),
+                  "blockjacobi": (3, 3)}
+
+
+def workload_smoothers(a):
+    """The benchmark problem (3D warped, mu = exp(4.6 sx sy sz), f = 1, a.nelem^3 hexes at
+    p = a.order) solved to 1e-10 by FP64 PCG with the p-multigrid V-cycle and each smoother the
+    paper compares (§4.3, §4.4.3: Chebyshev(4,4) of the workload, Jacobi(3,3), SSOR(2,1),
+    l1-Jacobi(3,3), block Jacobi(3,3)): time to solution, iterations, the time of one
+    fine-level smoothing step (HIP events on the launch stream) and of one V-cycle."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
+    rows = []
+    for name in a.smoothers.split(","):
+        pre, post = SMOOTHER_CASES[name]
+        cfg = gllmg.make_config(3, prob.nelem, prob.order, "p", name, pre, nu_post=post)
+        t0 = time.perf_counter()
+        G = gllmg.Problem(cfg, prob.map, prob.mu)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        b = G.rhs(G.eval_field(prob.f))
+        t, r, x = _solve_timed(G, b, a.steps, a.warmup, prob.rtol, prob.maxit)
+        # one smoothing step on the finest level and one V-cycle
+        xs = torch.zeros_like(b)
+        z = torch.empty_like(b)
+        G.smooth(b, xs, 1, 0, zero_guess=False)
+        G.vcycle(b, z)
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        e[0].record()
+        G.smooth(b, xs, 1, 0, zero_guess=False)
+        e[1].record()
+        G.vcycle(b, z)
+        e[2].record()
+        torch.cuda.synchronize()
+        rows.append({"smoother": name, "nu_pre": pre, "nu_post": post, "pcg_iterations": r.iters,
+                     "converged": r.converged, "time_to_solution_ms": t * 1e3,
+                     "smoothing_step_us": e[0].elapsed_time(e[1]) * 1e3,
+                     "vcycle_ms": e[1].elapsed_time(e[2]), "setup_s": t_setup,
+                     "relres_true": r.relres_true})
+        G.close()
+        torch.cuda.empty_cache()
+    return {"workload": f"smoothers: 3D warped var {a.nelem}^3 hexes p={a.order}, FP64 PCG to 1e-10",
+            "nodes": inputs.node_count(prob.nelem, prob.order), "cases": rows}
+
+
 SWEEP_CASES = [(3, 256, 1), (3, 128, 2), (3, 64, 4), (3, 40, 6), (3, 32, 8), (3, 20, 12), (3, 16, 16),
                (2, 512, 8)]
 
@@ -309,7 +356,9 @@ def workload_apply(a):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep"])
+    ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep",
+                                                          "smoothers"])
+    ap.add_argument("--smoothers", default="chebyshev,jacobi,ssor")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=100.0)
@@ -334,7 +383,8 @@ def main():
     torch.cuda.set_device(0)
     if a.workload != "config2":
         fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
-              "apply": workload_apply, "sweep": workload_sweep}[a.workload]
+              "apply": workload_apply, "sweep": workload_sweep,
+              "smoothers": workload_smoothers}[a.workload]
         print(json.dumps(fn(a)))
         return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)

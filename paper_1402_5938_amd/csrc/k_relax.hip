@@ -8,9 +8,9 @@
 // axis have distinct residues mod n, so nodes of one color never couple. One launch updates
 // every interior node of one color,
 //   x_i <- x_i + omega dinv_i (b_i - (A x)_i),
-// each thread forming its own row (A x)_i matrix-free from the elements around the node. It
-// reads only nodes of other colors (and its own), so the threads of a launch never read what
-// another writes: a whole color at once is the node-by-node Gauss-Seidel update. A forward
+// each node's row (A x)_i formed matrix-free from the elements around it by a group of lanes.
+// A row reads only nodes of other colors (and its own), so the threads of a launch never read
+// what another writes: a whole color at once is the node-by-node Gauss-Seidel update. A forward
 // sweep launches colors 0..C-1, a backward sweep C-1..0.
 //
 // The row of element e at its local node (i, j, k): with q running along the coordinate line
@@ -31,94 +31,85 @@ namespace {
 
 constexpr int kGsT = 256;
 
+// Lanes per node: lane m of a node's group evaluates the terms at position m (and m + LPN, ...)
+// along the coordinate lines through the node; the group then sums its lanes.
+template <int N>
+struct Lpn {
+  static constexpr int v = N <= 4 ? 4 : (N <= 8 ? 8 : 16);
+};
+
+// The terms of position m of element e's row at its local node (i, j, k): for each axis a the
+// point q on the a-line through the node with q_a = m,
+//   D[m, i_a] (G_a0 u_0(q) + G_a1 u_1(q) + G_a2 u_2(q)),  u_b(q) = sum_l D[q_b, l] x(q, b -> l).
 template <int N, typename T>
-__device__ __forceinline__ T row3d(const T* __restrict__ x, const T* __restrict__ Ge,
-                                   const T* __restrict__ sD, int64_t base, int64_t sy, int64_t sz,
-                                   int i, int j, int k) {
+__device__ __forceinline__ T terms3d(const T* __restrict__ x, const T* __restrict__ Ge,
+                                     const T* __restrict__ sD, int64_t base, int64_t sy,
+                                     int64_t sz, int i, int j, int k, int m) {
   constexpr int NN = N * N, NNN = N * N * N;
   auto X = [&](int a, int b, int c) { return x[base + a + sy * b + sz * c]; };
-  T lx[N], ly[N], lz[N];
-#pragma unroll
-  for (int l = 0; l < N; ++l) {
-    lx[l] = X(l, j, k);
-    ly[l] = X(i, l, k);
-    lz[l] = X(i, j, l);
-  }
   T acc = T(0);
-  // a = 0: the x-line through the node
-  for (int m = 0; m < N; ++m) {
+  {  // a = 0: q = (m, j, k)
+    T u0 = T(0), u1 = T(0), u2 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      u0 += sD[m * N + l] * X(l, j, k);
+      u1 += sD[j * N + l] * X(m, l, k);
+      u2 += sD[k * N + l] * X(m, j, l);
+    }
     const int q = m + N * j + NN * k;
+    acc += sD[m * N + i] * (Ge[q] * u0 + Ge[NNN + q] * u1 + Ge[2 * NNN + q] * u2);
+  }
+  {  // a = 1: q = (i, m, k)
     T u0 = T(0), u1 = T(0), u2 = T(0);
 #pragma unroll
-    for (int l = 0; l < N; ++l) u0 += sD[m * N + l] * lx[l];
-#pragma unroll
-    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(m, l, k);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u2 += sD[k * N + l] * X(m, j, l);
-    const T w = Ge[q] * u0 + Ge[NNN + q] * u1 + Ge[2 * NNN + q] * u2;
-    acc += sD[m * N + i] * w;
-  }
-  // a = 1: the y-line
-  for (int m = 0; m < N; ++m) {
+    for (int l = 0; l < N; ++l) {
+      u0 += sD[i * N + l] * X(l, m, k);
+      u1 += sD[m * N + l] * X(i, l, k);
+      u2 += sD[k * N + l] * X(i, m, l);
+    }
     const int q = i + N * m + NN * k;
-    T u0 = T(0), u1 = T(0), u2 = T(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, m, k);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u1 += sD[m * N + l] * ly[l];
-#pragma unroll
-    for (int l = 0; l < N; ++l) u2 += sD[k * N + l] * X(i, m, l);
-    const T w = Ge[NNN + q] * u0 + Ge[3 * NNN + q] * u1 + Ge[4 * NNN + q] * u2;
-    acc += sD[m * N + j] * w;
+    acc += sD[m * N + j] * (Ge[NNN + q] * u0 + Ge[3 * NNN + q] * u1 + Ge[4 * NNN + q] * u2);
   }
-  // a = 2: the z-line
-  for (int m = 0; m < N; ++m) {
-    const int q = i + N * j + NN * m;
+  {  // a = 2: q = (i, j, m)
     T u0 = T(0), u1 = T(0), u2 = T(0);
 #pragma unroll
-    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, j, m);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(i, l, m);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u2 += sD[m * N + l] * lz[l];
-    const T w = Ge[2 * NNN + q] * u0 + Ge[4 * NNN + q] * u1 + Ge[5 * NNN + q] * u2;
-    acc += sD[m * N + k] * w;
+    for (int l = 0; l < N; ++l) {
+      u0 += sD[i * N + l] * X(l, j, m);
+      u1 += sD[j * N + l] * X(i, l, m);
+      u2 += sD[m * N + l] * X(i, j, l);
+    }
+    const int q = i + N * j + NN * m;
+    acc += sD[m * N + k] * (Ge[2 * NNN + q] * u0 + Ge[4 * NNN + q] * u1 + Ge[5 * NNN + q] * u2);
   }
   return acc;
 }
 
 template <int N, typename T>
-__device__ __forceinline__ T row2d(const T* __restrict__ x, const T* __restrict__ Ge,
-                                   const T* __restrict__ sD, int64_t base, int64_t sy, int i,
-                                   int j) {
+__device__ __forceinline__ T terms2d(const T* __restrict__ x, const T* __restrict__ Ge,
+                                     const T* __restrict__ sD, int64_t base, int64_t sy, int i,
+                                     int j, int m) {
   constexpr int NN = N * N;
   auto X = [&](int a, int b) { return x[base + a + sy * b]; };
-  T lx[N], ly[N];
-#pragma unroll
-  for (int l = 0; l < N; ++l) {
-    lx[l] = X(l, j);
-    ly[l] = X(i, l);
-  }
   T acc = T(0);
-  for (int m = 0; m < N; ++m) {
+  {  // a = 0: q = (m, j)
+    T u0 = T(0), u1 = T(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      u0 += sD[m * N + l] * X(l, j);
+      u1 += sD[j * N + l] * X(m, l);
+    }
     const int q = m + N * j;
-    T u0 = T(0), u1 = T(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u0 += sD[m * N + l] * lx[l];
-#pragma unroll
-    for (int l = 0; l < N; ++l) u1 += sD[j * N + l] * X(m, l);
-    const T w = Ge[q] * u0 + Ge[NN + q] * u1;
-    acc += sD[m * N + i] * w;
+    acc += sD[m * N + i] * (Ge[q] * u0 + Ge[NN + q] * u1);
   }
-  for (int m = 0; m < N; ++m) {
-    const int q = i + N * m;
+  {  // a = 1: q = (i, m)
     T u0 = T(0), u1 = T(0);
 #pragma unroll
-    for (int l = 0; l < N; ++l) u0 += sD[i * N + l] * X(l, m);
-#pragma unroll
-    for (int l = 0; l < N; ++l) u1 += sD[m * N + l] * ly[l];
-    const T w = Ge[NN + q] * u0 + Ge[2 * NN + q] * u1;
-    acc += sD[m * N + j] * w;
+    for (int l = 0; l < N; ++l) {
+      u0 += sD[i * N + l] * X(l, m);
+      u1 += sD[m * N + l] * X(i, l);
+    }
+    const int q = i + N * m;
+    acc += sD[m * N + j] * (Ge[NN + q] * u0 + Ge[2 * NN + q] * u1);
   }
   return acc;
 }
@@ -138,54 +129,64 @@ __device__ __forceinline__ int axis_elems(int gi, int p, int* e, int* loc) {
   return 1;
 }
 
-// One color of a Gauss-Seidel sweep. Thread t -> (kx, ky, gz) (2D: gz = 0); the node is
-// (ox + n kx, oy + n ky, gz) with ox, oy the color's residues shifted by gz in 3D.
+// One color of a Gauss-Seidel sweep. Lane group t / LPN -> node (kx, ky, gz) (2D: gz = 0): the
+// node is (ox + n kx, oy + n ky, gz) with ox, oy the color's residues, shifted by gz in 3D.
+// Each lane sums its positions over the elements around the node (lower element first per
+// axis, z outermost); the group adds its lanes by an xor butterfly (the same sum in every lane)
+// and its first lane writes the update.
 template <int N, int DIM, typename T>
 __global__ void __launch_bounds__(kGsT)
 k_gs_color(T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ dinv,
            const T* __restrict__ G, const T* __restrict__ Dm, Grid g, int ca, int cb, int cx,
            int cy, T omega) {
+  constexpr int LPN = Lpn<N>::v;
   __shared__ T sD[N * N];
   for (int q = threadIdx.x; q < N * N; q += blockDim.x) sD[q] = Dm[q];
   __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * kGsT + threadIdx.x;
+  const int lane = (int)(t % LPN);
+  const int64_t nid = t / LPN;
   const int64_t per = (int64_t)cx * cy;
-  if (t >= per * g.nn[2]) return;
-  const int gz = (int)(t / per);
-  const int rem = (int)(t - (int64_t)gz * per);
+  bool ok = nid < per * g.nn[2];
+  const int gz = ok ? (int)(nid / per) : 0;
+  const int rem = ok ? (int)(nid - (int64_t)gz * per) : 0;
   const int ky = rem / cx, kx = rem - ky * cx;
   const int ox = DIM == 3 ? ((ca - gz) % N + N) % N : ca;
   const int oy = DIM == 3 ? ((cb - gz) % N + N) % N : cb;
   const int gx = ox + kx * N, gy = oy + ky * N;
-  if (gx <= 0 || gx >= g.nn[0] - 1 || gy <= 0 || gy >= g.nn[1] - 1) return;
-  if (DIM == 3 && (gz <= 0 || gz >= g.nn[2] - 1)) return;
+  ok = ok && gx > 0 && gx < g.nn[0] - 1 && gy > 0 && gy < g.nn[1] - 1;
+  if (DIM == 3) ok = ok && gz > 0 && gz < g.nn[2] - 1;
   const int p = N - 1;
   const int64_t sy = g.nn[0], sz = (int64_t)g.nn[0] * g.nn[1];
-  const int64_t node = gx + sy * gy + sz * gz;
-  int exs[2], lxs[2], eys[2], lys[2], ezs[2], lzs[2];
-  const int nx = axis_elems(gx, p, exs, lxs);
-  const int ny = axis_elems(gy, p, eys, lys);
-  const int nz = DIM == 3 ? axis_elems(gz, p, ezs, lzs) : 1;
-  if (DIM == 2) {
-    ezs[0] = 0;
-    lzs[0] = 0;
-  }
-  constexpr int NLOC = DIM == 3 ? N * N * N : N * N;
-  constexpr int NC = DIM == 3 ? 6 : 3;
   T acc = T(0);
-  for (int c = 0; c < nz; ++c)
-    for (int bb = 0; bb < ny; ++bb)
-      for (int a = 0; a < nx; ++a) {
-        const int ex = exs[a], ey = eys[bb], ez = ezs[c];
-        const int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
-        const int64_t base = (int64_t)ex * p + sy * ((int64_t)ey * p) + sz * ((int64_t)ez * p);
-        const T* Ge = G + e * (NC * NLOC);
-        if constexpr (DIM == 3)
-          acc += row3d<N, T>(x, Ge, sD, base, sy, sz, lxs[a], lys[bb], lzs[c]);
-        else
-          acc += row2d<N, T>(x, Ge, sD, base, sy, lxs[a], lys[bb]);
-      }
-  x[node] = x[node] + omega * dinv[node] * (b[node] - acc);
+  if (ok) {
+    int exs[2], lxs[2], eys[2], lys[2], ezs[2] = {0, 0}, lzs[2] = {0, 0};
+    const int nx = axis_elems(gx, p, exs, lxs);
+    const int ny = axis_elems(gy, p, eys, lys);
+    const int nz = DIM == 3 ? axis_elems(gz, p, ezs, lzs) : 1;
+    constexpr int NLOC = DIM == 3 ? N * N * N : N * N;
+    constexpr int NC = DIM == 3 ? 6 : 3;
+    for (int c = 0; c < nz; ++c)
+      for (int bb = 0; bb < ny; ++bb)
+        for (int a = 0; a < nx; ++a) {
+          const int ex = exs[a], ey = eys[bb], ez = ezs[c];
+          const int64_t e = ex + (int64_t)g.ne[0] * (ey + (int64_t)g.ne[1] * ez);
+          const int64_t base = (int64_t)ex * p + sy * ((int64_t)ey * p) + sz * ((int64_t)ez * p);
+          const T* Ge = G + e * (NC * NLOC);
+          for (int m = lane; m < N; m += LPN) {
+            if constexpr (DIM == 3)
+              acc += terms3d<N, T>(x, Ge, sD, base, sy, sz, lxs[a], lys[bb], lzs[c], m);
+            else
+              acc += terms2d<N, T>(x, Ge, sD, base, sy, lxs[a], lys[bb], m);
+          }
+        }
+  }
+#pragma unroll
+  for (int off = LPN / 2; off >= 1; off /= 2) acc += __shfl_xor(acc, off, LPN);
+  if (ok && lane == 0) {
+    const int64_t node = gx + sy * gy + sz * gz;
+    x[node] = x[node] + omega * dinv[node] * (b[node] - acc);
+  }
 }
 
 template <typename T>
@@ -206,7 +207,7 @@ void gs_color_n(const Level& L, const T* G, const T* D, const void* b, void* x, 
   const Grid& g = L.g;
   const int ca = color % N, cb = color / N;
   const int cx = (g.nn[0] + N - 1) / N, cy = (g.nn[1] + N - 1) / N;
-  const int64_t threads = (int64_t)cx * cy * g.nn[2];
+  const int64_t threads = (int64_t)cx * cy * g.nn[2] * Lpn<N>::v;
   const unsigned nb = (unsigned)((threads + kGsT - 1) / kGsT);
   if (g.dim == 3)
     hipLaunchKernelGGL((k_gs_color<N, 3, T>), dim3(nb), dim3(kGsT), 0, s, (T*)x, (const T*)b,

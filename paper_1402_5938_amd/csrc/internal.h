@@ -73,6 +73,8 @@ struct Level {
   double* w64 = nullptr;
   double* dinv64 = nullptr;
   float* dinv32 = nullptr;
+  double* l1inv64 = nullptr;  // l1-Jacobi smoother: 1 / sum_j |A_ij| (interior), else unused
+  float* l1inv32 = nullptr;
   double lmax = 0.0;
   // V-cycle scratch in the V-cycle precision (and an FP64 set for FP64 calls)
   void* vb[2] = {nullptr, nullptr};
@@ -221,6 +223,8 @@ size_t face_buffer_elems(const Level& L);
 void launch_gs_color(const Level& L, int prec, const void* b, void* x, const void* dinv, int color,
                      double omega, hipStream_t s);
 void zero_boundary(const Level& L, int prec, void* v, hipStream_t s);
+// l1 row sums of the interior block, sum_j |A_ij| over interior j (0 at boundary rows); FP64
+void launch_l1_rowsum(const Level& L, double* out, hipStream_t s);
 
 // The allocation-free product's element-vector buffer: a file-scope device array of this many
 // bytes (one per device, shared by every call on that device). static_scratch(dev) returns its

@@ -189,6 +189,136 @@ k_gs_color(T* __restrict__ x, const T* __restrict__ b, const T* __restrict__ din
   }
 }
 
+// ------------------------------------------------------------------ assembled entries
+// Packed index of G_ab (a <= b): 00 01 02 11 12 22 in 3D, 00 01 11 in 2D.
+__device__ __forceinline__ int gcomp(int dim, int a, int b) {
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  if (dim == 2) return a == 0 ? b : 2;
+  if (a == 0) return b;
+  return a == 1 ? 2 + b : 5;
+}
+
+// (K_e)_ij of the collocated element stiffness sum_q B_q^T G_q B_q between local nodes li and
+// lj of element e: B_a(q, i) = D[q_a, i_a] when q agrees with i off axis a, so
+//   a = b: i, j on one a-line: sum_m D[m, i_a] G_aa(i with a -> m) D[m, j_a];
+//   a != b: i, j agree on the remaining axis (3D); the one point q = (q_a = j_a, q_b = i_b, rest
+//           = i) gives D[j_a, i_a] G_ab(q) D[i_b, j_b].
+__device__ double elem_entry(const double* __restrict__ Ge, const double* __restrict__ Dm, int n,
+                             int dim, const int* li, const int* lj) {
+  const int nloc = dim == 3 ? n * n * n : n * n;
+  const int st[3] = {1, n, n * n};
+  double k = 0.0;
+  for (int a = 0; a < dim; ++a)
+    for (int b = 0; b < dim; ++b) {
+      if (a == b) {
+        bool line = true;
+        for (int c = 0; c < dim; ++c)
+          if (c != a && li[c] != lj[c]) line = false;
+        if (!line) continue;
+        int q0 = 0;
+        for (int c = 0; c < dim; ++c)
+          if (c != a) q0 += li[c] * st[c];
+        const double* Gaa = Ge + (int64_t)gcomp(dim, a, a) * nloc;
+        for (int m = 0; m < n; ++m)
+          k += Dm[m * n + li[a]] * Gaa[q0 + m * st[a]] * Dm[m * n + lj[a]];
+      } else {
+        if (dim == 3) {
+          const int c3 = 3 - a - b;
+          if (li[c3] != lj[c3]) continue;
+        }
+        int q = lj[a] * st[a] + li[b] * st[b];
+        if (dim == 3) q += li[3 - a - b] * st[3 - a - b];
+        k += Dm[lj[a] * n + li[a]] * Ge[(int64_t)gcomp(dim, a, b) * nloc + q] * Dm[li[b] * n + lj[b]];
+      }
+    }
+  return k;
+}
+
+// l1 row sums of the interior block: out_i = sum_j |A_ij| over interior nodes j, A_ij = the sum
+// of (K_e)_ij over the elements holding both nodes (0 at boundary rows). One thread per node;
+// the candidates j are the nodes of the elements around i that share a grid coordinate with i
+// (3D) or any node of them (2D). FP64, setup only.
+__global__ void __launch_bounds__(256)
+k_l1_rowsum(const double* __restrict__ G, const double* __restrict__ Dm, Grid g,
+            double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const int dim = g.dim, p = g.p, n = p + 1;
+  const int gi[3] = {(int)(t % g.nn[0]), (int)((t / g.nn[0]) % g.nn[1]),
+                     dim == 3 ? (int)(t / ((int64_t)g.nn[0] * g.nn[1])) : 0};
+  for (int a = 0; a < dim; ++a)
+    if (gi[a] == 0 || gi[a] == g.nn[a] - 1) {
+      out[t] = 0.0;
+      return;
+    }
+  // per axis: the elements around gi (one below first) and the range of their nodes
+  int ea[3][2], na[3], lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= dim) {
+      na[a] = 1;
+      ea[a][0] = ea[a][1] = 0;
+      lo[a] = hi[a] = 0;
+      continue;
+    }
+    if (gi[a] % p == 0) {
+      na[a] = 2;
+      ea[a][0] = gi[a] / p - 1;
+      ea[a][1] = gi[a] / p;
+    } else {
+      na[a] = 1;
+      ea[a][0] = ea[a][1] = gi[a] / p;
+    }
+    lo[a] = ea[a][0] * p;
+    hi[a] = ea[a][na[a] - 1] * p + p;
+  }
+  const int nloc = dim == 3 ? n * n * n : n * n;
+  const int ncomp = dim == 3 ? 6 : 3;
+  double acc = 0.0;
+  for (int jz = lo[2]; jz <= hi[2]; ++jz)
+    for (int jy = lo[1]; jy <= hi[1]; ++jy)
+      for (int jx = lo[0]; jx <= hi[0]; ++jx) {
+        const int gj[3] = {jx, jy, jz};
+        bool inter = true;
+        for (int a = 0; a < dim; ++a) inter = inter && gj[a] > 0 && gj[a] < g.nn[a] - 1;
+        if (!inter) continue;
+        if (dim == 3 && gj[0] != gi[0] && gj[1] != gi[1] && gj[2] != gi[2]) continue;
+        // per axis the elements holding both: both around gi if gj == gi, else the one on gj's side
+        int ce[3][2], nc[3];
+        for (int a = 0; a < 3; ++a) {
+          if (a >= dim) {
+            nc[a] = 1;
+            ce[a][0] = 0;
+          } else if (gj[a] == gi[a]) {
+            nc[a] = na[a];
+            ce[a][0] = ea[a][0];
+            ce[a][1] = ea[a][1];
+          } else {
+            nc[a] = 1;
+            ce[a][0] = (na[a] == 2 && gj[a] > gi[a]) ? ea[a][1] : ea[a][0];
+          }
+        }
+        double aij = 0.0;
+        for (int cz = 0; cz < nc[2]; ++cz)
+          for (int cy = 0; cy < nc[1]; ++cy)
+            for (int cx = 0; cx < nc[0]; ++cx) {
+              const int e3[3] = {ce[0][cx], ce[1][cy], ce[2][cz]};
+              int li[3], lj[3];
+              for (int a = 0; a < 3; ++a) {
+                li[a] = a < dim ? gi[a] - e3[a] * p : 0;
+                lj[a] = a < dim ? gj[a] - e3[a] * p : 0;
+              }
+              const int64_t e = e3[0] + (int64_t)g.ne[0] * (e3[1] + (int64_t)g.ne[1] * e3[2]);
+              aij += elem_entry(G + e * (int64_t)ncomp * nloc, Dm, n, dim, li, lj);
+            }
+        acc += fabs(aij);
+      }
+  out[t] = acc;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_zero_boundary(T* __restrict__ v, Grid g) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -245,6 +375,12 @@ void launch_gs_color(const Level& L, int prec, const void* b, void* x, const voi
     gs_color_t<double>(L, b, x, dinv, color, omega, s);
   else
     gs_color_t<float>(L, b, x, dinv, color, omega, s);
+}
+
+void launch_l1_rowsum(const Level& L, double* out, hipStream_t s) {
+  const unsigned nb = (unsigned)((L.g.N + 255) / 256);
+  hipLaunchKernelGGL(k_l1_rowsum, dim3(nb), dim3(256), 0, s, L.G64, L.D64, L.g, out);
+  GLLMG_HIP(hipGetLastError());
 }
 
 void zero_boundary(const Level& L, int prec, void* v, hipStream_t s) {

@@ -36,7 +36,7 @@ void validate(const gllmg_config& c) {
   GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P, GLLMG_EINVAL,
               "hierarchy must be GLLMG_HIER_H or GLLMG_HIER_P");
   GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
-                  c.smoother == GLLMG_SMOOTH_SSOR,
+                  c.smoother == GLLMG_SMOOTH_SSOR || c.smoother == GLLMG_SMOOTH_L1_JACOBI,
               GLLMG_EINVAL, "unknown smoother");
   GLLMG_CHECK(c.nu_pre >= 0 && c.nu_post >= 0 && c.nu_pre <= 64 && c.nu_post <= 64, GLLMG_EINVAL,
               "smoothing steps out of range");
@@ -202,6 +202,10 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
     L.ctab = (double*)A.take(sizeof(double) * 2 * ctab_pairs(c));
     L.dinv64 = (double*)A.take(sizeof(double) * L.g.N);
     L.dinv32 = f32 ? (float*)A.take(sizeof(float) * L.g.N) : nullptr;
+    if (c.smoother == GLLMG_SMOOTH_L1_JACOBI) {
+      L.l1inv64 = (double*)A.take(sizeof(double) * L.g.N);
+      L.l1inv32 = f32 ? (float*)A.take(sizeof(float) * L.g.N) : nullptr;
+    }
     face = std::max(face, face_buffer_elems(L));
     if (!L.has_coarse && L.nint <= kMaxCoarse) {
       // the exact coarse solve exists only up to kMaxCoarse unknowns; a larger coarsest level
@@ -475,6 +479,11 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
     launch_diag(L, diag, (double*)P->F, s);
     launch_dinv(L.g, diag, L.dinv64, f32 ? L.dinv32 : nullptr, P->flag, s);
     check_flag(P, s);
+    if (c.smoother == GLLMG_SMOOTH_L1_JACOBI) {
+      launch_l1_rowsum(L, diag, s);
+      launch_dinv(L.g, diag, L.l1inv64, f32 ? L.l1inv32 : nullptr, P->flag, s);
+      check_flag(P, s);
+    }
   }
   for (size_t l = 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
   for (size_t l = 0; l < P->L.size(); ++l)
@@ -487,6 +496,18 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
 
 // ------------------------------------------------------------------ smoothers and cycles
 const void* dinv_of(const Level& L, int pr) { return pr == 0 ? (const void*)L.dinv64 : (const void*)L.dinv32; }
+
+// The inverse diagonal a Jacobi-type smoother scales residuals by: D^{-1}, or D_l1^{-1} for
+// l1-Jacobi (§3.2.3).
+const void* jacobi_dinv(const gllmg_problem* P, const Level& L, int pr) {
+  if (P->cfg.smoother == GLLMG_SMOOTH_L1_JACOBI)
+    return pr == 0 ? (const void*)L.l1inv64 : (const void*)L.l1inv32;
+  return dinv_of(L, pr);
+}
+
+bool jacobi_type(const gllmg_config& c) {
+  return c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_L1_JACOBI;
+}
 
 // Chebyshev interval [cheb_lo lambda, lambda]: its center theta and half-width delta
 void cheb_interval(const gllmg_problem* P, const Level& L, double* theta, double* delta) {
@@ -549,7 +570,8 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
     }
     return;
   }
-  if (P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
+  if (jacobi_type(P->cfg)) {
+    dinv = jacobi_dinv(P, L, pr);
     for (int it = 0; it < k; ++it) {
       if (it == 0 && zero) {
         if (!started) jacobi_step(pr, N, 1, x, b, nullptr, dinv, P->cfg.omega, s);
@@ -660,11 +682,11 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
   // the coarse level's first pre-smoothing step from zero rides on the restriction's gather
   // (Jacobi and Chebyshev; the Gauss-Seidel sweeps start from a cleared vector instead)
   const bool fuse = C.has_coarse && P->cfg.nu_pre > 0 &&
-                    (P->cfg.smoother == GLLMG_SMOOTH_JACOBI || P->cfg.smoother == GLLMG_SMOOTH_CHEBYSHEV);
-  if (fuse && P->cfg.smoother == GLLMG_SMOOTH_JACOBI) {
+                    (jacobi_type(P->cfg) || P->cfg.smoother == GLLMG_SMOOTH_CHEBYSHEV);
+  if (fuse && jacobi_type(P->cfg)) {
     ep.mode = EPI_STORE_JACOBI0;
     ep.x = C.vx[pr];
-    ep.dinv = dinv_of(C, pr);
+    ep.dinv = jacobi_dinv(P, C, pr);
     ep.om = P->cfg.omega;
   } else if (fuse) {
     double theta, delta;
@@ -1019,7 +1041,7 @@ thread_local const LaunchGroup* g_launch_group = nullptr;
 // ------------------------------------------------------------------ launch groups of a batch
 // Smoothers whose kernels take launch groups (the Gauss-Seidel passes do not).
 bool groupable_smoother(int sm) {
-  return sm == GLLMG_SMOOTH_JACOBI || sm == GLLMG_SMOOTH_CHEBYSHEV;
+  return sm == GLLMG_SMOOTH_JACOBI || sm == GLLMG_SMOOTH_CHEBYSHEV || sm == GLLMG_SMOOTH_L1_JACOBI;
 }
 
 // Problems that a launch group can take together: the same levels, smoother and V-cycle
@@ -1037,7 +1059,7 @@ bool same_shape(const gllmg_problem* A, const gllmg_problem* B) {
       o.insert(o.end(), {L.g.ne[0], L.g.ne[1], L.g.ne[2], L.g.p, (int64_t)L.has_coarse,
                          (int64_t)L.tp.nch, off(L.G64), off(L.G32), off(L.D64), off(L.D32),
                          off(L.dinv64), off(L.dinv32), off(L.tp.P64), off(L.tp.P32), off(L.Ainv64),
-                         off(L.Ainv32), off(L.ctab), off(L.zero)});
+                         off(L.Ainv32), off(L.ctab), off(L.zero), off(L.l1inv64), off(L.l1inv32)});
       for (int q = 0; q < 2; ++q)
         o.insert(o.end(), {off(L.vb[q]), off(L.vx[q]), off(L.vr[q]), off(L.vd[q]), off(L.vd2[q]),
                            off(L.vd3[q])});

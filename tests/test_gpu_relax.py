@@ -97,3 +97,71 @@ def test_ssor_batch_equals_alone():
         assert torch.equal(xb, x)
     for P in probs:
         P.close()
+
+
+# ------------------------------------------------------------------ l1-Jacobi (§3.2.3, §4.4.3)
+L1_CASES = [(2, (3, 2), 3), (2, (2, 2), 16), (3, (2, 1, 2), 4), (3, (1, 2, 1), 8),
+            (3, (3, 2, 2), 1), (3, (2, 2, 1), 2), (3, (1, 1, 1), 16)]
+
+
+@pytest.mark.parametrize("dim,ne,p", L1_CASES)
+def test_l1_jacobi_smoother_fp64(dim, ne, p):
+    G, H = build_pair(dim, ne, p, smoother="l1jacobi", nu=3, max_levels=2)
+    lv = H.levels[0]
+    b = random_vec(lv.mesh.N, 25) * lv.mesh.interior
+    x0 = random_vec(lv.mesh.N, 26) * lv.mesh.interior
+    for k in (1, 3):
+        for zero in (True, False):
+            xg = to_dev(x0.copy())
+            G.smooth(to_dev(b), xg, k, 0, zero_guess=zero)
+            xo = H.smooth(0, b, None if zero else x0.copy(), steps=k)
+            ok, e = fp64_close(to_np(xg), xo)
+            assert ok, (k, zero, e)
+    G.close()
+
+
+@pytest.mark.parametrize("dim,ne,p,hier", [(2, (4, 4), 4, "h"), (3, (2, 2, 2), 4, "p"),
+                                           (3, (2, 2, 2), 8, "p")])
+def test_l1_jacobi_vcycle_and_pcg(dim, ne, p, hier):
+    G, H = build_pair(dim, ne, p, hierarchy=hier, smoother="l1jacobi", nu=3)
+    m = H.fine.mesh
+    r = random_vec(m.N, 29) * m.interior
+    assert rel_err(to_np(G.vcycle(to_dev(r))), H.vcycle(r)) <= 1e-10
+    f = np.random.default_rng(4).uniform(-1, 1, m.N)
+    b = fem.load_vector(m, f)
+    ro = mg.pcg(H, b, rtol=1e-10)
+    rg = G.solve(G.rhs(to_dev(f)), rtol=1e-10)
+    assert rg.converged and ro.converged and rg.iters == ro.iters, (rg.iters, ro.iters)
+    assert rel_err(rg.history, ro.history) <= 1e-8
+    G.close()
+
+
+def test_l1_jacobi_fp32_and_launch_group():
+    import torch
+    from paper_1402_5938_amd import gllmg, inputs
+    G, H = build_pair(3, (2, 1, 2), 4, smoother="l1jacobi", nu=3, max_levels=2, vcycle_prec="f32")
+    lv = H.levels[0]
+    b = random_vec(lv.mesh.N, 31) * lv.mesh.interior
+    x = torch.zeros(lv.mesh.N, dtype=torch.float32, device="cuda")
+    G.smooth(to_dev(b, torch.float32), x, 3, 0, zero_guess=True)
+    assert rel_err(to_np(x), H.smooth(0, b, None, steps=3)) <= 1e-5
+    G.close()
+    # two problems of one shape form a launch group: results equal solving alone, bit for bit
+    probs, bs = [], []
+    for s in range(2):
+        cfg = gllmg.make_config(3, (2, 2, 2), 4, "p", "l1jacobi", 3, vcycle_prec="f32")
+        P = gllmg.Problem(cfg, inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(1.0 + s))
+        f = torch.from_numpy(np.random.default_rng(s).uniform(-1, 1, P.nnodes(0))).cuda()
+        probs.append(P)
+        bs.append(P.rhs(f))
+    alone = []
+    for P, b in zip(probs, bs):
+        xa = torch.zeros_like(b)
+        alone.append((P.solve(b, xa, rtol=1e-10), xa))
+    xs = [torch.zeros_like(b) for b in bs]
+    res = gllmg.batch_solve(probs, bs, xs, rtol=1e-10)
+    for (r, xa), rb, xb in zip(alone, res, xs):
+        assert rb.converged and rb.iters == r.iters
+        assert torch.equal(xb, xa)
+    for P in probs:
+        P.close()

@@ -75,6 +75,8 @@ struct Level {
   float* dinv32 = nullptr;
   double* l1inv64 = nullptr;  // l1-Jacobi smoother: 1 / sum_j |A_ij| (interior), else unused
   float* l1inv32 = nullptr;
+  double* Binv64 = nullptr;   // block Jacobi: E inverted padded blocks of p^d x p^d
+  float* Binv32 = nullptr;
   double lmax = 0.0;
   // V-cycle scratch in the V-cycle precision (and an FP64 set for FP64 calls)
   void* vb[2] = {nullptr, nullptr};
@@ -225,6 +227,13 @@ void launch_gs_color(const Level& L, int prec, const void* b, void* x, const voi
 void zero_boundary(const Level& L, int prec, void* v, hipStream_t s);
 // l1 row sums of the interior block, sum_j |A_ij| over interior j (0 at boundary rows); FP64
 void launch_l1_rowsum(const Level& L, double* out, hipStream_t s);
+// Element block Jacobi: P = p^d slots per element; B = E padded P x P blocks (FP64), filled with
+// the assembled owned-node blocks and inverted in place (flag bit 8: a non-positive pivot)
+int block_slots(const Level& L);
+void launch_block_setup(const Level& L, double* B, int* flag, hipStream_t s);
+// x += omega Binv^T r per element block (the owned interior nodes)
+void launch_block_apply(const Level& L, int prec, const void* Binv, const void* r, void* x,
+                        double omega, hipStream_t s);
 
 // The allocation-free product's element-vector buffer: a file-scope device array of this many
 // bytes (one per device, shared by every call on that device). static_scratch(dev) returns its

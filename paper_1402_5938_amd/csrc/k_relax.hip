@@ -319,6 +319,167 @@ k_l1_rowsum(const double* __restrict__ G, const double* __restrict__ Dm, Grid g,
   out[t] = acc;
 }
 
+// ------------------------------------------------------------------ element block Jacobi
+// Blocks (§3.2.3, §4.4.3): element e owns, along each axis, its local nodes 0..p-1 (the last
+// element also p, always a boundary node), so every interior node lies in exactly one block.
+// Block e is stored as a padded P x P matrix, P = p^d, over the slots s = i + p (j + p k) of the
+// local nodes [0, p)^d: slots of owned interior nodes hold A restricted to them, slots of
+// boundary nodes (local 0 on an element at the low domain face) an identity row and column, so
+// the inverse of the padded matrix is the block inverse beside an identity.
+
+// The elements holding global grid index gi along an axis (one below first; 1 or 2).
+__device__ __forceinline__ int holders(int gi, int p, int ne, int* e) {
+  if (gi % p == 0 && gi > 0 && gi < ne * p) {
+    e[0] = gi / p - 1;
+    e[1] = gi / p;
+    return 2;
+  }
+  e[0] = e[1] = min(gi / p, ne - 1);
+  return 1;
+}
+
+// A_ij of the assembled stiffness between global nodes gi and gj: (K_e)_ij summed over the
+// elements holding both.
+__device__ double assembled_entry(const double* __restrict__ G, const double* __restrict__ Dm,
+                                  const Grid& g, const int* gi, const int* gj) {
+  const int dim = g.dim, p = g.p, n = p + 1;
+  int ce[3][2], nc[3];
+  for (int a = 0; a < 3; ++a) {
+    if (a >= dim) {
+      nc[a] = 1;
+      ce[a][0] = 0;
+      continue;
+    }
+    int ei[2], ej[2];
+    const int ni = holders(gi[a], p, g.ne[a], ei), nj = holders(gj[a], p, g.ne[a], ej);
+    nc[a] = 0;
+    for (int u = 0; u < ni; ++u)
+      for (int v = 0; v < nj; ++v)
+        if (ei[u] == ej[v]) ce[a][nc[a]++] = ei[u];
+    if (nc[a] == 0) return 0.0;
+  }
+  const int nloc = dim == 3 ? n * n * n : n * n;
+  const int ncomp = dim == 3 ? 6 : 3;
+  double aij = 0.0;
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        const int e3[3] = {ce[0][cx], ce[1][cy], ce[2][cz]};
+        int li[3], lj[3];
+        for (int a = 0; a < 3; ++a) {
+          li[a] = a < dim ? gi[a] - e3[a] * p : 0;
+          lj[a] = a < dim ? gj[a] - e3[a] * p : 0;
+        }
+        const int64_t e = e3[0] + (int64_t)g.ne[0] * (e3[1] + (int64_t)g.ne[1] * e3[2]);
+        aij += elem_entry(G + e * (int64_t)ncomp * nloc, Dm, n, dim, li, lj);
+      }
+  return aij;
+}
+
+// Fill the padded blocks: one thread per (element, row slot, column slot).
+__global__ void __launch_bounds__(256)
+k_block_fill(const double* __restrict__ G, const double* __restrict__ Dm, Grid g, int P,
+             double* __restrict__ B) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t PP = (int64_t)P * P;
+  if (t >= g.E * PP) return;
+  const int64_t e = t / PP;
+  const int rs = (int)((t - e * PP) / P), cs = (int)(t - e * PP - (int64_t)rs * P);
+  const int dim = g.dim, p = g.p;
+  const int ex = (int)(e % g.ne[0]), ey = (int)((e / g.ne[0]) % g.ne[1]),
+            ez = (int)(e / ((int64_t)g.ne[0] * g.ne[1]));
+  const int eo[3] = {ex * p, ey * p, ez * p};
+  const int ls[2][3] = {{rs % p, (rs / p) % p, dim == 3 ? rs / (p * p) : 0},
+                        {cs % p, (cs / p) % p, dim == 3 ? cs / (p * p) : 0}};
+  int gi[3] = {0, 0, 0}, gj[3] = {0, 0, 0};
+  bool bi = false, bj = false;
+  for (int a = 0; a < dim; ++a) {
+    gi[a] = eo[a] + ls[0][a];
+    gj[a] = eo[a] + ls[1][a];
+    bi = bi || gi[a] == 0;
+    bj = bj || gj[a] == 0;
+  }
+  double v;
+  if (bi || bj)
+    v = rs == cs ? 1.0 : 0.0;
+  else
+    v = assembled_entry(G, Dm, g, gi, gj);
+  B[t] = v;
+}
+
+// In-place inverse of each P x P block by Gauss-Jordan elimination without pivoting (the blocks
+// are SPD, so every pivot is positive): at step k, with the old row k and column k kept,
+//   a_kk <- 1/a_kk,  a_kj <- a_kj / a_kk,  a_ik <- -a_ik / a_kk,  a_ij <- a_ij - a_ik a_kj / a_kk.
+// One workgroup per block; the block lives in global memory (P <= kBlockMaxP).
+constexpr int kBlockMaxP = 1024;
+__global__ void __launch_bounds__(1024) k_block_invert(double* __restrict__ B, int P, int* flag) {
+  double* A = B + (int64_t)blockIdx.x * P * P;
+  __shared__ double rowk[kBlockMaxP], colk[kBlockMaxP];
+  const int64_t PP = (int64_t)P * P;
+  for (int k = 0; k < P; ++k) {
+    for (int q = threadIdx.x; q < P; q += blockDim.x) {
+      rowk[q] = A[(int64_t)k * P + q];
+      colk[q] = A[(int64_t)q * P + k];
+    }
+    __syncthreads();
+    const double akk = rowk[k];
+    if (!(akk > 0.0)) {
+      if (threadIdx.x == 0) atomicOr(flag, 8);
+      return;  // the whole workgroup sees the same pivot and leaves together
+    }
+    const double piv = 1.0 / akk;
+    for (int64_t q = threadIdx.x; q < PP; q += blockDim.x) {
+      const int i = (int)(q / P), j = (int)(q - (int64_t)i * P);
+      double v;
+      if (i == k)
+        v = j == k ? piv : rowk[j] * piv;
+      else if (j == k)
+        v = -colk[i] * piv;
+      else
+        v = A[q] - colk[i] * rowk[j] * piv;
+      A[q] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// One block-Jacobi update x <- x + omega B^{-1} r per element: the workgroup gathers r at the
+// element's slots into LDS, each thread forms z_s = sum_t Binv[t][s] r_t for its slots (the
+// stored inverse read by columns: consecutive threads, consecutive words) and updates the owned
+// interior nodes. r at boundary slots is 0.
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256)
+k_block_apply(const T* __restrict__ Binv, const T* __restrict__ r, T* __restrict__ x, Grid g,
+              int P, T omega) {
+  extern __shared__ unsigned char smem[];
+  T* sr = (T*)smem;
+  const int64_t e = blockIdx.x;
+  const int p = g.p;
+  const int ex = (int)(e % g.ne[0]), ey = (int)((e / g.ne[0]) % g.ne[1]),
+            ez = DIM == 3 ? (int)(e / ((int64_t)g.ne[0] * g.ne[1])) : 0;
+  const int64_t sy = g.nn[0], sz = (int64_t)g.nn[0] * g.nn[1];
+  auto node = [&](int s, bool* bnd) {
+    const int i = s % p, j = (s / p) % p, k = DIM == 3 ? s / (p * p) : 0;
+    const int gx = ex * p + i, gy = ey * p + j, gz = ez * p + k;
+    *bnd = gx == 0 || gy == 0 || (DIM == 3 && gz == 0);
+    return gx + sy * gy + sz * gz;
+  };
+  for (int s = threadIdx.x; s < P; s += blockDim.x) {
+    bool bnd;
+    const int64_t gidx = node(s, &bnd);
+    sr[s] = bnd ? T(0) : r[gidx];
+  }
+  __syncthreads();
+  const T* Be = Binv + e * (int64_t)P * P;
+  for (int s = threadIdx.x; s < P; s += blockDim.x) {
+    T z = T(0);
+    for (int t = 0; t < P; ++t) z += Be[(int64_t)t * P + s] * sr[t];
+    bool bnd;
+    const int64_t gidx = node(s, &bnd);
+    if (!bnd) x[gidx] = x[gidx] + omega * z;
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_zero_boundary(T* __restrict__ v, Grid g) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -380,6 +541,47 @@ void launch_gs_color(const Level& L, int prec, const void* b, void* x, const voi
 void launch_l1_rowsum(const Level& L, double* out, hipStream_t s) {
   const unsigned nb = (unsigned)((L.g.N + 255) / 256);
   hipLaunchKernelGGL(k_l1_rowsum, dim3(nb), dim3(256), 0, s, L.G64, L.D64, L.g, out);
+  GLLMG_HIP(hipGetLastError());
+}
+
+int block_slots(const Level& L) {
+  int P = 1;
+  for (int a = 0; a < L.g.dim; ++a) P *= L.g.p;
+  return P;
+}
+
+void launch_block_setup(const Level& L, double* B, int* flag, hipStream_t s) {
+  const int P = block_slots(L);
+  GLLMG_CHECK(P <= kBlockMaxP, GLLMG_EUNSUPPORTED,
+              "block Jacobi: element blocks of p^d > 1024 unknowns are not supported");
+  const int64_t tot = L.g.E * (int64_t)P * P;
+  hipLaunchKernelGGL(k_block_fill, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.G64,
+                     L.D64, L.g, P, B);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_block_invert, dim3((unsigned)L.g.E), dim3(1024), 0, s, B, P, flag);
+  GLLMG_HIP(hipGetLastError());
+}
+
+void launch_block_apply(const Level& L, int prec, const void* Binv, const void* r, void* x,
+                        double omega, hipStream_t s) {
+  const int P = block_slots(L);
+  const size_t lds = (size_t)P * (prec == 0 ? sizeof(double) : sizeof(float));
+  const dim3 grid((unsigned)L.g.E), block(256);
+  if (prec == 0) {
+    if (L.g.dim == 3)
+      hipLaunchKernelGGL((k_block_apply<double, 3>), grid, block, lds, s, (const double*)Binv,
+                         (const double*)r, (double*)x, L.g, P, omega);
+    else
+      hipLaunchKernelGGL((k_block_apply<double, 2>), grid, block, lds, s, (const double*)Binv,
+                         (const double*)r, (double*)x, L.g, P, omega);
+  } else {
+    if (L.g.dim == 3)
+      hipLaunchKernelGGL((k_block_apply<float, 3>), grid, block, lds, s, (const float*)Binv,
+                         (const float*)r, (float*)x, L.g, P, (float)omega);
+    else
+      hipLaunchKernelGGL((k_block_apply<float, 2>), grid, block, lds, s, (const float*)Binv,
+                         (const float*)r, (float*)x, L.g, P, (float)omega);
+  }
   GLLMG_HIP(hipGetLastError());
 }
 

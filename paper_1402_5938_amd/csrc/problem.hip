@@ -36,8 +36,15 @@ void validate(const gllmg_config& c) {
   GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P, GLLMG_EINVAL,
               "hierarchy must be GLLMG_HIER_H or GLLMG_HIER_P");
   GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
-                  c.smoother == GLLMG_SMOOTH_SSOR || c.smoother == GLLMG_SMOOTH_L1_JACOBI,
+                  c.smoother == GLLMG_SMOOTH_SSOR || c.smoother == GLLMG_SMOOTH_L1_JACOBI ||
+                  c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI,
               GLLMG_EINVAL, "unknown smoother");
+  if (c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
+    int P = 1;
+    for (int a = 0; a < c.dim; ++a) P *= c.order;
+    GLLMG_CHECK(P <= 1024, GLLMG_EUNSUPPORTED,
+                "block Jacobi needs element blocks of at most 1024 unknowns (p^d <= 1024)");
+  }
   GLLMG_CHECK(c.nu_pre >= 0 && c.nu_post >= 0 && c.nu_pre <= 64 && c.nu_post <= 64, GLLMG_EINVAL,
               "smoothing steps out of range");
   GLLMG_CHECK(c.omega > 0.0 && c.omega < 2.0, GLLMG_EINVAL, "omega out of range");
@@ -205,6 +212,11 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
     if (c.smoother == GLLMG_SMOOTH_L1_JACOBI) {
       L.l1inv64 = (double*)A.take(sizeof(double) * L.g.N);
       L.l1inv32 = f32 ? (float*)A.take(sizeof(float) * L.g.N) : nullptr;
+    }
+    if (c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
+      const size_t PP = (size_t)block_slots(L) * block_slots(L);
+      L.Binv64 = (double*)A.take(sizeof(double) * L.g.E * PP);
+      L.Binv32 = f32 ? (float*)A.take(sizeof(float) * L.g.E * PP) : nullptr;
     }
     face = std::max(face, face_buffer_elems(L));
     if (!L.has_coarse && L.nint <= kMaxCoarse) {
@@ -449,6 +461,7 @@ void check_flag(gllmg_problem* P, hipStream_t s) {
   GLLMG_CHECK(!(f & 1), GLLMG_EINVAL, "detJ <= 0 at a quadrature point: the map is not a diffeomorphism");
   GLLMG_CHECK(!(f & 2), GLLMG_EINVAL, "mu is not positive and finite at a quadrature point");
   GLLMG_CHECK(!(f & 4), GLLMG_EINVAL, "the operator diagonal is not positive");
+  GLLMG_CHECK(!(f & 8), GLLMG_EINVAL, "an element block of the block-Jacobi smoother is not positive definite");
 }
 
 void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu, hipStream_t s) {
@@ -483,6 +496,11 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
       launch_l1_rowsum(L, diag, s);
       launch_dinv(L.g, diag, L.l1inv64, f32 ? L.l1inv32 : nullptr, P->flag, s);
       check_flag(P, s);
+    }
+    if (c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
+      launch_block_setup(L, L.Binv64, P->flag, s);
+      check_flag(P, s);
+      if (f32) cast_64_32(L.g.E * (int64_t)block_slots(L) * block_slots(L), L.Binv64, L.Binv32, s);
     }
   }
   for (size_t l = 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
@@ -567,6 +585,23 @@ void smooth_impl(gllmg_problem* P, int l, int pr, const void* b, void* x, int k,
       for (int c = 0; c < C; ++c) launch_gs_color(L, pr, b, x, dinv, c, P->cfg.omega, s);
       for (int c = C - 1; c >= 0; --c) launch_gs_color(L, pr, b, x, dinv, c, P->cfg.omega, s);
       L.applies += 2;  // a forward and a backward sweep: about two products' arithmetic
+    }
+    return;
+  }
+  if (P->cfg.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
+    // k steps x += omega B^{-1} (b - A x): the residual product, then the element-block update
+    const void* Binv = pr == 0 ? (const void*)L.Binv64 : (const void*)L.Binv32;
+    if (zero)
+      vec_zero(pr, N, x, s);
+    else
+      zero_boundary(L, pr, x, s);
+    for (int it = 0; it < k; ++it) {
+      if (it == 0 && zero) {
+        launch_block_apply(L, pr, Binv, b, x, P->cfg.omega, s);  // r = b
+      } else {
+        residual(P, l, pr, b, x, r, s);
+        launch_block_apply(L, pr, Binv, r, x, P->cfg.omega, s);
+      }
     }
     return;
   }

@@ -165,3 +165,59 @@ def test_l1_jacobi_fp32_and_launch_group():
         assert torch.equal(xb, xa)
     for P in probs:
         P.close()
+
+
+# ------------------------------------------------------------------ element block Jacobi
+BJ_CASES = [(2, (3, 2), 3), (2, (2, 2), 16), (3, (2, 1, 2), 4), (3, (1, 2, 1), 8),
+            (3, (3, 2, 2), 1), (3, (2, 2, 1), 2), (3, (2, 1, 1), 10)]
+
+
+@pytest.mark.parametrize("dim,ne,p", BJ_CASES)
+def test_block_jacobi_smoother_fp64(dim, ne, p):
+    G, H = build_pair(dim, ne, p, smoother="blockjacobi", nu=3, max_levels=2)
+    lv = H.levels[0]
+    b = random_vec(lv.mesh.N, 35) * lv.mesh.interior
+    x0 = random_vec(lv.mesh.N, 36)
+    for k in (1, 3):
+        for zero in (True, False):
+            xg = to_dev(x0.copy())
+            G.smooth(to_dev(b), xg, k, 0, zero_guess=zero)
+            xo = H.smooth(0, b, None if zero else x0 * lv.mesh.interior, steps=k)
+            ok, e = fp64_close(to_np(xg), xo)
+            assert ok, (k, zero, e)
+    G.close()
+
+
+@pytest.mark.parametrize("dim,ne,p,hier", [(2, (4, 4), 4, "h"), (3, (2, 2, 2), 4, "p"),
+                                           (3, (2, 2, 2), 8, "p")])
+def test_block_jacobi_vcycle_and_pcg(dim, ne, p, hier):
+    G, H = build_pair(dim, ne, p, hierarchy=hier, smoother="blockjacobi", nu=3)
+    m = H.fine.mesh
+    r = random_vec(m.N, 39) * m.interior
+    assert rel_err(to_np(G.vcycle(to_dev(r))), H.vcycle(r)) <= 1e-10
+    f = np.random.default_rng(5).uniform(-1, 1, m.N)
+    b = fem.load_vector(m, f)
+    for mode in ("pcg", "mg"):
+        ro = mg.pcg(H, b, rtol=1e-10) if mode == "pcg" else mg.mg_solve(H, b, rtol=1e-10)
+        rg = G.solve(G.rhs(to_dev(f)), mode=mode, rtol=1e-10)
+        assert rg.converged and ro.converged and rg.iters == ro.iters, (mode, rg.iters, ro.iters)
+        assert rel_err(rg.history, ro.history) <= 1e-8
+    G.close()
+
+
+def test_block_jacobi_fp32_and_limits():
+    import torch
+    from paper_1402_5938_amd import gllmg, inputs
+    G, H = build_pair(3, (2, 1, 2), 4, smoother="blockjacobi", nu=3, max_levels=2,
+                      vcycle_prec="f32")
+    lv = H.levels[0]
+    b = random_vec(lv.mesh.N, 41) * lv.mesh.interior
+    x = torch.zeros(lv.mesh.N, dtype=torch.float32, device="cuda")
+    G.smooth(to_dev(b, torch.float32), x, 3, 0, zero_guess=True)
+    assert rel_err(to_np(x), H.smooth(0, b, None, steps=3)) <= 1e-5
+    G.close()
+    # element blocks beyond 1024 unknowns (3D p = 11: 1331) are refused at planning
+    cfg = gllmg.make_config(3, (1, 1, 1), 11, "p", "blockjacobi", 3)
+    with pytest.raises(gllmg.GllmgError) as e:
+        gllmg.plan(cfg)
+    assert e.value.status == gllmg.EUNSUPPORTED

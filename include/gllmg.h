@@ -82,19 +82,34 @@ enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1 };
  *   EXP_FOURIER       exp(sqrt(2/J) sum_j a_j cos(2 pi k_j.x + phi_j)); nmodes = J and
  *                     modes = host array of J rows [k0, k1, k2, a, phi] (copied at setup)
  *   SIN_PRODUCT       param[0] prod_i sin(param[1] pi x_i)
- *   COS2_SUM          param[0] + param[1] sum_i cos^2(param[2] pi x_i)   (paper §4.1 form) */
+ *   COS2_SUM          param[0] + param[1] sum_i cos^2(param[2] pi x_i)   (paper §4.1 form)
+ *   MAP_CALLBACK      any map Phi given by the caller (the smooth diffeomorphism of §2.3):
+ *                     fn(X, npts, dim, x, ctx) writes x = Phi(X) for npts reference points X
+ *                     (row-major npts x dim in, npts x dim out)
+ *   FIELD_CALLBACK    any coefficient mu(x) given by the caller (§2, Eq. (Poisson)):
+ *                     fn(x, npts, dim, out, ctx) writes out[i] = mu(x_i) at npts physical points
+ * Callbacks run only inside gllmg_setup, on the calling thread, once per level, with the points
+ * of every node of that level in node order (collocated quadrature needs Phi and mu at the nodes
+ * only); their values are copied to the device. After setup a problem with a callback map does
+ * not provide gllmg_node_coords or gllmg_eval_field (EUNSUPPORTED), and gllmg_eval_field does not
+ * take a callback field (EINVAL). */
 enum {
-  GLLMG_MAP_IDENTITY = 0, GLLMG_MAP_WARP_SINE = 1, GLLMG_MAP_AFFINE = 2,
+  GLLMG_MAP_IDENTITY = 0, GLLMG_MAP_WARP_SINE = 1, GLLMG_MAP_AFFINE = 2, GLLMG_MAP_CALLBACK = 3,
   GLLMG_FIELD_CONST = 10, GLLMG_FIELD_EXP_SINE_PRODUCT = 11, GLLMG_FIELD_EXP_FOURIER = 12,
-  GLLMG_FIELD_SIN_PRODUCT = 13, GLLMG_FIELD_COS2_SUM = 14
+  GLLMG_FIELD_SIN_PRODUCT = 13, GLLMG_FIELD_COS2_SUM = 14, GLLMG_FIELD_CALLBACK = 20
 };
 #define GLLMG_MAX_MODES 64
+
+typedef void (*gllmg_field_fn)(const double* pts, int64_t npts, int32_t dim, double* out,
+                               void* ctx);
 
 typedef struct {
   int32_t kind;
   int32_t nmodes;
   double param[12];
   const double* modes;   /* host pointer, nmodes x 5 doubles, or NULL */
+  gllmg_field_fn fn;     /* MAP_CALLBACK / FIELD_CALLBACK: the host function, else NULL */
+  void* ctx;             /* passed to fn unchanged */
 } gllmg_field;
 
 typedef struct {

@@ -35,6 +35,8 @@ def eval_map(desc: dict, X: np.ndarray) -> np.ndarray:
         M = np.array(prm[:d * d]).reshape(d, d)
         c = np.array(prm[d * d:d * d + d])
         return X @ M.T + c[None, :]
+    if kind == "map_callback":          # a map the caller gives as a function (§2.3)
+        return np.asarray(desc["fn"](X.copy()), dtype=np.float64).reshape(X.shape)
     raise ValueError(f"unknown map kind {kind!r}")
 
 
@@ -46,6 +48,8 @@ def eval_scalar(desc: dict, x: np.ndarray) -> np.ndarray:
     prm = list(desc.get("param") or [])
     if kind == "const":
         return np.full(x.shape[0], prm[0])
+    if kind == "callback":              # a coefficient the caller gives as a function (§2)
+        return np.asarray(desc["fn"](x.copy()), dtype=np.float64).reshape(x.shape[0])
     if kind == "exp_sine_product":
         amp = prm[0]
         prod = np.ones(x.shape[0])

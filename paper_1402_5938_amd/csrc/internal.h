@@ -128,8 +128,11 @@ bool spd_inverse(std::vector<double>& A, int n);
 
 // ------------------------------------------------------------------ kernel launchers
 // precision index: 0 = double, 1 = float
-void launch_geometry(const Level& L, const FieldDev& map, const FieldDev& mu, double* G64,
+// Geometric factors of a level from the physical coordinates xn (N x dim) and mu (N) at its nodes
+void launch_geometry(const Level& L, const double* xn, const double* mun, double* G64,
                      float* G32, double* wdet, int* flag, hipStream_t s);
+// a field at given physical node coordinates xn (N x dim)
+void launch_field_at(const Grid& g, const double* xn, const FieldDev& f, double* out, hipStream_t s);
 void launch_gather_full(const Level& L, const double* elem_vals, double* out, hipStream_t s);
 void launch_node_coords(const Grid& g, const double* xi, const FieldDev& map, double* out,
                         hipStream_t s);

@@ -12,13 +12,15 @@ constexpr int kThreads = 256;
 inline unsigned nblocks(int64_t n, int t = kThreads) { return (unsigned)((n + t - 1) / t); }
 
 // Geometry at one GLL point q of element e (paper §2.3): J_ab = d x_a / d xi_b of the degree-p
-// interpolant of Phi through the element's nodes, i.e. sum_l D[q_b, l] Phi_a(X(q with b -> l));
-// G = w_q mu(x_q) detJ J^{-1} J^{-T}; also w_q detJ for the lumped mass.
+// interpolant of Phi through the element's nodes, sum_l D[q_b, l] x_a(node q with b -> l), from
+// the physical coordinates xn of the level's nodes (N x dim); G = w_q mu_q detJ J^{-1} J^{-T}
+// with mu_q = mun at the node (collocated quadrature: the points are the nodes); also w_q detJ.
 template <int DIM>
 __global__ void __launch_bounds__(kThreads)
-k_geometry(Grid g, int n, const double* __restrict__ xi, const double* __restrict__ w,
-           const double* __restrict__ D, FieldDev map, FieldDev mu, double* __restrict__ G64,
-           float* __restrict__ G32, double* __restrict__ wdet, int* __restrict__ flag) {
+k_geometry(Grid g, int n, const double* __restrict__ w, const double* __restrict__ D,
+           const double* __restrict__ xn, const double* __restrict__ mun,
+           double* __restrict__ G64, float* __restrict__ G32, double* __restrict__ wdet,
+           int* __restrict__ flag) {
   int nloc = n * n;
   if (DIM == 3) nloc *= n;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -32,20 +34,17 @@ k_geometry(Grid g, int n, const double* __restrict__ xi, const double* __restric
   qc[0] = q % n;
   qc[1] = (q / n) % n;
   qc[2] = (DIM == 3) ? q / (n * n) : 0;
-  double Xq[3], xq[3];
-  for (int a = 0; a < DIM; ++a) Xq[a] = ref_coord(ec[a], qc[a], g.ne[a], xi);
+  const int64_t st[3] = {1, g.nn[0], (int64_t)g.nn[0] * g.nn[1]};
+  int64_t node = 0;  // global index of the point's node
+  for (int a = 0; a < DIM; ++a) node += (int64_t)(ec[a] * (n - 1) + qc[a]) * st[a];
   double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int b = 0; b < DIM; ++b) {
     for (int l = 0; l < n; ++l) {
-      double X[3] = {Xq[0], Xq[1], Xq[2]};
-      X[b] = ref_coord(ec[b], l, g.ne[b], xi);
-      double x[3];
-      map_eval(map, DIM, X, x);
+      const int64_t nb = node + (int64_t)(l - qc[b]) * st[b];
       const double dq = D[qc[b] * n + l];
-      for (int a = 0; a < DIM; ++a) J[a][b] += dq * x[a];
+      for (int a = 0; a < DIM; ++a) J[a][b] += dq * xn[nb * DIM + a];
     }
   }
-  map_eval(map, DIM, Xq, xq);
   double wq = w[qc[0]] * w[qc[1]];
   if (DIM == 3) wq *= w[qc[2]];
   double det, I[3][3];
@@ -71,7 +70,7 @@ k_geometry(Grid g, int n, const double* __restrict__ xi, const double* __restric
     I[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
   }
   if (!(det > 0.0)) atomicOr(flag, 1);
-  const double m = field_eval(mu, DIM, xq);
+  const double m = mun[node];
   if (!(m > 0.0) || !isfinite(m)) atomicOr(flag, 2);
   const double sc = wq * m * det;
   const int ncomp = (DIM == 3) ? 6 : 3;
@@ -165,6 +164,15 @@ __global__ void k_eval_field(Grid g, const double* __restrict__ xi, FieldDev map
   out[t] = field_eval(f, g.dim, x);
 }
 
+// A field at given physical node coordinates xn (N x dim).
+__global__ void k_field_at(Grid g, const double* __restrict__ xn, FieldDev f, double* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  double x[3] = {0, 0, 0};
+  for (int a = 0; a < g.dim; ++a) x[a] = xn[t * g.dim + a];
+  out[t] = field_eval(f, g.dim, x);
+}
+
 __device__ inline bool on_boundary(const Grid& g, int64_t t) {
   const int gx = (int)(t % g.nn[0]);
   const int gy = (int)((t / g.nn[0]) % g.nn[1]);
@@ -215,15 +223,20 @@ __global__ void k_start_vector(Grid g, uint64_t seed, int level, double* __restr
 
 }  // namespace
 
-void launch_geometry(const Level& L, const FieldDev& map, const FieldDev& mu, double* G64,
+void launch_geometry(const Level& L, const double* xn, const double* mun, double* G64,
                      float* G32, double* wdet, int* flag, hipStream_t s) {
   const int64_t tot = L.npts;
   if (L.g.dim == 2)
-    hipLaunchKernelGGL(k_geometry<2>, dim3(nblocks(tot)), dim3(kThreads), 0, s, L.g, L.n, L.xi64,
-                       L.w64, L.D64, map, mu, G64, G32, wdet, flag);
+    hipLaunchKernelGGL(k_geometry<2>, dim3(nblocks(tot)), dim3(kThreads), 0, s, L.g, L.n, L.w64,
+                       L.D64, xn, mun, G64, G32, wdet, flag);
   else
-    hipLaunchKernelGGL(k_geometry<3>, dim3(nblocks(tot)), dim3(kThreads), 0, s, L.g, L.n, L.xi64,
-                       L.w64, L.D64, map, mu, G64, G32, wdet, flag);
+    hipLaunchKernelGGL(k_geometry<3>, dim3(nblocks(tot)), dim3(kThreads), 0, s, L.g, L.n, L.w64,
+                       L.D64, xn, mun, G64, G32, wdet, flag);
+  GLLMG_HIP(hipGetLastError());
+}
+
+void launch_field_at(const Grid& g, const double* xn, const FieldDev& f, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_field_at, dim3(nblocks(g.N)), dim3(kThreads), 0, s, g, xn, f, out);
   GLLMG_HIP(hipGetLastError());
 }
 

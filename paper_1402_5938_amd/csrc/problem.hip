@@ -119,6 +119,9 @@ struct gllmg_problem {
   std::vector<Level> L;
   std::vector<RefElem> re;
   FieldDev map{}, mu{};
+  gllmg_field_fn map_fn = nullptr, mu_fn = nullptr;  // callback kinds (used during setup only)
+  void* map_ctx = nullptr;
+  void* mu_ctx = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   bool owns_ws = false;
@@ -277,7 +280,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const size_t setup = sizeof(double) * (size_t)std::max<int64_t>(
                                             (int64_t)c.eig_steps * maxN + 4 * maxN +
                                                 (int64_t)(c.eig_steps + 1) * (3 + kMdBlocks),
-                                            P->L[0].npts + maxN) + 4096;
+                                            P->L[0].npts + 4 * maxN) + 4096;
   if (setup > steady) A.take(setup - steady);
   P->scratch_bytes = A.used - before;
   return A.used + 256;
@@ -289,11 +292,14 @@ FieldDev to_dev(const gllmg_field* f, double* dev_modes, hipStream_t s, bool is_
   d.kind = f->kind;
   if (is_map)
     GLLMG_CHECK(f->kind == GLLMG_MAP_IDENTITY || f->kind == GLLMG_MAP_WARP_SINE ||
-                    f->kind == GLLMG_MAP_AFFINE,
+                    f->kind == GLLMG_MAP_AFFINE || f->kind == GLLMG_MAP_CALLBACK,
                 GLLMG_EINVAL, "unknown map kind");
   else
-    GLLMG_CHECK(f->kind >= GLLMG_FIELD_CONST && f->kind <= GLLMG_FIELD_COS2_SUM, GLLMG_EINVAL,
-                "unknown field kind");
+    GLLMG_CHECK((f->kind >= GLLMG_FIELD_CONST && f->kind <= GLLMG_FIELD_COS2_SUM) ||
+                    f->kind == GLLMG_FIELD_CALLBACK,
+                GLLMG_EINVAL, "unknown field kind");
+  if (f->kind == GLLMG_MAP_CALLBACK || f->kind == GLLMG_FIELD_CALLBACK)
+    GLLMG_CHECK(f->fn != nullptr, GLLMG_EINVAL, "a callback field needs fn");
   for (int i = 0; i < 12; ++i) d.param[i] = f->param[i];
   d.nmodes = 0;
   d.modes = dev_modes;
@@ -464,11 +470,62 @@ void check_flag(gllmg_problem* P, hipStream_t s) {
   GLLMG_CHECK(!(f & 8), GLLMG_EINVAL, "an element block of the block-Jacobi smoother is not positive definite");
 }
 
+// Phi and mu at every node of level l, into `nodal` (N dim coordinates, then N values of mu):
+// the built-in families by the same kernels as gllmg_node_coords and gllmg_eval_field; callback
+// kinds by the caller's functions, called once with every node of the level in node order
+// (Phi at the reference coordinates, mu at the physical ones) and copied to the device.
+void nodal_fields(gllmg_problem* P, int l, double* nodal, hipStream_t s) {
+  const Level& L = P->L[l];
+  const int dim = L.g.dim;
+  const int64_t N = L.g.N;
+  double* xn = nodal;
+  double* mun = nodal + (size_t)N * dim;
+  std::vector<double> x;
+  if (P->map_fn) {
+    const RefElem& re = P->re[l];
+    std::vector<double> X((size_t)N * dim);
+    x.resize((size_t)N * dim);
+    for (int64_t t = 0; t < N; ++t) {
+      const int64_t gc[3] = {t % L.g.nn[0], (t / L.g.nn[0]) % L.g.nn[1],
+                             t / ((int64_t)L.g.nn[0] * L.g.nn[1])};
+      for (int a = 0; a < dim; ++a) {
+        const int p = L.g.p, ne = L.g.ne[a];
+        const int e = (int)std::min<int64_t>(gc[a] / p, ne - 1);
+        X[(size_t)t * dim + a] = ((double)e + (re.xi[gc[a] - (int64_t)e * p] + 1.0) * 0.5) / (double)ne;
+      }
+    }
+    P->map_fn(X.data(), N, dim, x.data(), P->map_ctx);
+    GLLMG_HIP(hipMemcpyAsync(xn, x.data(), sizeof(double) * x.size(), hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+  } else {
+    launch_node_coords(L.g, L.xi64, P->map, xn, s);
+  }
+  if (P->mu_fn) {
+    if (x.empty()) {
+      x.resize((size_t)N * dim);
+      GLLMG_HIP(hipMemcpyAsync(x.data(), xn, sizeof(double) * x.size(), hipMemcpyDeviceToHost, s));
+      GLLMG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<double> m((size_t)N);
+    P->mu_fn(x.data(), N, dim, m.data(), P->mu_ctx);
+    GLLMG_HIP(hipMemcpyAsync(mun, m.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+    GLLMG_HIP(hipStreamSynchronize(s));  // the host values go out of scope
+  } else if (P->map_fn) {
+    launch_field_at(L.g, xn, P->mu, mun, s);
+  } else {
+    launch_eval_field(L.g, L.xi64, P->map, P->mu, mun, s);
+  }
+}
+
 void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu, hipStream_t s) {
   const gllmg_config& c = P->cfg;
   const bool f32 = c.vcycle_prec == GLLMG_F32;
   P->map = to_dev(map, P->map_modes, s, true);
   P->mu = to_dev(mu, P->mu_modes, s, false);
+  P->map_fn = map->kind == GLLMG_MAP_CALLBACK ? map->fn : nullptr;
+  P->map_ctx = map->ctx;
+  P->mu_fn = mu->kind == GLLMG_FIELD_CALLBACK ? mu->fn : nullptr;
+  P->mu_ctx = mu->ctx;
   GLLMG_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
   GLLMG_HIP(hipMemsetAsync(P->zeros, 0, 64, s));
   P->re.clear();
@@ -485,7 +542,10 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
   for (size_t l = 0; l < P->L.size(); ++l) {
     Level& L = P->L[l];
     double* wdet = l == 0 ? (double*)P->scratch : nullptr;
-    launch_geometry(L, P->map, P->mu, L.G64, f32 ? L.G32 : nullptr, wdet, P->flag, s);
+    double* nodal = (double*)P->scratch + P->L[0].npts;
+    nodal_fields(P, (int)l, nodal, s);
+    launch_geometry(L, nodal, nodal + (size_t)L.g.N * c.dim, L.G64, f32 ? L.G32 : nullptr, wdet,
+                    P->flag, s);
     if (l == 0) launch_gather_full(L, wdet, P->mass, s);
     check_flag(P, s);
     double* diag = (double*)P->scratch;
@@ -1494,6 +1554,8 @@ gllmg_status gllmg_node_coords(const gllmg_problem* P, int32_t level, double* ou
   return guard([&]() {
     const Level& L = level_of(P, level);
     check_ptr(out, 8, "out");
+    GLLMG_CHECK(P->map.kind != GLLMG_MAP_CALLBACK, GLLMG_EUNSUPPORTED,
+                "node coordinates of a callback map are the caller's own Phi");
     launch_node_coords(L.g, L.xi64, P->map, out, (hipStream_t)stream);
     return GLLMG_OK;
   });
@@ -1511,7 +1573,9 @@ gllmg_status gllmg_eval_field(const gllmg_problem* P, int32_t level, const gllmg
     d.kind = f->kind;
     for (int i = 0; i < 12; ++i) d.param[i] = f->param[i];
     GLLMG_CHECK(f->kind >= GLLMG_FIELD_CONST && f->kind <= GLLMG_FIELD_COS2_SUM, GLLMG_EINVAL,
-                "unknown field kind");
+                "unknown field kind (callback fields are evaluated at setup only)");
+    GLLMG_CHECK(P->map.kind != GLLMG_MAP_CALLBACK, GLLMG_EUNSUPPORTED,
+                "fields on a callback map are evaluated by the caller");
     launch_eval_field(L.g, L.xi64, P->map, d, out, (hipStream_t)stream);
     return GLLMG_OK;
   });

@@ -25,8 +25,9 @@ SMOOTHERS = {"jacobi": SMOOTH_JACOBI, "chebyshev": SMOOTH_CHEBYSHEV, "ssor": SMO
              "l1jacobi": SMOOTH_L1_JACOBI, "blockjacobi": SMOOTH_BLOCK_JACOBI}
 MODE_PCG, MODE_MG = 0, 1
 
-KINDS = {"identity": 0, "warp_sine": 1, "affine": 2, "const": 10, "exp_sine_product": 11,
-         "exp_fourier": 12, "sin_product": 13, "cos2_sum": 14}
+KINDS = {"identity": 0, "warp_sine": 1, "affine": 2, "map_callback": 3, "const": 10,
+         "exp_sine_product": 11, "exp_fourier": 12, "sin_product": 13, "cos2_sum": 14,
+         "callback": 20}
 
 STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTCONV",
                 5: "EBREAKDOWN", 6: "EUNSUPPORTED"}
@@ -38,9 +39,13 @@ class GllmgError(RuntimeError):
         self.status = status
 
 
+FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.c_int32,
+                       C.POINTER(C.c_double), C.c_void_p)
+
+
 class Field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("nmodes", C.c_int32), ("param", C.c_double * 12),
-                ("modes", C.POINTER(C.c_double))]
+                ("modes", C.POINTER(C.c_double)), ("fn", FIELD_FN), ("ctx", C.c_void_p)]
 
 
 class Config(C.Structure):
@@ -134,7 +139,24 @@ def make_field(desc: dict):
         keep = np.ascontiguousarray(modes, dtype=np.float64)
         f.nmodes = keep.shape[0]
         f.modes = keep.ctypes.data_as(C.POINTER(C.c_double))
+    if desc["kind"] in ("map_callback", "callback"):
+        keep = _callback(desc["fn"], desc["kind"] == "map_callback")
+        f.fn = keep
     return f, keep
+
+
+def _callback(fn, is_map):
+    """A C callback around fn(points) -> values: points is a (npts, dim) float64 array (reference
+    coordinates for a map, physical ones for a coefficient); fn returns (npts, dim) or (npts,).
+    An exception inside fn leaves NaN values, which setup then rejects."""
+    def cb(pts, npts, dim, out, ctx):
+        o = np.ctypeslib.as_array(out, shape=(npts, dim) if is_map else (npts,))
+        try:
+            X = np.ctypeslib.as_array(pts, shape=(npts, dim)).copy()
+            o[...] = np.asarray(fn(X), dtype=np.float64).reshape(o.shape)
+        except Exception:
+            o[...] = np.nan
+    return FIELD_FN(cb)
 
 
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
@@ -233,8 +255,8 @@ class Problem:
     @classmethod
     def from_inputs(cls, prob, stream=None, **kw):
         cfg = make_config(prob.dim, prob.nelem, prob.order, prob.hierarchy, prob.smoother,
-                          prob.nu, vcycle_prec=prob.vcycle_prec, max_levels=prob.max_levels,
-                          eig_seed=prob.eig_seed, **kw)
+                          prob.nu, nu_post=prob.nu_post, vcycle_prec=prob.vcycle_prec,
+                          max_levels=prob.max_levels, eig_seed=prob.eig_seed, **kw)
         return cls(cfg, prob.map, prob.mu, stream=stream)
 
     def close(self):

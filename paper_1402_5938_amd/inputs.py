@@ -49,6 +49,18 @@ def map_affine(M, c) -> dict:
     return {"kind": "affine", "param": list(M.ravel()) + list(c.ravel()), "modes": None}
 
 
+def map_callback(fn) -> dict:
+    """A map given as a function of reference points: fn(X) with X of shape (npts, d) returns the
+    physical points (npts, d)."""
+    return {"kind": "map_callback", "fn": fn}
+
+
+def field_callback(fn) -> dict:
+    """A coefficient given as a function of physical points: fn(x) with x of shape (npts, d)
+    returns (npts,) values."""
+    return {"kind": "callback", "fn": fn}
+
+
 def mu_exp_sine_product(amp: float, phase=(0.0, 0.0, 0.0)) -> dict:
     ph = list(phase) + [0.0] * (3 - len(phase))
     return {"kind": "exp_sine_product", "param": [float(amp)] + [float(v) for v in ph],

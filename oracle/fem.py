@@ -8,7 +8,10 @@ Discretization (paper §2.1 and §2.3):
 * geometry is isoparametric: on every element the map is replaced by its degree-p interpolant
   through the mapped nodes, and the Jacobian J = dx/dxi is evaluated at every quadrature point;
 * quadrature is the collocated (p+1)^d-point GLL rule (nodes = quadrature points), so the
-  mass matrix is diagonal;
+  mass matrix is diagonal, or (quadrature="gauss", the paper's rule, §2.3) the (p+1)^d-point
+  Gauss-Legendre rule, at whose points the basis is interpolated (I~_qi = l_i(eta_q)) and
+  differentiated (D~ = I~ D, exact since l_i' has degree p); the geometry, mu and the weights
+  are taken at the Gauss points and the mass matrix is the consistent one;
 * the stiffness is (A)_ij = a(phi_i, phi_j) = int mu grad phi_i . grad phi_j, which under
   the quadrature is  A = sum_e sum_q B_q^T G_q B_q  with B_q the reference gradient of the
   element basis at q and G_q = w_q mu(x_q) detJ_q J^{-1} J^{-T};
@@ -24,7 +27,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .fields import eval_map, eval_scalar
-from .gll import deriv_matrix, gll
+from .gll import deriv_matrix, gll, lagrange_eval
 
 
 def lex(shape):
@@ -38,7 +41,10 @@ def lex(shape):
 class Mesh:
     """A structured conforming mesh of order p and its geometry at the GLL points."""
 
-    def __init__(self, dim, nelem, p, map_desc, mu_desc):
+    def __init__(self, dim, nelem, p, map_desc, mu_desc, quadrature="gll"):
+        if quadrature not in ("gll", "gauss"):
+            raise ValueError("quadrature must be 'gll' or 'gauss'")
+        self.quadrature = quadrature
         self.dim = int(dim)
         self.nelem = tuple(int(v) for v in nelem)
         assert len(self.nelem) == self.dim
@@ -52,6 +58,14 @@ class Mesh:
         self.nloc = self.n ** self.dim
         self.xi, self.w = gll(self.p)
         self.D = deriv_matrix(self.xi)
+        if quadrature == "gauss":
+            self.eta, self.wg = np.polynomial.legendre.leggauss(self.n)
+            self.Iq = lagrange_eval(self.xi, self.eta)      # (q, n): l_i(eta_q)
+            self.Dq = self.Iq @ self.D                      # (q, n): l_i'(eta_q)
+        else:
+            self.eta, self.wg = self.xi, self.w
+            self.Iq = np.eye(self.n)
+            self.Dq = self.D
 
         # reference coordinate of every global 1D grid index, per axis
         self.X1 = []
@@ -81,61 +95,113 @@ class Mesh:
         self.elem_coords = Ee
 
     # ------------------------------------------------------------------ geometry
+    def _contract(self, arr, mats):
+        """Apply the 1D matrix mats[b] along reference direction b of arr (m, n_z, n_y, n_x,
+        ...) for every b (array axis d - b holds direction b)."""
+        d = self.dim
+        for b in range(d):
+            ax = d - b
+            moved = np.moveaxis(arr, ax, 0)
+            arr = np.moveaxis(np.tensordot(mats[b], moved, axes=([1], [0])), 0, ax)
+        return arr
+
     def geometry(self, elems=None):
-        """Per element and GLL point: G = w mu detJ J^{-1} J^{-T} (m, nloc, d, d), the
-        quadrature weight times detJ (m, nloc), mu (m, nloc) and detJ (m, nloc)."""
+        """Per element and quadrature point: G = w mu detJ J^{-1} J^{-T} (m, nq, d, d), the
+        quadrature weight times detJ (m, nq), mu (m, nq) and detJ (m, nq). The points are the GLL
+        nodes (collocation) or the Gauss points, where the isoparametric interpolant of the
+        mapped nodes gives both x_q and J."""
         if elems is None:
             elems = np.arange(self.E)
         d, n = self.dim, self.n
         m = len(elems)
+        nq = len(self.eta)
         xe = self.x[self.conn[elems]].reshape((m,) + (n,) * d + (d,))
-        J = np.empty((m,) + (n,) * d + (d, d))
+        J = np.empty((m,) + (nq,) * d + (d, d))
         for b in range(d):
-            ax = d - b                                   # array axis of reference direction b
-            moved = np.moveaxis(xe, ax, 0)
-            der = np.tensordot(self.D, moved, axes=([1], [0]))
-            J[..., :, b] = np.moveaxis(der, 0, ax)
+            mats = [self.Dq if c == b else self.Iq for c in range(d)]
+            J[..., :, b] = self._contract(xe, mats)
+        xq = self._contract(xe, [self.Iq] * d)
         detJ = np.linalg.det(J)
         if not np.all(detJ > 0):
             raise ValueError("detJ <= 0: the map is not a diffeomorphism on this mesh")
         Jinv = np.linalg.inv(J)
-        wq = self.w
+        wq = self.wg
         for _ in range(d - 1):
-            wq = np.multiply.outer(self.w, wq)          # (n,)*d, last axis = x
-        mu = eval_scalar(self.mu_desc, xe.reshape(-1, d)).reshape((m,) + (n,) * d)
+            wq = np.multiply.outer(self.wg, wq)         # (nq,)*d, last axis = x
+        mu = eval_scalar(self.mu_desc, xq.reshape(-1, d)).reshape((m,) + (nq,) * d)
         if not np.all(np.isfinite(mu)) or not np.all(mu > 0):
             raise ValueError("mu must be finite and positive")
         scale = wq[None] * mu * detJ
         G = scale[..., None, None] * np.einsum("...ac,...bc->...ab", Jinv, Jinv)
-        return (G.reshape(m, self.nloc, d, d), (wq[None] * detJ).reshape(m, self.nloc),
-                mu.reshape(m, self.nloc), detJ.reshape(m, self.nloc))
+        npts = nq ** d
+        return (G.reshape(m, npts, d, d), (wq[None] * detJ).reshape(m, npts),
+                mu.reshape(m, npts), detJ.reshape(m, npts))
 
     # ------------------------------------------------------------------ operators
     def grad_matrices(self, elems=None):
         """Global reference-gradient matrices B_a, a < d: row (e, q) of B_a maps the global
-        node vector to d u_e / d xi_a at the GLL point q of element e, i.e.
-        sum_l D[q_a, l] u(local node q with coordinate a replaced by l)."""
+        node vector to d u_e / d xi_a at quadrature point q of element e. Collocated GLL:
+        sum_l D[q_a, l] u(local node q with coordinate a replaced by l); Gauss: the tensor
+        product of D~ along a and I~ along the other axes (a dense row per element)."""
         if elems is None:
             elems = np.arange(self.E)
         d, n, nloc = self.dim, self.n, self.nloc
         m = len(elems)
-        rows = np.repeat(np.arange(m * nloc), n)
         conn = self.conn[elems]
         mats = []
+        if self.quadrature == "gll":
+            rows = np.repeat(np.arange(m * nloc), n)
+            for a in range(d):
+                qa = self.local[a]
+                base = np.arange(nloc) - qa * n ** a
+                loc = base[:, None] + np.arange(n)[None, :] * n ** a        # (nloc, n)
+                cols = conn[:, loc]                                          # (m, nloc, n)
+                vals = np.broadcast_to(self.D[qa], (m, nloc, n))
+                B = sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(m * nloc, self.N))
+                mats.append(B)
+            return mats
+        nq = len(self.eta) ** d
         for a in range(d):
-            qa = self.local[a]
-            base = np.arange(nloc) - qa * n ** a
-            loc = base[:, None] + np.arange(n)[None, :] * n ** a        # (nloc, n)
-            cols = conn[:, loc]                                          # (m, nloc, n)
-            vals = np.broadcast_to(self.D[qa], (m, nloc, n))
-            B = sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(m * nloc, self.N))
+            K = np.ones((1, 1))
+            for c in range(d):                  # local index x fastest: kron(M_z, M_y, M_x)
+                K = np.kron(self.Dq if c == a else self.Iq, K)
+            rows = np.repeat(np.arange(m * nq), nloc)
+            cols = np.tile(conn[:, None, :], (1, nq, 1))
+            vals = np.broadcast_to(K, (m, nq, nloc))
+            B = sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(m * nq, self.N))
             mats.append(B)
         return mats
 
+    def interp_matrix(self, elems=None):
+        """Rows (e, q): the global node vector interpolated to quadrature point q of e."""
+        if elems is None:
+            elems = np.arange(self.E)
+        d, nloc = self.dim, self.nloc
+        m = len(elems)
+        nq = len(self.eta) ** d
+        K = np.ones((1, 1))
+        for c in range(d):
+            K = np.kron(self.Iq, K)
+        rows = np.repeat(np.arange(m * nq), nloc)
+        cols = np.tile(self.conn[elems][:, None, :], (1, nq, 1))
+        vals = np.broadcast_to(K, (m, nq, nloc))
+        return sp.csr_matrix((vals.ravel(), (rows, cols.ravel())), shape=(m * nq, self.N))
+
     def lumped_mass(self):
         """M_L = diag of the GLL-quadrature mass matrix: sum over elements of w_q detJ_q."""
+        if self.quadrature != "gll":
+            raise ValueError("the mass matrix is diagonal only under GLL quadrature")
         _, wdet, _, _ = self.geometry()
         return np.bincount(self.conn.ravel(), weights=wdet.ravel(), minlength=self.N)
+
+    def mass_matrix(self):
+        """The mass matrix (phi_i, phi_j) under the mesh's quadrature: I^T diag(w detJ) I
+        (diagonal, the lumped mass, under GLL collocation)."""
+        _, wdet, _, _ = self.geometry()
+        Iq = self.interp_matrix() if self.quadrature == "gauss" else None
+        if Iq is None:
+            return sp.diags(self.lumped_mass()).tocsr()
+        return (Iq.T @ sp.diags(wdet.ravel()) @ Iq).tocsr()
 
 
 class Stiffness:
@@ -230,8 +296,14 @@ class LevelOperator:
 
 
 def load_vector(mesh: Mesh, f_nodal):
-    """b_j = (f, phi_j) under GLL quadrature = (lumped mass) * f at the node, 0 on the boundary."""
-    b = mesh.lumped_mass() * np.asarray(f_nodal, dtype=np.float64)
+    """b_j = (f_h, phi_j) under the mesh's quadrature for the nodal interpolant f_h of f: under
+    GLL quadrature (lumped mass) * f at the node; under Gauss quadrature M f with the consistent
+    mass. 0 on the boundary."""
+    f = np.asarray(f_nodal, dtype=np.float64)
+    if mesh.quadrature == "gll":
+        b = mesh.lumped_mass() * f
+    else:
+        b = mesh.mass_matrix() @ f
     b[mesh.boundary] = 0.0
     return b
 

@@ -145,7 +145,7 @@ class Hierarchy:
     def __init__(self, dim, nelem, p, map_desc, mu_desc, hierarchy="p", max_levels=0,
                  smoother="chebyshev", nu=4, omega=None, cheb_lo=0.25, cheb_safety=1.0,
                  eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False,
-                 nu_post=None):
+                 nu_post=None, quadrature="gll"):
         if smoother not in ("jacobi", "chebyshev", "ssor", "l1jacobi", "blockjacobi"):
             raise ValueError(f"unknown smoother {smoother!r}")
         if omega is None:
@@ -156,8 +156,11 @@ class Hierarchy:
         self.cheb_lo, self.cheb_safety = cheb_lo, cheb_safety
         self.plan = plan_levels(dim, nelem, p, hierarchy, max_levels)
         self.levels: List[Level] = []
+        if quadrature != "gll" and smoother in ("ssor", "l1jacobi", "blockjacobi"):
+            raise ValueError("the Gauss-Seidel, l1 and block smoothers are built for GLL collocation")
+        self.quadrature = quadrature
         for (ne, q) in self.plan:
-            mesh = Mesh(dim, ne, q, map_desc, mu_desc)
+            mesh = Mesh(dim, ne, q, map_desc, mu_desc, quadrature)
             op = LevelOperator(mesh)
             dg = op.diag()
             dinv = np.zeros_like(dg)
@@ -299,7 +302,7 @@ def build_problem(prob, **kw):
     H = Hierarchy(prob.dim, prob.nelem, prob.order, prob.map, prob.mu,
                   hierarchy=prob.hierarchy, max_levels=prob.max_levels,
                   smoother=prob.smoother, nu=prob.nu, nu_post=prob.nu_post,
-                  eig_seed=prob.eig_seed, **kw)
+                  eig_seed=prob.eig_seed, quadrature=prob.quadrature, **kw)
     fn = prob.nodal_rhs()
     if fn is None:
         fn = nodal_field(H.fine.mesh, prob.f)

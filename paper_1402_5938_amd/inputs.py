@@ -95,6 +95,7 @@ class Problem:
     smoother: str = "chebyshev"         # "chebyshev", "jacobi", "ssor", "l1jacobi", "blockjacobi"
     nu: int = 4                         # Chebyshev degree / sweeps / SSOR steps, pre-smoothing
     nu_post: Optional[int] = None       # post-smoothing count (None: the same as nu)
+    quadrature: str = "gll"             # "gll" (collocated) or "gauss" (p+1 Gauss points)
     mode: str = "pcg"                   # "pcg" or "mg"
     vcycle_prec: str = "f64"            # "f64" or "f32"
     rtol: float = 1e-10

@@ -70,6 +70,12 @@ enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1 };
 enum { GLLMG_SMOOTH_JACOBI = 0, GLLMG_SMOOTH_CHEBYSHEV = 1, GLLMG_SMOOTH_SSOR = 2,
        GLLMG_SMOOTH_L1_JACOBI = 3, GLLMG_SMOOTH_BLOCK_JACOBI = 4 };
 enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1 };
+/* Quadrature (§2.3): GLL collocation (the nodes are the (p+1)^d quadrature points: diagonal mass,
+ * the stiffness couples a node with the coordinate planes through it) or the paper's Gauss rule
+ * with p+1 Gauss-Legendre points per axis (geometry and mu at the Gauss points, dense element
+ * matrices, consistent mass in gllmg_rhs). The Gauss rule takes the Jacobi and Chebyshev
+ * smoothers (the SSOR coloring and the l1/block entries are built for collocation). */
+enum { GLLMG_QUAD_GLL = 0, GLLMG_QUAD_GAUSS = 1 };
 
 /* Field families, evaluated on the device at every level's nodes (physical coordinates
  * x = Phi(X) for coefficients and right-hand sides, reference coordinates X for maps).
@@ -128,6 +134,7 @@ typedef struct {
   int32_t eig_steps;      /* Lanczos/Arnoldi steps for lambda_max (paper: 10)             */
   int32_t vcycle_prec;    /* GLLMG_F64, or GLLMG_F32 for the mixed-precision V-cycle        */
   uint64_t eig_seed;      /* seed of the SplitMix64 start vector                           */
+  int32_t quadrature;     /* GLLMG_QUAD_GLL (default) or GLLMG_QUAD_GAUSS                  */
 } gllmg_config;
 
 typedef struct gllmg_problem gllmg_problem;
@@ -198,8 +205,9 @@ gllmg_status gllmg_node_coords(const gllmg_problem* prob, int32_t level, double*
 gllmg_status gllmg_eval_field(const gllmg_problem* prob, int32_t level, const gllmg_field* f,
                               double* out, void* stream);
 
-/* Load vector on the finest level: b_j = (f, phi_j) under GLL quadrature = (lumped mass)_j
- * f_j for interior nodes, 0 on the boundary (§2.1). f_nodal, b: FP64. Asynchronous. */
+/* Load vector on the finest level: b_j = (f_h, phi_j) for the nodal interpolant f_h of f (§2.1):
+ * under GLL quadrature (lumped mass)_j f_j, under Gauss quadrature the consistent mass times f;
+ * 0 on the boundary. f_nodal (every node, boundary included), b: FP64. Asynchronous. */
 gllmg_status gllmg_rhs(const gllmg_problem* prob, const double* f_nodal, double* b, void* stream);
 
 /* diag(A_level) at interior nodes, 0 on the boundary (§3.2.1). Asynchronous. */

@@ -303,7 +303,9 @@ def load_vector(mesh: Mesh, f_nodal):
     if mesh.quadrature == "gll":
         b = mesh.lumped_mass() * f
     else:
-        b = mesh.mass_matrix() @ f
+        _, wdet, _, _ = mesh.geometry()
+        Iq = mesh.interp_matrix()
+        b = Iq.T @ (wdet.ravel() * (Iq @ f))
     b[mesh.boundary] = 0.0
     return b
 

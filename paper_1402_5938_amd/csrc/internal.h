@@ -61,6 +61,7 @@ struct Xfer {
 
 struct Level {
   Grid g;
+  bool gauss = false;     // Gauss quadrature (else collocated GLL)
   int n;                  // p + 1
   int64_t nint;           // interior nodes
   int64_t npts;           // E * n^d quadrature points
@@ -71,6 +72,11 @@ struct Level {
   float* D32 = nullptr;
   double* xi64 = nullptr; // GLL nodes and weights of the level's order
   double* w64 = nullptr;
+  double* Iq64 = nullptr; // Gauss quadrature: basis and derivative at the Gauss points (n x n)
+  float* Iq32 = nullptr;
+  double* Dq64 = nullptr;
+  float* Dq32 = nullptr;
+  double* wg64 = nullptr; // Gauss weights
   double* dinv64 = nullptr;
   float* dinv32 = nullptr;
   double* l1inv64 = nullptr;  // l1-Jacobi smoother: 1 / sum_j |A_ij| (interior), else unused
@@ -117,8 +123,13 @@ struct RefElem {
   int p;
   std::vector<double> xi, w, D;   // D[i*(p+1)+l] = l_l'(xi_i)
   std::vector<double> lam;        // barycentric weights of the nodes xi
+  // Gauss-Legendre rule with p+1 points: eta, wg; the basis at the points Iq[q*(p+1)+i] =
+  // l_i(eta_q) and its derivative Dq = Iq D (l_i' has degree p, so it equals its interpolant)
+  std::vector<double> eta, wg, Iq, Dq;
 };
 RefElem ref_element(int p);
+// fills eta, wg, Iq, Dq of re (after ref_element)
+void gauss_rule(RefElem& re);
 // Lagrange basis of the order-p GLL nodes evaluated at point y: out[j] = l_j(y).
 void lagrange_at(const RefElem& re, double y, double* out);
 // Largest eigenvalue of the symmetric tridiagonal matrix (diag a[0..m-1], offdiag b[0..m-2]).
@@ -246,6 +257,23 @@ void* static_scratch(int dev);
 
 // Node-order sum of element vectors R (layout [e][k][j][i] on level L) followed by the epilogue.
 void launch_gather_epi(const Level& L, int prec, const void* R, const Epi& ep, hipStream_t s);
+// ... with the product's input xin (read by the in-place epilogues) and the boundary rule
+void launch_gather_in(const Level& L, int prec, const void* R, const void* xin, int neumann,
+                      const Epi& ep, hipStream_t s);
+
+// Gauss quadrature (k_gauss.hip): the product (element pass + gather), the physical Gauss points
+// (E n^d x dim), a field at given points, the geometric factors and w~ detJ, the diagonal and
+// the consistent mass on element vectors (FP64)
+void launch_apply_gauss(const Level& L, int prec, int neumann, const void* x, const Epi& ep,
+                        void* F, hipStream_t s);
+void launch_gauss_points(const Level& L, const double* xn, double* xq, hipStream_t s);
+void launch_field_pts(int64_t npts, int dim, const double* pts, const FieldDev& f, double* out,
+                      hipStream_t s);
+void launch_geometry_gauss(const Level& L, const double* xn, const double* muq, double* G64,
+                           float* G32, double* wdetq, int* flag, hipStream_t s);
+void launch_diag_gauss(const Level& L, double* diag, double* F, hipStream_t s);
+void launch_mass_gauss(const Level& L, const double* f, const double* wdetq, double* F,
+                       hipStream_t s);
 
 // xf = P xc (or xf += P xc)
 void launch_prolong(const Level& fine, const Level& coarse, int prec, const void* xc, void* xf,

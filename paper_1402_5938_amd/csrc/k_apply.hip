@@ -272,6 +272,7 @@ void apply_box_n(const Level& L, int neumann, const void* x, const Epi& epi, hip
 
 template <typename T>
 void apply_t(const Level& L, int neumann, const void* x, const Epi& ep, void* F, hipStream_t s) {
+  if (L.gauss) return launch_apply_gauss(L, sizeof(T) == 8 ? 0 : 1, neumann, x, ep, F, s);
   // order 1: the one-kernel product where launch latency dominates (small levels); on large
   // 3D levels the element kernel and gather, whose F round trip costs less than the one-kernel
   // form's 8 lanes per node. Measured crossover (3D): between 4913 and 35,937 nodes in FP64,
@@ -318,7 +319,16 @@ void launch_gather_epi(const Level& L, int prec, const void* R, const Epi& ep, h
     launch_gather_rt<float>((const float*)R, nullptr, L.g, 0, typed<float>(ep), s);
 }
 
+void launch_gather_in(const Level& L, int prec, const void* R, const void* xin, int neumann,
+                      const Epi& ep, hipStream_t s) {
+  if (prec == 0)
+    launch_gather_rt<double>((const double*)R, (const double*)xin, L.g, neumann, typed<double>(ep), s);
+  else
+    launch_gather_rt<float>((const float*)R, (const float*)xin, L.g, neumann, typed<float>(ep), s);
+}
+
 void launch_diag(const Level& L, double* diag, double* F, hipStream_t s) {
+  if (L.gauss) return launch_diag_gauss(L, diag, F, s);
   const int64_t tot = L.npts;
   hipLaunchKernelGGL(k_diag, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, L.G64, L.D64,
                      L.g, F);

@@ -39,6 +39,12 @@ void validate(const gllmg_config& c) {
                   c.smoother == GLLMG_SMOOTH_SSOR || c.smoother == GLLMG_SMOOTH_L1_JACOBI ||
                   c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI,
               GLLMG_EINVAL, "unknown smoother");
+  GLLMG_CHECK(c.quadrature == GLLMG_QUAD_GLL || c.quadrature == GLLMG_QUAD_GAUSS, GLLMG_EINVAL,
+              "quadrature must be GLLMG_QUAD_GLL or GLLMG_QUAD_GAUSS");
+  GLLMG_CHECK(c.quadrature == GLLMG_QUAD_GLL || c.smoother == GLLMG_SMOOTH_JACOBI ||
+                  c.smoother == GLLMG_SMOOTH_CHEBYSHEV,
+              GLLMG_EUNSUPPORTED,
+              "the Gauss-quadrature operator takes the Jacobi and Chebyshev smoothers");
   if (c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
     int P = 1;
     for (int a = 0; a < c.dim; ++a) P *= c.order;
@@ -126,6 +132,7 @@ struct gllmg_problem {
   size_t ws_bytes = 0;
   bool owns_ws = false;
   double* mass = nullptr;
+  double* wdetq = nullptr;  // Gauss quadrature: w~ detJ at the finest level's Gauss points
   void* F = nullptr;
   void* zeros = nullptr;
   double* scal = nullptr;
@@ -197,6 +204,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   for (size_t l = 0; l < specs.size(); ++l) {
     Level& L = P->L[l];
     L.g = make_grid(c.dim, specs[l]);
+    L.gauss = c.quadrature == GLLMG_QUAD_GAUSS;
     L.n = specs[l].p + 1;
     L.nint = interior_count(c.dim, L.g.ne, L.g.p);
     L.ncomp = c.dim == 3 ? 6 : 3;
@@ -207,6 +215,13 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
     L.D32 = (float*)A.take(sizeof(float) * n * n);
     L.xi64 = (double*)A.take(sizeof(double) * n);
     L.w64 = (double*)A.take(sizeof(double) * n);
+    if (L.gauss) {
+      L.Iq64 = (double*)A.take(sizeof(double) * n * n);
+      L.Iq32 = (float*)A.take(sizeof(float) * n * n);
+      L.Dq64 = (double*)A.take(sizeof(double) * n * n);
+      L.Dq32 = (float*)A.take(sizeof(float) * n * n);
+      L.wg64 = (double*)A.take(sizeof(double) * n);
+    }
     L.G64 = (double*)A.take(sizeof(double) * L.npts * L.ncomp);
     L.G32 = f32 ? (float*)A.take(sizeof(float) * L.npts * L.ncomp) : nullptr;
     L.ctab = (double*)A.take(sizeof(double) * 2 * ctab_pairs(c));
@@ -240,6 +255,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   }
   const int64_t N0 = P->L[0].g.N;
   P->mass = (double*)A.take(sizeof(double) * N0);
+  if (c.quadrature == GLLMG_QUAD_GAUSS) P->wdetq = (double*)A.take(sizeof(double) * P->L[0].npts);
   P->F = A.take(sizeof(double) * std::max<size_t>(face, 1));
   P->bdev = (BatchProblem*)A.take(sizeof(BatchProblem));
   P->zeros = A.take(64);
@@ -280,7 +296,7 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   const size_t setup = sizeof(double) * (size_t)std::max<int64_t>(
                                             (int64_t)c.eig_steps * maxN + 4 * maxN +
                                                 (int64_t)(c.eig_steps + 1) * (3 + kMdBlocks),
-                                            P->L[0].npts + 4 * maxN) + 4096;
+                                            5 * P->L[0].npts + 4 * maxN) + 4096;
   if (setup > steady) A.take(setup - steady);
   P->scratch_bytes = A.used - before;
   return A.used + 256;
@@ -474,7 +490,7 @@ void check_flag(gllmg_problem* P, hipStream_t s) {
 // the built-in families by the same kernels as gllmg_node_coords and gllmg_eval_field; callback
 // kinds by the caller's functions, called once with every node of the level in node order
 // (Phi at the reference coordinates, mu at the physical ones) and copied to the device.
-void nodal_fields(gllmg_problem* P, int l, double* nodal, hipStream_t s) {
+void nodal_fields(gllmg_problem* P, int l, double* nodal, hipStream_t s, bool need_mu = true) {
   const Level& L = P->L[l];
   const int dim = L.g.dim;
   const int64_t N = L.g.N;
@@ -500,6 +516,7 @@ void nodal_fields(gllmg_problem* P, int l, double* nodal, hipStream_t s) {
   } else {
     launch_node_coords(L.g, L.xi64, P->map, xn, s);
   }
+  if (!need_mu) return;
   if (P->mu_fn) {
     if (x.empty()) {
       x.resize((size_t)N * dim);
@@ -531,7 +548,17 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
   P->re.clear();
   for (auto& L : P->L) {
     P->re.push_back(ref_element(L.g.p));
-    const RefElem& r = P->re.back();
+    RefElem& r = P->re.back();
+    if (L.gauss) {
+      gauss_rule(r);
+      std::vector<float> I32(r.Iq.begin(), r.Iq.end()), Dq32(r.Dq.begin(), r.Dq.end());
+      GLLMG_HIP(hipMemcpyAsync(L.Iq64, r.Iq.data(), sizeof(double) * r.Iq.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(L.Iq32, I32.data(), sizeof(float) * I32.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(L.Dq64, r.Dq.data(), sizeof(double) * r.Dq.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(L.Dq32, Dq32.data(), sizeof(float) * Dq32.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipMemcpyAsync(L.wg64, r.wg.data(), sizeof(double) * r.wg.size(), hipMemcpyHostToDevice, s));
+      GLLMG_HIP(hipStreamSynchronize(s));
+    }
     std::vector<float> D32(r.D.begin(), r.D.end());
     GLLMG_HIP(hipMemcpyAsync(L.D64, r.D.data(), sizeof(double) * r.D.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice, s));
@@ -543,10 +570,31 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
     Level& L = P->L[l];
     double* wdet = l == 0 ? (double*)P->scratch : nullptr;
     double* nodal = (double*)P->scratch + P->L[0].npts;
-    nodal_fields(P, (int)l, nodal, s);
-    launch_geometry(L, nodal, nodal + (size_t)L.g.N * c.dim, L.G64, f32 ? L.G32 : nullptr, wdet,
-                    P->flag, s);
-    if (l == 0) launch_gather_full(L, wdet, P->mass, s);
+    if (L.gauss) {
+      // the physical Gauss points (isoparametric interpolant of the mapped nodes), mu there
+      // (built-in family on the device, or the caller's callback), then the factors
+      nodal_fields(P, (int)l, nodal, s, false);
+      double* xq = nodal + 4 * (size_t)L.g.N;
+      double* muq = xq + (size_t)L.npts * c.dim;
+      launch_gauss_points(L, nodal, xq, s);
+      if (P->mu_fn) {
+        std::vector<double> xh((size_t)L.npts * c.dim), mh((size_t)L.npts);
+        GLLMG_HIP(hipMemcpyAsync(xh.data(), xq, sizeof(double) * xh.size(), hipMemcpyDeviceToHost, s));
+        GLLMG_HIP(hipStreamSynchronize(s));
+        P->mu_fn(xh.data(), L.npts, c.dim, mh.data(), P->mu_ctx);
+        GLLMG_HIP(hipMemcpyAsync(muq, mh.data(), sizeof(double) * mh.size(), hipMemcpyHostToDevice, s));
+        GLLMG_HIP(hipStreamSynchronize(s));
+      } else {
+        launch_field_pts(L.npts, c.dim, xq, P->mu, muq, s);
+      }
+      launch_geometry_gauss(L, nodal, muq, L.G64, f32 ? L.G32 : nullptr, l == 0 ? P->wdetq : nullptr,
+                            P->flag, s);
+    } else {
+      nodal_fields(P, (int)l, nodal, s);
+      launch_geometry(L, nodal, nodal + (size_t)L.g.N * c.dim, L.G64, f32 ? L.G32 : nullptr, wdet,
+                      P->flag, s);
+      if (l == 0) launch_gather_full(L, wdet, P->mass, s);
+    }
     check_flag(P, s);
     double* diag = (double*)P->scratch;
     launch_diag(L, diag, (double*)P->F, s);
@@ -1067,6 +1115,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
 // n0 or at 2), and maxit below the history capacity.
 bool batch_eligible(const gllmg_problem* P, int maxit) {
   if (!P->persistent || P->cfg.dim != 3 || P->vprec != 1) return false;
+  if (P->cfg.quadrature != GLLMG_QUAD_GLL) return false;
   if (P->cfg.smoother != GLLMG_SMOOTH_JACOBI && P->cfg.smoother != GLLMG_SMOOTH_CHEBYSHEV) return false;
   if (P->L.size() > (size_t)kBatchMaxLevels || !P->L.back().Ainv64) return false;
   if (maxit >= kBatchHist || P->L[0].g.N > kBatchMaxNodes) return false;
@@ -1408,6 +1457,7 @@ void gllmg_config_default(gllmg_config* c) {
   c->eig_steps = 10;
   c->vcycle_prec = GLLMG_F64;
   c->eig_seed = 0;
+  c->quadrature = GLLMG_QUAD_GLL;
 }
 
 gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* bytes) {
@@ -1586,6 +1636,13 @@ gllmg_status gllmg_rhs(const gllmg_problem* P, const double* f, double* b, void*
     const Level& L = level_of(P, 0);
     check_ptr(f, 8, "f_nodal");
     check_ptr(b, 8, "b");
+    if (L.gauss) {  // consistent mass: element vectors, then the node-order sum (boundary 0)
+      launch_mass_gauss(L, f, P->wdetq, (double*)P->F, (hipStream_t)stream);
+      Epi ep;
+      ep.y = b;
+      launch_gather_in(L, 0, P->F, nullptr, 0, ep, (hipStream_t)stream);
+      return GLLMG_OK;
+    }
     launch_rhs(L.g, P->mass, f, b, (hipStream_t)stream);
     return GLLMG_OK;
   });
@@ -1783,7 +1840,7 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       for (int i = 0; i < count; ++i) {
         gllmg_problem* P = probs[i];
         if (P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
-        if (!groupable_smoother(P->cfg.smoother)) continue;
+        if (!groupable_smoother(P->cfg.smoother) || P->cfg.quadrature != GLLMG_QUAD_GLL) continue;
         if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
         bool placed = false;
         for (auto& sh : shapes)

@@ -131,6 +131,51 @@ RefElem ref_element(int p) {
   return re;
 }
 
+// Gauss-Legendre rule of q = p + 1 points: the zeros of P_q are the eigenvalues of the
+// symmetric tridiagonal Jacobi matrix of the Legendre polynomials (Golub-Welsch), zero diagonal
+// and off-diagonal k / sqrt(4 k^2 - 1), found by Sturm bisection and polished by Newton's method
+// on P_q; weights 2 / ((1 - x^2) P_q'(x)^2) with P_q' = q (x P_q - P_{q-1}) / (x^2 - 1).
+// The basis of the GLL nodes at those points by barycentric evaluation, its derivative as Iq D.
+void gauss_rule(RefElem& re) {
+  const int q = re.p + 1, n = re.p + 1;
+  std::vector<double> a(q, 0.0), b(std::max(q - 1, 0));
+  for (int k = 1; k <= q - 1; ++k) b[k - 1] = (double)k / std::sqrt(4.0 * k * k - 1.0);
+  re.eta.assign(q, 0.0);
+  re.wg.assign(q, 0.0);
+  for (int k = 0; k < q; ++k) {
+    double x = tridiag_eig_k(a, b, k, -1.0, 1.0);
+    for (int it = 0; it < 3; ++it) {
+      double P, Pm1;
+      legendre_pp(q, x, &P, &Pm1);
+      const double dP = q * (x * P - Pm1) / (x * x - 1.0);
+      x -= P / dP;
+    }
+    re.eta[k] = x;
+  }
+  for (int k = 0; k < q / 2; ++k) {  // the rule is symmetric
+    const double s = 0.5 * (re.eta[q - 1 - k] - re.eta[k]);
+    re.eta[k] = -s;
+    re.eta[q - 1 - k] = s;
+  }
+  if (q % 2 == 1) re.eta[q / 2] = 0.0;
+  for (int k = 0; k < q; ++k) {
+    const double x = re.eta[k];
+    double P, Pm1;
+    legendre_pp(q, x, &P, &Pm1);
+    const double dP = q * (x * P - Pm1) / (x * x - 1.0);
+    re.wg[k] = 2.0 / ((1.0 - x * x) * dP * dP);
+  }
+  re.Iq.assign((size_t)q * n, 0.0);
+  for (int k = 0; k < q; ++k) lagrange_at(re, re.eta[k], &re.Iq[(size_t)k * n]);
+  re.Dq.assign((size_t)q * n, 0.0);
+  for (int k = 0; k < q; ++k)
+    for (int j = 0; j < n; ++j) {
+      double v = 0.0;
+      for (int i = 0; i < n; ++i) v += re.Iq[(size_t)k * n + i] * re.D[(size_t)i * n + j];
+      re.Dq[(size_t)k * n + j] = v;
+    }
+}
+
 // Barycentric Lagrange evaluation (Berrut and Trefethen, SIAM Review 2004, "second form").
 void lagrange_at(const RefElem& re, double y, double* out) {
   const int n = re.p + 1;

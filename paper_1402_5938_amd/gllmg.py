@@ -53,7 +53,7 @@ class Config(C.Structure):
                 ("hierarchy", C.c_int32), ("max_levels", C.c_int32), ("smoother", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("cheb_lo", C.c_double), ("cheb_safety", C.c_double), ("eig_steps", C.c_int32),
-                ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64)]
+                ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64), ("quadrature", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -161,7 +161,7 @@ def _callback(fn, is_map):
 
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
                 vcycle_prec="f64", max_levels=0, omega=None, cheb_lo=0.25,
-                cheb_safety=1.0, eig_steps=10, eig_seed=0) -> Config:
+                cheb_safety=1.0, eig_steps=10, eig_seed=0, quadrature="gll") -> Config:
     c = Config()
     lib().gllmg_config_default(C.byref(c))
     c.dim = dim
@@ -181,6 +181,9 @@ def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu
     c.max_levels = max_levels
     c.omega, c.cheb_lo, c.cheb_safety = omega, cheb_lo, cheb_safety
     c.eig_steps, c.eig_seed = eig_steps, eig_seed
+    if quadrature not in ("gll", "gauss"):
+        raise ValueError(f"unknown quadrature {quadrature!r}")
+    c.quadrature = 1 if quadrature == "gauss" else 0
     return c
 
 
@@ -256,7 +259,8 @@ class Problem:
     def from_inputs(cls, prob, stream=None, **kw):
         cfg = make_config(prob.dim, prob.nelem, prob.order, prob.hierarchy, prob.smoother,
                           prob.nu, nu_post=prob.nu_post, vcycle_prec=prob.vcycle_prec,
-                          max_levels=prob.max_levels, eig_seed=prob.eig_seed, **kw)
+                          max_levels=prob.max_levels, eig_seed=prob.eig_seed,
+                          quadrature=prob.quadrature, **kw)
         return cls(cfg, prob.map, prob.mu, stream=stream)
 
     def close(self):

@@ -253,6 +253,49 @@ def workload_smoothers(a):
             "nodes": inputs.node_count(prob.nelem, prob.order), "cases": rows}
 
 
+def apply_flops_gauss(dim, ne, p):
+    """Flops of one Gauss-quadrature product (q = p + 1 points): the five sum-factorized passes
+    take 16 n^4 (3D) or 6 n^3 (2D) multiply-adds per element, the pointwise factors 9 n^3 (4 n^2)."""
+    n = p + 1
+    E = 1
+    for v in ne:
+        E *= v
+    return E * (32 * n ** 4 + 18 * n ** 3) if dim == 3 else E * (12 * n ** 3 + 8 * n ** 2)
+
+
+def workload_gauss(a):
+    """The warped variable-coefficient problem (16^3 hexes at p = 8 and 8^3 at p = 16, f = 1)
+    with the collocated GLL and the Gauss-quadrature operator: FP64 PCG time to 1e-10,
+    iterations, and one fine-level product (median of 50, HIP events) against the HBM
+    roofline (algorithmic bytes: 6 factors per quadrature point, x and y once)."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    rows = []
+    for ne, p in ((16, 8), (8, 16)):
+        prob = inputs.warped_var3d(nelem=ne, order=p)
+        for quad in ("gll", "gauss"):
+            cfg = gllmg.make_config(3, prob.nelem, p, "p", "chebyshev", 4, quadrature=quad)
+            G = gllmg.Problem(cfg, prob.map, prob.mu)
+            b = G.rhs(G.eval_field(prob.f))
+            t, r, _ = _solve_timed(G, b, a.steps, a.warmup, prob.rtol, prob.maxit)
+            N = G.nnodes(0)
+            x = torch.from_numpy(inputs.uniform_nodal(99, N)).cuda()
+            y = torch.empty_like(x)
+            us = _median_apply_us(G, x, y, 50)
+            nb = apply_bytes(3, prob.nelem, p, N, 8)
+            fl = apply_flops_gauss(3, prob.nelem, p) if quad == "gauss" else apply_flops(3, prob.nelem, p)
+            rows.append({"nelem": ne, "order": p, "quadrature": quad, "nodes": N,
+                         "pcg_iterations": r.iters, "time_to_solution_ms": t * 1e3,
+                         "apply_us": us, "achieved_gbs": nb / (us * 1e-6) / 1e9,
+                         "frac_hbm": nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                         "tflops": fl / (us * 1e-6) / 1e12})
+            G.close()
+            torch.cuda.empty_cache()
+    return {"workload": "quadrature: 3D warped var, GLL collocation vs Gauss (p+1 points), FP64 PCG to 1e-10",
+            "cases": rows}
+
+
 SWEEP_CASES = [(3, 256, 1), (3, 128, 2), (3, 64, 4), (3, 40, 6), (3, 32, 8), (3, 20, 12), (3, 16, 16),
                (2, 512, 8)]
 
@@ -357,7 +400,7 @@ def workload_apply(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep",
-                                                          "smoothers"])
+                                                          "smoothers", "gauss"])
     ap.add_argument("--smoothers", default="chebyshev,jacobi,ssor")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
@@ -384,7 +427,7 @@ def main():
     if a.workload != "config2":
         fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
               "apply": workload_apply, "sweep": workload_sweep,
-              "smoothers": workload_smoothers}[a.workload]
+              "smoothers": workload_smoothers, "gauss": workload_gauss}[a.workload]
         print(json.dumps(fn(a)))
         return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)

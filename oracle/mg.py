@@ -40,7 +40,8 @@ from .transfer import Transfer
 
 
 def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0):
-    """List of (nelem, p) from fine to coarse."""
+    """List of (nelem, p) from fine to coarse. hierarchy "low": the order-p level, then the
+    first-order level on the same nodes (n_e p cells of order 1 per axis), then h-coarsening."""
     nelem = tuple(int(v) for v in nelem)
 
     def interior(ne, q):
@@ -52,8 +53,12 @@ def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0):
         while q > 1:
             q = (q + 1) // 2
             levels.append((ne, q))
+    elif hierarchy == "low":
+        if q > 1:
+            ne, q = tuple(v * q for v in ne), 1
+            levels.append((ne, q))
     elif hierarchy != "h":
-        raise ValueError("hierarchy must be 'h' or 'p'")
+        raise ValueError("hierarchy must be 'h', 'p' or 'low'")
     while all(v % 2 == 0 for v in ne) and interior(tuple(v // 2 for v in ne), q) >= 1:
         ne = tuple(v // 2 for v in ne)
         levels.append((ne, q))
@@ -145,7 +150,7 @@ class Hierarchy:
     def __init__(self, dim, nelem, p, map_desc, mu_desc, hierarchy="p", max_levels=0,
                  smoother="chebyshev", nu=4, omega=None, cheb_lo=0.25, cheb_safety=1.0,
                  eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False,
-                 nu_post=None, quadrature="gll"):
+                 nu_post=None, quadrature="gll", low_cycles=1):
         if smoother not in ("jacobi", "chebyshev", "ssor", "l1jacobi", "blockjacobi"):
             raise ValueError(f"unknown smoother {smoother!r}")
         if omega is None:
@@ -159,14 +164,22 @@ class Hierarchy:
         if quadrature != "gll" and smoother in ("ssor", "l1jacobi", "blockjacobi"):
             raise ValueError("the Gauss-Seidel, l1 and block smoothers are built for GLL collocation")
         self.quadrature = quadrature
-        for (ne, q) in self.plan:
-            mesh = Mesh(dim, ne, q, map_desc, mu_desc, quadrature)
+        self.hierarchy, self.low_cycles = hierarchy, int(low_cycles)
+        for li, (ne, q) in enumerate(self.plan):
+            if hierarchy == "low" and li >= 1 and p > 1:
+                # first-order cells whose vertices are the order-p nodes (every 2^(li-1)-th one
+                # on the coarser first-order levels): the geometry comes from those nodes
+                mesh = Mesh(dim, ne, q, _node_lookup(self.levels[0].mesh, ne), mu_desc, quadrature)
+            else:
+                mesh = Mesh(dim, ne, q, map_desc, mu_desc, quadrature)
             op = LevelOperator(mesh)
             dg = op.diag()
             dinv = np.zeros_like(dg)
             dinv[mesh.interior] = 1.0 / dg[mesh.interior]
             self.levels.append(Level(mesh=mesh, op=op, dinv=dinv))
         for li in range(len(self.levels) - 1):
+            if hierarchy == "low" and li == 0:
+                continue            # levels 0 and 1 share their nodes
             self.levels[li].to_coarse = Transfer(self.levels[li].mesh,
                                                  self.levels[li + 1].mesh, direct_transfer)
         for li, lv in enumerate(self.levels[:-1]):
@@ -219,6 +232,30 @@ class Hierarchy:
             x[lv.idx] = sla.cho_solve(lv.chol, b[lv.idx])
         return x
 
+    def precond(self, r):
+        """The preconditioner of the solvers: the V-cycle from the finest level, or (hierarchy
+        "low", §3.1.3) low_cycles sweeps of x <- x + V_1 (r - A_1 x) from x = 0 with the
+        first-order operator A_1 on the order-p nodes and its V-cycle V_1 (level 1 down): an
+        approximation of A_1^{-1} r that tends to it as the sweeps grow. Levels 0 and 1 share
+        their nodes, so r and the result are the same vectors on both."""
+        if self.hierarchy != "low" or len(self.levels) == 1:
+            return self.vcycle(r)
+        op1 = self.levels[1].op
+        x = self.vcycle(r, 1)
+        for _ in range(self.low_cycles - 1):
+            x = x + self.vcycle(r - op1.apply(x), 1)
+        return x
+
+    def low_order_exact(self, r):
+        """A_1^{-1} r by a sparse direct factorization (the paper's experiments, §4.3)."""
+        import scipy.sparse.linalg as spla
+        lv = self.levels[1]
+        A = lv.op.K.csr()
+        idx = np.nonzero(lv.mesh.interior)[0]
+        x = np.zeros_like(r)
+        x[idx] = spla.spsolve(A[idx][:, idx].tocsc(), r[idx])
+        return x
+
     def vcycle(self, r, li=0):
         """e = V r with zero initial guess on level li."""
         if li == len(self.levels) - 1:
@@ -243,6 +280,23 @@ class SolveResult:
     relres_true: float = float("nan")
 
 
+def _node_lookup(fine_mesh, ne):
+    """A map description placing the vertices of a first-order mesh of ne cells per axis on the
+    physical nodes of fine_mesh (every (n_e p / ne)-th node per axis)."""
+    stride = [fm // c for fm, c in zip([v * fine_mesh.p for v in fine_mesh.nelem], ne)]
+    nax, x = fine_mesh.nax, fine_mesh.x
+
+    def fn(X):
+        idx = np.zeros(len(X), dtype=np.int64)
+        mult = 1
+        for a in range(X.shape[1]):
+            g = np.rint(X[:, a] * ne[a]).astype(np.int64) * stride[a]
+            idx += g * mult
+            mult *= nax[a]
+        return x[idx]
+    return {"kind": "map_callback", "fn": fn}
+
+
 def mg_solve(H: Hierarchy, b, x0=None, rtol=1e-10, maxit=1000):
     op = H.fine.op
     x = np.zeros_like(b) if x0 is None else x0.copy()
@@ -252,7 +306,7 @@ def mg_solve(H: Hierarchy, b, x0=None, rtol=1e-10, maxit=1000):
     if n0 == 0.0:
         return SolveResult(x, 0, True, hist, 0.0)
     for it in range(1, maxit + 1):
-        x = x + H.vcycle(r)
+        x = x + H.precond(r)
         r = b - op.apply(x)
         nr = float(np.linalg.norm(r))
         hist.append(nr)
@@ -267,7 +321,7 @@ def pcg(H: Hierarchy, b, x0=None, rtol=1e-10, maxit=500, precond=None):
     """Algorithm 1: h = A p; alpha = (z, r) / (p, h); x += alpha p; r -= alpha h; test;
     z = V r; beta = (z, r)_new / (z, r)_old; p = z + beta p."""
     op = H.fine.op
-    M = H.vcycle if precond is None else precond
+    M = H.precond if precond is None else precond
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - op.apply(x) if x0 is not None else b.copy()
     n0 = float(np.linalg.norm(r))

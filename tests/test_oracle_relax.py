@@ -224,3 +224,71 @@ def test_new_smoothers_solve_to_the_dense_solution(smoother):
         res = solve(H, b, rtol=1e-10)
         assert res.converged
         assert np.abs(res.x[idx] - xs).max() <= 1e-8 * np.abs(xs).max()
+
+
+# ------------------------------------------------------------------ first-order preconditioner
+def test_low_order_level_is_order_one_on_the_high_order_nodes():
+    H = mg.Hierarchy(2, (3, 2), 4, WARP, MU, hierarchy="low")
+    m0, m1 = H.levels[0].mesh, H.levels[1].mesh
+    assert m1.p == 1 and m1.nelem == (12, 8) and m1.N == m0.N
+    assert np.array_equal(m1.x, m0.x)                     # the same physical nodes
+    # at p = 1 the order-p level is already first order: the hierarchy is the h-hierarchy
+    assert mg.plan_levels(3, (4, 4, 2), 1, "low") == mg.plan_levels(3, (4, 4, 2), 1, "h")
+    # coarser first-order levels sit on every other node
+    H2 = mg.Hierarchy(2, (2, 2), 4, WARP, MU, hierarchy="low")
+    m2 = H2.levels[2].mesh
+    sub = H2.levels[0].mesh.x.reshape(9, 9, 2)[::2, ::2].reshape(-1, 2)
+    assert np.array_equal(m2.x, sub)
+
+
+def _equivalence_band(dim, ne, p):
+    H = mg.Hierarchy(dim, ne, p, WARP, MU, hierarchy="low")
+    A0, idx = H.levels[0].op.dense_interior()
+    A1, idx1 = H.levels[1].op.dense_interior()
+    assert np.array_equal(idx, idx1)
+    ev = np.linalg.eigvals(np.linalg.solve(A1, A0))
+    assert np.abs(ev.imag).max() <= 1e-8 * np.abs(ev.real).max()
+    return ev.real.min(), ev.real.max()
+
+
+@pytest.mark.parametrize("dim,p,ne0,ne1", [(2, 4, (2, 2), (4, 4)), (3, 2, (2, 2, 2), (4, 4, 4))])
+def test_low_order_operator_is_spectrally_equivalent(dim, p, ne0, ne1):
+    """A_1^{-1} A_p has real positive eigenvalues in a bounded band (the finite-element /
+    spectral-element equivalence) that refining the mesh leaves nearly unchanged."""
+    lo0, hi0 = _equivalence_band(dim, ne0, p)
+    lo1, hi1 = _equivalence_band(dim, ne1, p)
+    assert 0.3 < lo1 and hi1 < 6.0, (lo1, hi1)
+    assert hi1 / lo1 < 1.3 * hi0 / lo0, ((lo0, hi0), (lo1, hi1))
+
+
+def test_low_order_sweeps_tend_to_the_exact_inverse():
+    H = mg.Hierarchy(2, (4, 4), 4, WARP, MU, hierarchy="low", low_cycles=1)
+    m = H.fine.mesh
+    r = np.random.default_rng(7).standard_normal(m.N) * m.interior
+    exact = H.low_order_exact(r)
+    errs = []
+    for k in (1, 3, 6, 12):
+        H.low_cycles = k
+        errs.append(np.abs(H.precond(r) - exact).max() / np.abs(exact).max())
+    assert errs[-1] < 1e-8 and all(errs[i + 1] < errs[i] for i in range(3))
+    # the preconditioner is symmetric (a polynomial in the symmetric V_1 A_1, times V_1)
+    H.low_cycles = 3
+    idx = np.nonzero(m.interior)[0]
+    M = np.zeros((len(idx), len(idx)))
+    for c, i in enumerate(idx):
+        e = np.zeros(m.N)
+        e[i] = 1.0
+        M[:, c] = H.precond(e)[idx]
+    assert np.abs(M - M.T).max() <= 1e-11 * np.abs(M).max()
+
+
+def test_low_order_pcg_solves():
+    H = mg.Hierarchy(3, (2, 2, 2), 4, WARP, MU, hierarchy="low", low_cycles=2)
+    m = H.fine.mesh
+    b = fem.load_vector(m, np.ones(m.N))
+    A, idx = H.fine.op.dense_interior()
+    xs = np.linalg.solve(A, b[idx])
+    res = mg.pcg(H, b, rtol=1e-10)
+    assert res.converged and np.abs(res.x[idx] - xs).max() <= 1e-8 * np.abs(xs).max()
+    exact = mg.pcg(H, b, rtol=1e-10, precond=H.low_order_exact)
+    assert exact.converged and exact.iters <= res.iters

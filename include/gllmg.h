@@ -53,7 +53,15 @@ typedef enum {
 
 typedef enum { GLLMG_F64 = 0, GLLMG_F32 = 1 } gllmg_prec;
 
-enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1 };
+/* Hierarchies (§3.1): H keeps p and halves the elements per axis; P takes p -> ceil(p/2) down to
+ * 1, then halves the elements; LOW (§3.1.3, the first-order approximation built on the nodes of
+ * the high-order discretization) keeps the order-p level, then a level of first-order cells
+ * whose vertices are exactly the order-p nodes (n_e p cells per axis, same node numbering), then
+ * halves that first-order grid (each coarser level on every other node). With LOW the solvers'
+ * preconditioner is low_cycles sweeps x <- x + V_1 (r - A_1 x) from x = 0 of the first-order
+ * operator A_1 and its V-cycle V_1 (levels 1 and below): an approximation of A_1^{-1} that tends
+ * to it as the sweeps grow (the paper applies A_1^{-1} exactly). GLL quadrature only. */
+enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1, GLLMG_HIER_LOW = 2 };
 /* Smoothers (§3.2, §4.3, §4.4.3):
  *   JACOBI        nu sweeps x += omega D^{-1} (b - A x)                    (paper: omega = 2/3)
  *   CHEBYSHEV     one degree-nu Chebyshev polynomial in D^{-1} A on [cheb_lo lambda, lambda]
@@ -122,8 +130,7 @@ typedef struct {
   int32_t dim;            /* 2 or 3                                                        */
   int32_t nelem[3];       /* elements per axis (>= 1); nelem[2] ignored in 2D              */
   int32_t order;          /* polynomial order p, 1..16                                     */
-  int32_t hierarchy;      /* GLLMG_HIER_H: fixed p, halve elements; GLLMG_HIER_P: p -> ceil(p/2)
-                             down to 1, then halve elements (§3.1.1, §3.1.2, §4.3)           */
+  int32_t hierarchy;      /* GLLMG_HIER_H, GLLMG_HIER_P or GLLMG_HIER_LOW (see above)        */
   int32_t max_levels;     /* 0: as many levels as the rule allows; else keep the finest k  */
   int32_t smoother;       /* GLLMG_SMOOTH_*                                                */
   int32_t nu_pre;         /* sweeps / Chebyshev degree / SSOR steps before the correction   */
@@ -135,6 +142,7 @@ typedef struct {
   int32_t vcycle_prec;    /* GLLMG_F64, or GLLMG_F32 for the mixed-precision V-cycle        */
   uint64_t eig_seed;      /* seed of the SplitMix64 start vector                           */
   int32_t quadrature;     /* GLLMG_QUAD_GLL (default) or GLLMG_QUAD_GAUSS                  */
+  int32_t low_cycles;     /* GLLMG_HIER_LOW: first-order V-cycle sweeps per preconditioning  */
 } gllmg_config;
 
 typedef struct gllmg_problem gllmg_problem;

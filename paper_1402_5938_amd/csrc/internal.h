@@ -142,6 +142,9 @@ bool spd_inverse(std::vector<double>& A, int n);
 // Geometric factors of a level from the physical coordinates xn (N x dim) and mu (N) at its nodes
 void launch_geometry(const Level& L, const double* xn, const double* mun, double* G64,
                      float* G32, double* wdet, int* flag, hipStream_t s);
+// nodal coordinates and mu of a grid whose node (i, j, k) is node stride * (i, j, k) of grid g0
+void launch_subsample_nodal(const Grid& g0, const Grid& g, int stride, const double* xn0,
+                            const double* mu0, double* xn, double* mu, hipStream_t s);
 // a field at given physical node coordinates xn (N x dim)
 void launch_field_at(const Grid& g, const double* xn, const FieldDev& f, double* out, hipStream_t s);
 void launch_gather_full(const Level& L, const double* elem_vals, double* out, hipStream_t s);

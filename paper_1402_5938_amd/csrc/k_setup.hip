@@ -164,6 +164,20 @@ __global__ void k_eval_field(Grid g, const double* __restrict__ xi, FieldDev map
   out[t] = field_eval(f, g.dim, x);
 }
 
+// Nodal coordinates and mu of a coarser grid whose node (i, j, k) is node (s i, s j, s k) of the
+// grid g0.
+__global__ void k_subsample_nodal(Grid g0, Grid g, int stride, const double* __restrict__ xn0,
+                                  const double* __restrict__ mu0, double* __restrict__ xn,
+                                  double* __restrict__ mu) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const int64_t gc[3] = {t % g.nn[0], (t / g.nn[0]) % g.nn[1], t / ((int64_t)g.nn[0] * g.nn[1])};
+  const int64_t src = gc[0] * stride + (int64_t)g0.nn[0] * (gc[1] * stride +
+                                                            (int64_t)g0.nn[1] * gc[2] * stride);
+  for (int a = 0; a < g.dim; ++a) xn[t * g.dim + a] = xn0[src * g.dim + a];
+  mu[t] = mu0[src];
+}
+
 // A field at given physical node coordinates xn (N x dim).
 __global__ void k_field_at(Grid g, const double* __restrict__ xn, FieldDev f, double* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -232,6 +246,13 @@ void launch_geometry(const Level& L, const double* xn, const double* mun, double
   else
     hipLaunchKernelGGL(k_geometry<3>, dim3(nblocks(tot)), dim3(kThreads), 0, s, L.g, L.n, L.w64,
                        L.D64, xn, mun, G64, G32, wdet, flag);
+  GLLMG_HIP(hipGetLastError());
+}
+
+void launch_subsample_nodal(const Grid& g0, const Grid& g, int stride, const double* xn0,
+                            const double* mu0, double* xn, double* mu, hipStream_t s) {
+  hipLaunchKernelGGL(k_subsample_nodal, dim3(nblocks(g.N)), dim3(kThreads), 0, s, g0, g, stride, xn0,
+                     mu0, xn, mu);
   GLLMG_HIP(hipGetLastError());
 }
 

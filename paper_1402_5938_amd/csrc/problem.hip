@@ -33,8 +33,13 @@ void validate(const gllmg_config& c) {
   for (int a = 0; a < c.dim; ++a)
     GLLMG_CHECK(c.nelem[a] >= 1 && (int64_t)c.nelem[a] * c.order + 1 < (1 << 30), GLLMG_EINVAL,
                 "nelem out of range");
-  GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P, GLLMG_EINVAL,
-              "hierarchy must be GLLMG_HIER_H or GLLMG_HIER_P");
+  GLLMG_CHECK(c.hierarchy == GLLMG_HIER_H || c.hierarchy == GLLMG_HIER_P ||
+                  c.hierarchy == GLLMG_HIER_LOW,
+              GLLMG_EINVAL, "hierarchy must be GLLMG_HIER_H, GLLMG_HIER_P or GLLMG_HIER_LOW");
+  GLLMG_CHECK(c.hierarchy != GLLMG_HIER_LOW || (c.low_cycles >= 1 && c.low_cycles <= 64),
+              GLLMG_EINVAL, "low_cycles must be in [1, 64]");
+  GLLMG_CHECK(c.hierarchy != GLLMG_HIER_LOW || c.quadrature == GLLMG_QUAD_GLL, GLLMG_EUNSUPPORTED,
+              "the first-order hierarchy is built for GLL collocation");
   GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
                   c.smoother == GLLMG_SMOOTH_SSOR || c.smoother == GLLMG_SMOOTH_L1_JACOBI ||
                   c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI,
@@ -80,6 +85,11 @@ std::vector<LevelSpec> plan_levels(const gllmg_config& c) {
       s.p = (s.p + 1) / 2;
       L.push_back(s);
     }
+  if (c.hierarchy == GLLMG_HIER_LOW && s.p > 1) {  // first-order cells on the order-p nodes
+    for (int a = 0; a < c.dim; ++a) s.ne[a] *= s.p;
+    s.p = 1;
+    L.push_back(s);
+  }
   for (;;) {
     bool even = true;
     for (int a = 0; a < c.dim; ++a) even = even && (s.ne[a] % 2 == 0);
@@ -244,7 +254,9 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
       L.Ainv32 = f32 ? (float*)A.take(sizeof(float) * L.nint * L.nint) : nullptr;
     }
   }
-  for (size_t l = 0; l + 1 < specs.size(); ++l) {
+  // the first-order hierarchy's levels 0 and 1 share their nodes: no transfer between them
+  const bool shares = c.hierarchy == GLLMG_HIER_LOW && specs.size() > 1 && specs[0].p > 1;
+  for (size_t l = shares ? 1 : 0; l + 1 < specs.size(); ++l) {
     Level& F = P->L[l];
     Level& C = P->L[l + 1];
     face = std::max(face, restrict_buffer_elems(F, C));
@@ -486,6 +498,11 @@ void check_flag(gllmg_problem* P, hipStream_t s) {
   GLLMG_CHECK(!(f & 8), GLLMG_EINVAL, "an element block of the block-Jacobi smoother is not positive definite");
 }
 
+// The first-order hierarchy's levels 0 (order p) and 1 (first order) share their nodes.
+bool low_first(const gllmg_problem* P) {
+  return P->cfg.hierarchy == GLLMG_HIER_LOW && P->L.size() > 1 && P->L[0].g.p > 1;
+}
+
 // Phi and mu at every node of level l, into `nodal` (N dim coordinates, then N values of mu):
 // the built-in families by the same kernels as gllmg_node_coords and gllmg_eval_field; callback
 // kinds by the caller's functions, called once with every node of the level in node order
@@ -589,6 +606,15 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
       }
       launch_geometry_gauss(L, nodal, muq, L.G64, f32 ? L.G32 : nullptr, l == 0 ? P->wdetq : nullptr,
                             P->flag, s);
+    } else if (l >= 1 && low_first(P)) {
+      // first-order levels: the vertices are the order-p nodes (every stride-th one per axis),
+      // whose Phi and mu level 0 left in `nodal`
+      double* nl = nodal + 4 * (size_t)P->L[0].g.N;
+      const int stride = (P->L[0].g.nn[0] - 1) / (L.g.nn[0] - 1);
+      launch_subsample_nodal(P->L[0].g, L.g, stride, nodal, nodal + (size_t)P->L[0].g.N * c.dim,
+                             nl, nl + (size_t)L.g.N * c.dim, s);
+      launch_geometry(L, nl, nl + (size_t)L.g.N * c.dim, L.G64, f32 ? L.G32 : nullptr, wdet,
+                      P->flag, s);
     } else {
       nodal_fields(P, (int)l, nodal, s);
       launch_geometry(L, nodal, nodal + (size_t)L.g.N * c.dim, L.G64, f32 ? L.G32 : nullptr, wdet,
@@ -611,7 +637,7 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
       if (f32) cast_64_32(L.g.E * (int64_t)block_slots(L) * block_slots(L), L.Binv64, L.Binv32, s);
     }
   }
-  for (size_t l = 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
+  for (size_t l = low_first(P) ? 1 : 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
   for (size_t l = 0; l < P->L.size(); ++l)
     if (P->L[l].has_coarse || !P->L[l].Ainv64)
       P->L[l].lmax = c.cheb_safety * lanczos_lmax(P, (int)l, s);
@@ -846,9 +872,41 @@ void vcycle_level(gllmg_problem* P, int l, int pr, const void* b, void* x, hipSt
   smooth_impl(P, l, pr, b, x, P->cfg.nu_post, false, s);
 }
 
+// First-order hierarchy: z = low_cycles sweeps x <- x + V_1 (r - A_1 x) from x = 0 at level 1
+// (whose nodes are level 0's), in precision pr; level 1's b and x vectors hold the residual and
+// the correction (the V-cycle from level 1 takes r and z as its own b and x).
+void low_sweeps(gllmg_problem* P, int pr, const void* r, void* z, hipStream_t s) {
+  Level& L1 = P->L[1];
+  vcycle_level(P, 1, pr, r, z, s);
+  for (int it = 1; it < P->cfg.low_cycles; ++it) {
+    residual(P, 1, pr, r, z, L1.vb[pr], s);
+    vcycle_level(P, 1, pr, L1.vb[pr], L1.vx[pr], s);
+    vec_axpy(pr, L1.g.N, 1.0, L1.vx[pr], z, s);
+  }
+}
+
+// The preconditioner in precision pr on vectors of that precision: the V-cycle, or the
+// first-order sweeps.
+void precond_level0(gllmg_problem* P, int pr, const void* r, void* z, hipStream_t s) {
+  if (low_first(P))
+    low_sweeps(P, pr, r, z, s);
+  else
+    vcycle_level(P, 0, pr, r, z, s);
+}
+
 // z = V r for FP64 vectors r, z on the finest level, in the problem's V-cycle precision
 void precond_eager(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
   Level& L = P->L[0];
+  if (low_first(P)) {
+    if (P->vprec == 0) {
+      low_sweeps(P, 0, r, z, s);
+    } else {
+      cast_64_32(L.g.N, r, (float*)L.vb[1], s);
+      low_sweeps(P, 1, L.vb[1], L.vx[1], s);
+      cast_32_64(L.g.N, (const float*)L.vx[1], z, s);
+    }
+    return;
+  }
   if (P->vprec == 0) {
     vcycle_level(P, 0, 0, r, z, s);
   } else {
@@ -1115,6 +1173,7 @@ gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, 
 // n0 or at 2), and maxit below the history capacity.
 bool batch_eligible(const gllmg_problem* P, int maxit) {
   if (!P->persistent || P->cfg.dim != 3 || P->vprec != 1) return false;
+  if (P->cfg.hierarchy == GLLMG_HIER_LOW) return false;
   if (P->cfg.quadrature != GLLMG_QUAD_GLL) return false;
   if (P->cfg.smoother != GLLMG_SMOOTH_JACOBI && P->cfg.smoother != GLLMG_SMOOTH_CHEBYSHEV) return false;
   if (P->L.size() > (size_t)kBatchMaxLevels || !P->L.back().Ainv64) return false;
@@ -1458,6 +1517,7 @@ void gllmg_config_default(gllmg_config* c) {
   c->vcycle_prec = GLLMG_F64;
   c->eig_seed = 0;
   c->quadrature = GLLMG_QUAD_GLL;
+  c->low_cycles = 1;
 }
 
 gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* bytes) {
@@ -1718,6 +1778,8 @@ gllmg_status gllmg_prolong(const gllmg_problem* P, int32_t fl, gllmg_prec prec, 
   return guard([&]() {
     level_of(P, fl);
     level_of(P, fl + 1);
+    GLLMG_CHECK(!(fl == 0 && low_first(P)), GLLMG_EUNSUPPORTED,
+                "levels 0 and 1 of the first-order hierarchy share their nodes (no transfer)");
     const int pr = prec_index(P, prec);
     check_ptr(xc, pr == 0 ? 8 : 4, "xc");
     check_ptr(xf, pr == 0 ? 8 : 4, "xf");
@@ -1732,6 +1794,8 @@ gllmg_status gllmg_restrict(const gllmg_problem* P, int32_t fl, gllmg_prec prec,
   return guard([&]() {
     level_of(P, fl);
     level_of(P, fl + 1);
+    GLLMG_CHECK(!(fl == 0 && low_first(P)), GLLMG_EUNSUPPORTED,
+                "levels 0 and 1 of the first-order hierarchy share their nodes (no transfer)");
     const int pr = prec_index(P, prec);
     check_ptr(rf, pr == 0 ? 8 : 4, "rf");
     check_ptr(rc, pr == 0 ? 8 : 4, "rc");
@@ -1750,7 +1814,7 @@ gllmg_status gllmg_vcycle(const gllmg_problem* P, gllmg_prec prec, const void* r
     check_ptr(r, pr == 0 ? 8 : 4, "r");
     check_ptr(e, pr == 0 ? 8 : 4, "e");
     GLLMG_CHECK(r != e, GLLMG_EINVAL, "r and e must not alias");
-    vcycle_level(const_cast<gllmg_problem*>(P), 0, pr, r, e, (hipStream_t)stream);
+    precond_level0(const_cast<gllmg_problem*>(P), pr, r, e, (hipStream_t)stream);
     return GLLMG_OK;
   });
 }
@@ -1840,7 +1904,9 @@ gllmg_status gllmg_batch_solve(gllmg_problem* const* probs, const double* const*
       for (int i = 0; i < count; ++i) {
         gllmg_problem* P = probs[i];
         if (P->sv.active || !P->persistent || !P->L.back().Ainv64) continue;
-        if (!groupable_smoother(P->cfg.smoother) || P->cfg.quadrature != GLLMG_QUAD_GLL) continue;
+        if (!groupable_smoother(P->cfg.smoother) || P->cfg.quadrature != GLLMG_QUAD_GLL ||
+            P->cfg.hierarchy == GLLMG_HIER_LOW)
+          continue;
         if (!b[i] || !x[i] || ((uintptr_t)b[i] % 8) || ((uintptr_t)x[i] % 8)) continue;
         bool placed = false;
         for (auto& sh : shapes)

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("GLLMG_LIB", os.path.join(HERE, "libgllmg.so"))
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTCONV, EBREAKDOWN, EUNSUPPORTED = range(7)
 F64, F32 = 0, 1
-HIER_H, HIER_P = 0, 1
+HIER_H, HIER_P, HIER_LOW = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_CHEBYSHEV, SMOOTH_SSOR, SMOOTH_L1_JACOBI, SMOOTH_BLOCK_JACOBI = 0, 1, 2, 3, 4
 SMOOTHERS = {"jacobi": SMOOTH_JACOBI, "chebyshev": SMOOTH_CHEBYSHEV, "ssor": SMOOTH_SSOR,
              "l1jacobi": SMOOTH_L1_JACOBI, "blockjacobi": SMOOTH_BLOCK_JACOBI}
@@ -53,7 +53,8 @@ class Config(C.Structure):
                 ("hierarchy", C.c_int32), ("max_levels", C.c_int32), ("smoother", C.c_int32),
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("cheb_lo", C.c_double), ("cheb_safety", C.c_double), ("eig_steps", C.c_int32),
-                ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64), ("quadrature", C.c_int32)]
+                ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64), ("quadrature", C.c_int32),
+                ("low_cycles", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -161,7 +162,8 @@ def _callback(fn, is_map):
 
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
                 vcycle_prec="f64", max_levels=0, omega=None, cheb_lo=0.25,
-                cheb_safety=1.0, eig_steps=10, eig_seed=0, quadrature="gll") -> Config:
+                cheb_safety=1.0, eig_steps=10, eig_seed=0, quadrature="gll",
+                low_cycles=1) -> Config:
     c = Config()
     lib().gllmg_config_default(C.byref(c))
     c.dim = dim
@@ -169,7 +171,10 @@ def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu
     for a in range(3):
         c.nelem[a] = int(ne[a])
     c.order = order
-    c.hierarchy = HIER_P if hierarchy == "p" else HIER_H
+    if hierarchy not in ("h", "p", "low"):
+        raise ValueError(f"unknown hierarchy {hierarchy!r}")
+    c.hierarchy = {"h": HIER_H, "p": HIER_P, "low": HIER_LOW}[hierarchy]
+    c.low_cycles = low_cycles
     if smoother not in SMOOTHERS:
         raise ValueError(f"unknown smoother {smoother!r}")
     c.smoother = SMOOTHERS[smoother]

@@ -253,6 +253,41 @@ def workload_smoothers(a):
             "nodes": inputs.node_count(prob.nelem, prob.order), "cases": rows}
 
 
+def workload_lowprec(a):
+    """The benchmark problem (3D warped, a.nelem^3 hexes at p = a.order, f = 1) solved to 1e-10
+    by FP64 PCG preconditioned by the p-multigrid V-cycle and by the first-order hierarchy's
+    preconditioner (k sweeps of the V-cycle of first-order cells on the order-p nodes, k = 1, 2,
+    4): iterations, time to solution, time of one preconditioner application."""
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
+    rows = []
+    for hier, k in (("p", 1), ("low", 1), ("low", 2), ("low", 4)):
+        cfg = gllmg.make_config(3, prob.nelem, prob.order, hier, "chebyshev", 4, low_cycles=k)
+        t0 = time.perf_counter()
+        G = gllmg.Problem(cfg, prob.map, prob.mu)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        b = G.rhs(G.eval_field(prob.f))
+        t, r, _ = _solve_timed(G, b, a.steps, a.warmup, prob.rtol, prob.maxit)
+        z = torch.empty_like(b)
+        G.vcycle(b, z)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        G.vcycle(b, z)
+        e1.record()
+        torch.cuda.synchronize()
+        rows.append({"hierarchy": hier, "low_cycles": k if hier == "low" else None,
+                     "levels": G.nlevels, "pcg_iterations": r.iters, "converged": r.converged,
+                     "time_to_solution_ms": t * 1e3, "precond_ms": e0.elapsed_time(e1),
+                     "setup_s": t_setup})
+        G.close()
+        torch.cuda.empty_cache()
+    return {"workload": f"hierarchies: 3D warped var {a.nelem}^3 hexes p={a.order}, FP64 PCG to 1e-10",
+            "cases": rows}
+
+
 def apply_flops_gauss(dim, ne, p):
     """Flops of one Gauss-quadrature product (q = p + 1 points): the five sum-factorized passes
     take 16 n^4 (3D) or 6 n^3 (2D) multiply-adds per element, the pointwise factors 9 n^3 (4 n^2)."""
@@ -400,7 +435,7 @@ def workload_apply(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep",
-                                                          "smoothers", "gauss"])
+                                                          "smoothers", "gauss", "lowprec"])
     ap.add_argument("--smoothers", default="chebyshev,jacobi,ssor")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
@@ -427,7 +462,8 @@ def main():
     if a.workload != "config2":
         fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
               "apply": workload_apply, "sweep": workload_sweep,
-              "smoothers": workload_smoothers, "gauss": workload_gauss}[a.workload]
+              "smoothers": workload_smoothers, "gauss": workload_gauss,
+              "lowprec": workload_lowprec}[a.workload]
         print(json.dumps(fn(a)))
         return
     prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)

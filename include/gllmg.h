@@ -290,6 +290,11 @@ gllmg_status gllmg_solve_begin(gllmg_problem* prob, int32_t mode, const double* 
 gllmg_status gllmg_solve_poll(gllmg_problem* prob, int32_t* done);
 gllmg_status gllmg_solve_end(gllmg_problem* prob, gllmg_solve_stats* stats);
 
+/* Device copy of `bytes` bytes (a multiple of 16; src and dst 16-byte aligned, not overlapping)
+ * by a plain streaming kernel, 16 bytes per lane: the library's achievable-bandwidth reference
+ * for its roofline figures. Asynchronous. */
+gllmg_status gllmg_stream_copy(const void* src, void* dst, size_t bytes, void* stream);
+
 /* Solve `count` independent problems (any mix of dimension, mesh, order and precision), all
  * ordered after `stream`; the call returns when every solve has finished. Three paths:
  * - In PCG mode, two or more problems that share one shape (dimension, elements, order,

@@ -291,6 +291,7 @@ void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipSt
 
 // elementwise vector kernels (prec 0 = double, 1 = float); scalars are passed in FP64
 void vec_copy(int prec, int64_t n, const void* a, void* out, hipStream_t s);
+void stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);  // bytes % 16 == 0
 void vec_zero(int prec, int64_t n, void* out, hipStream_t s);
 void vec_sub(int prec, int64_t n, const void* a, const void* b, void* out, hipStream_t s);  // a - b
 void vec_axpy(int prec, int64_t n, double alpha, const void* x, void* y, hipStream_t s);   // y += a x

@@ -367,6 +367,22 @@ void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipSt
   GLLMG_HIP(hipGetLastError());
 }
 
+// A plain streaming copy, 16 bytes per lane (the achievable-bandwidth reference of the
+// roofline figures): one read and one write of every byte.
+__global__ void __launch_bounds__(256) k_stream_copy(int64_t n16, const uint4* __restrict__ a,
+                                                     uint4* __restrict__ o) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n16) o[i] = a[i];
+}
+
+void stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)((n16 + 255) / 256)), dim3(256), 0, s, n16,
+                     (const uint4*)src, (uint4*)dst);
+  GLLMG_HIP(hipGetLastError());
+}
+
 void vec_copy(int prec, int64_t n, const void* a, void* o, hipStream_t s) {
   if (prec == 0)
     with_gr([&](auto gr) {

@@ -1757,6 +1757,19 @@ gllmg_status gllmg_apply_noalloc(const gllmg_problem* P, int32_t level, gllmg_pr
   });
 }
 
+gllmg_status gllmg_stream_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  return guard([&]() {
+    check_ptr(src, 16, "src");
+    check_ptr(dst, 16, "dst");
+    GLLMG_CHECK(bytes % 16 == 0, GLLMG_EINVAL, "bytes must be a multiple of 16");
+    const char* a = (const char*)src;
+    const char* b = (const char*)dst;
+    GLLMG_CHECK(a + bytes <= b || b + bytes <= a, GLLMG_EINVAL, "src and dst overlap");
+    stream_copy(src, dst, bytes, (hipStream_t)stream);
+    return GLLMG_OK;
+  });
+}
+
 gllmg_status gllmg_smooth(const gllmg_problem* P, int32_t level, gllmg_prec prec, const void* b,
                           void* x, int32_t steps, int32_t zero_guess, void* stream) {
   return guard([&]() {

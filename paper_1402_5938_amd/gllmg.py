@@ -70,7 +70,8 @@ EXPORTS = ["gllmg_last_error", "gllmg_config_default", "gllmg_plan", "gllmg_setu
            "gllmg_set_graphs", "gllmg_set_persistent",
            "gllmg_node_coords", "gllmg_eval_field", "gllmg_rhs", "gllmg_diag", "gllmg_apply",
            "gllmg_apply_noalloc", "gllmg_smooth", "gllmg_prolong", "gllmg_restrict", "gllmg_vcycle", "gllmg_solve",
-           "gllmg_solve_begin", "gllmg_solve_poll", "gllmg_solve_end", "gllmg_batch_solve"]
+           "gllmg_solve_begin", "gllmg_solve_poll", "gllmg_solve_end", "gllmg_batch_solve",
+           "gllmg_stream_copy"]
 
 
 def lib():
@@ -115,6 +116,7 @@ def lib():
     L.gllmg_solve_end.argtypes = [vp, C.POINTER(SolveStats)]
     L.gllmg_batch_solve.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), i32, i32, dbl,
                                     i32, C.POINTER(SolveStats), C.POINTER(C.c_int), vp]
+    L.gllmg_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
     for name in EXPORTS[2:]:
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -443,6 +445,14 @@ def batch_solve(problems, bs, xs, mode="pcg", rtol=1e-10, maxit=500, stream=None
     if st not in (OK, ENOTCONV):
         _check(st)
     return [_result(status[i], stats[i], hists[i], problems[i].nlevels) for i in range(n)]
+
+
+def stream_copy(src, dst, stream=None):
+    """gllmg_stream_copy of a whole contiguous device tensor into another of the same size."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().gllmg_stream_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream)))
+    return dst
 
 
 def _prec_of(t):

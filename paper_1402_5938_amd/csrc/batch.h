@@ -237,12 +237,14 @@ __device__ __attribute__((noinline)) void b_coarse(const BatchLevel& L, const T*
       continue;
     }
     const int64_t row = (gx - 1) + (int64_t)mx * ((gy - 1) + (int64_t)my * (gz - 1));
+    const T* a = Ainv + row;  // the symmetric inverse's column `row` (coalesced over lanes)
     T acc = T(0);
-    for (int64_t j = 0; j < L.nint; ++j) {
-      const int jx = (int)(j % mx), jy = (int)((j / mx) % my), jz = (int)(j / ((int64_t)mx * my));
-      const int64_t node = (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (jz + 1));
-      acc += Ainv[row * L.nint + j] * b[node];
-    }
+    int64_t j = 0;
+    for (int jz = 0; jz < nz - 2; ++jz)
+      for (int jy = 0; jy < my; ++jy) {
+        const T* bl = b + 1 + (int64_t)nx * ((jy + 1) + (int64_t)ny * (jz + 1));
+        for (int jx = 0; jx < mx; ++jx, ++j) acc += a[j * L.nint] * bl[jx];
+      }
     x[t] = acc;
   }
   __syncthreads();
@@ -387,19 +389,20 @@ __device__ void b_vcycle(const BatchCtx& c, const T* b0, T* x0) {
   }
 }
 
-// z = V r for the FP64 level-0 vectors, in the problem's V-cycle precision T
+// z = V r for the FP64 level-0 vectors, in the problem's V-cycle precision T; nr = ||r||_2
 template <int N0, typename T>
-__device__ void b_precond(const BatchCtx& c, const double* r, double* z) {
+__device__ void b_precond(const BatchCtx& c, const double* r, double* z, double nr) {
   if constexpr (sizeof(T) == 8) {
     b_vcycle<N0, double>(c, r, z);
-  } else {  // FP32 V-cycle between casts
+  } else {  // FP32 V-cycle between casts, on r scaled by a power of two to norm about 1
     const BatchLevel& L = c.L[0];
     float* rb = (float*)L.vb[1];
     float* xb = (float*)L.vx[1];
-    for (int64_t i = threadIdx.x; i < L.g.N; i += kBT) rb[i] = (float)r[i];
+    const double sc = pow2_inv_norm(nr * nr), isc = 1.0 / sc;
+    for (int64_t i = threadIdx.x; i < L.g.N; i += kBT) rb[i] = (float)(r[i] * sc);
     __syncthreads();
     b_vcycle<N0, float>(c, rb, xb);
-    for (int64_t i = threadIdx.x; i < L.g.N; i += kBT) z[i] = (double)xb[i];
+    for (int64_t i = threadIdx.x; i < L.g.N; i += kBT) z[i] = (double)xb[i] * isc;
     __syncthreads();
   }
 }
@@ -436,7 +439,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
   if (status == 1) {
     double g = 0.0;
     if (mode == GLLMG_MODE_PCG) {
-      b_precond<N0, T>(c, r, z);
+      b_precond<N0, T>(c, r, z, n0);
       g = b_dot<double>(z, r, N, red);
       for (int64_t i = threadIdx.x; i < N; i += kBT) p[i] = z[i];
       __syncthreads();
@@ -458,7 +461,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
         }
         nr = sqrt(b_sum(acc, red));
       } else {
-        b_precond<N0, T>(c, r, z);
+        b_precond<N0, T>(c, r, z, nr);
         for (int64_t i = threadIdx.x; i < N; i += kBT) x[i] = x[i] + z[i];
         __syncthreads();
         Epi rs;
@@ -480,7 +483,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
       }
       if (iters >= maxit) break;
       if (mode == GLLMG_MODE_PCG) {
-        b_precond<N0, T>(c, r, z);
+        b_precond<N0, T>(c, r, z, nr);
         const double gn = b_dot<double>(z, r, N, red);
         const double be = gn / g;
         for (int64_t i = threadIdx.x; i < N; i += kBT) p[i] = z[i] + be * p[i];

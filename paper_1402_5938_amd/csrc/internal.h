@@ -14,6 +14,18 @@
 
 namespace gllmg {
 
+// 2^-e with 2^e within a factor sqrt(2) of sqrt(rr), the norm of a vector r with (r, r) = rr:
+// r 2^-e has norm about 1. A power of two scales exactly in FP64 and FP32 while no value leaves
+// the normal range, so an FP32 V-cycle of r 2^-e, scaled back by 2^e, equals bitwise the FP32
+// V-cycle of r itself wherever that neither overflows nor underflows, and keeps residuals far
+// outside FP32's range (below 1e-38 or above 3e38) representable. 1 for rr = 0 or not finite.
+__host__ __device__ inline double pow2_inv_norm(double rr) {
+  if (!(rr > 0.0) || !(rr <= 1.7976931348623157e308)) return 1.0;
+  int k = 0;
+  (void)frexp(rr, &k);  // rr in [2^(k-1), 2^k)
+  return ldexp(1.0, -(k >> 1));
+}
+
 // ------------------------------------------------------------------ errors
 struct Error : std::runtime_error {
   gllmg_status status;
@@ -302,9 +314,11 @@ void vec_sqrt(int64_t n, const double* a, double* out, hipStream_t s);
 void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
                   hipStream_t s);                                        // y += sign * (*coef) x
 void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s);     // v = v ? 1/v : 0
-void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s);        // v = e_idx
-void cast_64_32(int64_t n, const double* a, float* out, hipStream_t s);
-void cast_32_64(int64_t n, const float* a, double* out, hipStream_t s);
+// Casts between the FP64 and FP32 vectors; with rr (the device (r, r) of the FP64 vector that the
+// FP32 one stands for) both scale by pow2_inv_norm(*rr): out = float(a * 2^-e), then
+// out = double(a) * 2^e.
+void cast_64_32(int64_t n, const double* a, float* out, hipStream_t s, const double* rr = nullptr);
+void cast_32_64(int64_t n, const float* a, double* out, hipStream_t s, const double* rr = nullptr);
 // Chebyshev / Jacobi fused updates
 // d = dinv (b - t) / theta (r = b - t when t is given); th, when given, holds theta on the
 // device (per problem in a launch group) and replaces the argument

@@ -35,14 +35,18 @@ k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* _
     x[t] = T(0);
     return;
   }
-  const int mx = nx - 2, my = ny - 2;
+  const int mx = nx - 2, my = ny - 2, mz = g.dim == 3 ? nz - 2 : 1;
   const int64_t row = (gx - 1) + (int64_t)mx * ((gy - 1) + (int64_t)my * (g.dim == 3 ? gz - 1 : 0));
+  // the inverse is exactly symmetric: row `row` is read as column `row`, so the lanes of a wave
+  // (consecutive interior nodes of a line) read consecutive addresses
+  const T* a = Ainv + row;
   T acc = T(0);
-  for (int64_t j = 0; j < nint; ++j) {
-    const int jx = (int)(j % mx), jy = (int)((j / mx) % my), jz = (int)(j / ((int64_t)mx * my));
-    const int64_t node = (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (g.dim == 3 ? jz + 1 : 0));
-    acc += Ainv[row * nint + j] * b[node];
-  }
+  int64_t j = 0;
+  for (int jz = 0; jz < mz; ++jz)
+    for (int jy = 0; jy < my; ++jy) {
+      const T* bl = b + 1 + (int64_t)nx * ((jy + 1) + (int64_t)ny * (g.dim == 3 ? jz + 1 : 0));
+      for (int jx = 0; jx < mx; ++jx, ++j) acc += a[j * nint] * bl[jx];
+    }
   x[t] = acc;
 }
 
@@ -85,26 +89,30 @@ template <typename T> __global__ void k_scale_mul(int64_t n, T al, const T* a, c
   if (i < n) o[i] = al * a[i] * b[i];
 }
 template <bool GR>
-__global__ void k_c6432(int64_t n, const double* a, float* o, Grp gp) {
+__global__ void k_c6432(int64_t n, const double* a, const double* rr, float* o, Grp gp) {
   if constexpr (GR) {
     int64_t dk;
     if (!grp_begin(gp, &dk)) return;
     a = shift(a, dk);
     o = shift(o, dk);
+    if (rr) rr = shift(rr, dk);
   }
+  const double sc = rr ? pow2_inv_norm(*rr) : 1.0;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) o[i] = (float)a[i];
+  if (i < n) o[i] = (float)(a[i] * sc);
 }
 template <bool GR>
-__global__ void k_c3264(int64_t n, const float* a, double* o, Grp gp) {
+__global__ void k_c3264(int64_t n, const float* a, const double* rr, double* o, Grp gp) {
   if constexpr (GR) {
     int64_t dk;
     if (!grp_begin(gp, &dk)) return;
     a = shift(a, dk);
     o = shift(o, dk);
+    if (rr) rr = shift(rr, dk);
   }
+  const double sc = rr ? 1.0 / pow2_inv_norm(*rr) : 1.0;  // exact: a power of two
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) o[i] = (double)a[i];
+  if (i < n) o[i] = (double)a[i] * sc;
 }
 
 __global__ void k_div(int64_t n, const double* a, double den, double* o) {
@@ -122,10 +130,6 @@ __global__ void k_axpy_dev(int64_t n, const double* coef, double sign, const dou
 template <typename T> __global__ void k_recip_masked(int64_t n, T* v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = v[i] != T(0) ? T(1) / v[i] : T(0);
-}
-__global__ void k_set_unit(int64_t n, int64_t idx, double* v) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = i == idx ? 1.0 : 0.0;
 }
 
 // Chebyshev start: r = b - t (t = A x; t == nullptr means x = 0 and r = b), d = dinv r / theta.
@@ -468,22 +472,17 @@ void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s) {
     hipLaunchKernelGGL(k_recip_masked<float>, dim3(nb(n)), dim3(kT), 0, s, n, (float*)v);
   GLLMG_HIP(hipGetLastError());
 }
-void set_unit(int64_t n, int64_t idx, double* v, hipStream_t s) {
-  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_set_unit, dim3(nb(n)), dim3(kT), 0, s, n, idx, v);
-  GLLMG_HIP(hipGetLastError());
-}
-void cast_64_32(int64_t n, const double* a, float* o, hipStream_t s) {
+void cast_64_32(int64_t n, const double* a, float* o, hipStream_t s, const double* rr) {
   with_gr([&](auto gr) {
     constexpr bool GR = decltype(gr)::value;
-    hipLaunchKernelGGL((k_c6432<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, o, cur_grp());
+    hipLaunchKernelGGL((k_c6432<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, rr, o, cur_grp());
   });
   GLLMG_HIP(hipGetLastError());
 }
-void cast_32_64(int64_t n, const float* a, double* o, hipStream_t s) {
+void cast_32_64(int64_t n, const float* a, double* o, hipStream_t s, const double* rr) {
   with_gr([&](auto gr) {
     constexpr bool GR = decltype(gr)::value;
-    hipLaunchKernelGGL((k_c3264<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, o, cur_grp());
+    hipLaunchKernelGGL((k_c3264<GR>), dim3(nb(n), grp_count()), dim3(kT), 0, s, n, a, rr, o, cur_grp());
   });
   GLLMG_HIP(hipGetLastError());
 }

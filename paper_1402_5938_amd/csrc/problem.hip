@@ -455,24 +455,46 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
   return tridiag_max_eig(al, be);
 }
 
+// The coarsest operator's interior block, column by column from matrix-free products. Two
+// nodes couple only if they share an element, so they lie within p index steps of each other
+// along every axis; nodes 2p+1 steps apart along some axis therefore couple to disjoint sets
+// of nodes, and one product of the sum of their unit vectors yields all their columns at once
+// (each entry bitwise equal to the product of its own unit vector: an element sees at most one
+// of the nodes). (2p+1)^d products instead of one per interior node.
 void build_coarse_inverse(gllmg_problem* P, hipStream_t s) {
   Level& L = P->L.back();
   const int64_t N = L.g.N, ni = L.nint;
+  const int dim = L.g.dim, p = L.g.p, c = 2 * p + 1;
   double* e = (double*)P->scratch;
   double* y = e + N;
-  std::vector<double> A((size_t)ni * ni), col(N);
-  const int mx = L.g.nn[0] - 2, my = L.g.nn[1] - 2;
-  auto node_of = [&](int64_t j) {
-    const int jx = (int)(j % mx), jy = (int)((j / mx) % my), jz = (int)(j / ((int64_t)mx * my));
-    return (jx + 1) + (int64_t)L.g.nn[0] * ((jy + 1) + (int64_t)L.g.nn[1] * (L.g.dim == 3 ? jz + 1 : 0));
+  const int nx = L.g.nn[0], ny = L.g.nn[1];
+  const int mx = nx - 2, my = ny - 2, mz = dim == 3 ? L.g.nn[2] - 2 : 1;
+  auto node = [&](int jx, int jy, int jz) {
+    return (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (dim == 3 ? jz + 1 : 0));
   };
-  for (int64_t j = 0; j < ni; ++j) {
-    set_unit(N, node_of(j), e, s);
-    apply_level(P, (int)P->L.size() - 1, 0, 0, e, y, s);
-    GLLMG_HIP(hipMemcpyAsync(col.data(), y, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-    GLLMG_HIP(hipStreamSynchronize(s));
-    for (int64_t i = 0; i < ni; ++i) A[(size_t)i * ni + j] = col[node_of(i)];
-  }
+  auto row = [&](int jx, int jy, int jz) { return jx + (int64_t)mx * (jy + (int64_t)my * jz); };
+  std::vector<double> A((size_t)ni * ni, 0.0), eh(N), col(N);
+  for (int oz = 0; oz < std::min(c, mz); ++oz)
+    for (int oy = 0; oy < std::min(c, my); ++oy)
+      for (int ox = 0; ox < std::min(c, mx); ++ox) {
+        std::fill(eh.begin(), eh.end(), 0.0);
+        for (int jz = oz; jz < mz; jz += c)
+          for (int jy = oy; jy < my; jy += c)
+            for (int jx = ox; jx < mx; jx += c) eh[node(jx, jy, jz)] = 1.0;
+        GLLMG_HIP(hipMemcpyAsync(e, eh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
+        apply_level(P, (int)P->L.size() - 1, 0, 0, e, y, s);
+        GLLMG_HIP(hipMemcpyAsync(col.data(), y, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+        GLLMG_HIP(hipStreamSynchronize(s));
+        for (int jz = oz; jz < mz; jz += c)
+          for (int jy = oy; jy < my; jy += c)
+            for (int jx = ox; jx < mx; jx += c) {
+              const int64_t j = row(jx, jy, jz);
+              for (int iz = std::max(0, jz - p); iz <= std::min(mz - 1, jz + p); ++iz)
+                for (int iy = std::max(0, jy - p); iy <= std::min(my - 1, jy + p); ++iy)
+                  for (int ix = std::max(0, jx - p); ix <= std::min(mx - 1, jx + p); ++ix)
+                    A[(size_t)row(ix, iy, iz) * ni + j] = col[node(ix, iy, iz)];
+            }
+      }
   // symmetrize the rounding of the matrix-free products
   for (int64_t i = 0; i < ni; ++i)
     for (int64_t j = 0; j < i; ++j) {
@@ -894,25 +916,22 @@ void precond_level0(gllmg_problem* P, int pr, const void* r, void* z, hipStream_
     vcycle_level(P, 0, pr, r, z, s);
 }
 
-// z = V r for FP64 vectors r, z on the finest level, in the problem's V-cycle precision
+// device scalars of a solve in P->scal: (r, r), (p, A p), the two (z, r), (b - A x, b - A x)
+enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
+
+// z = V r for the solve's FP64 residual r = P->pr, with (r, r) in scal[S_RR], into z on the
+// finest level, in the problem's V-cycle precision. An FP32 preconditioner sees r scaled by a
+// power of two to norm about 1 and its result is scaled back (pow2_inv_norm).
 void precond_eager(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
+  GLLMG_CHECK(r == P->pr, GLLMG_EINVAL, "the preconditioner runs on the solve's residual vector");
   Level& L = P->L[0];
-  if (low_first(P)) {
-    if (P->vprec == 0) {
-      low_sweeps(P, 0, r, z, s);
-    } else {
-      cast_64_32(L.g.N, r, (float*)L.vb[1], s);
-      low_sweeps(P, 1, L.vb[1], L.vx[1], s);
-      cast_32_64(L.g.N, (const float*)L.vx[1], z, s);
-    }
-    return;
-  }
+  const double* rr = P->scal + S_RR;
   if (P->vprec == 0) {
-    vcycle_level(P, 0, 0, r, z, s);
+    precond_level0(P, 0, r, z, s);
   } else {
-    cast_64_32(L.g.N, r, (float*)L.vb[1], s);
-    vcycle_level(P, 0, 1, L.vb[1], L.vx[1], s);
-    cast_32_64(L.g.N, (const float*)L.vx[1], z, s);
+    cast_64_32(L.g.N, r, (float*)L.vb[1], s, rr);
+    precond_level0(P, 1, L.vb[1], L.vx[1], s);
+    cast_32_64(L.g.N, (const float*)L.vx[1], z, s, rr);
   }
 }
 
@@ -973,7 +992,6 @@ void precond(gllmg_problem* P, const double* r, double* z, hipStream_t s) {
   for (size_t l = 0; l < P->L.size(); ++l) P->L[l].applies += P->vapplies[l];
 }
 
-enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
 enum { PH_INIT = 0, PH_ITER = 1, PH_FINAL = 2 };
 
 // Host-visible scalars of the solve arrive in the pinned buffer hbuf through stream-ordered

@@ -9,7 +9,9 @@
 // Derivative matrix D_ij = l_j'(x_i) in barycentric form from the computed nodes (off-diagonal
 // (lam_j / lam_i) / (x_i - x_j), diagonal minus the row's other entries; see ref_element).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <thread>
 
 #include "internal.h"
 
@@ -190,38 +192,114 @@ void lagrange_at(const RefElem& re, double y, double* out) {
   for (int j = 0; j < n; ++j) out[j] = (lam[j] / (y - re.xi[j])) / den;
 }
 
+namespace {
+// Host threads for the dense setup loops: up to 16, about one per 64 rows.
+int host_threads(int n) {
+  return std::max(1, std::min({16, (int)std::thread::hardware_concurrency(), n / 64}));
+}
+
+// Runs body(t) on T host threads (t = 0..T-1) and joins them.
+template <class F>
+void run_threads(int T, F body) {
+  if (T == 1) return body(0);
+  std::vector<std::thread> th;
+  for (int t = 0; t < T; ++t) th.emplace_back([&, t] { body(t); });
+  for (std::thread& x : th) x.join();
+}
+
+// Barrier of T spinning host threads; what a thread wrote before wait() is visible to every
+// thread after it.
+class SpinBarrier {
+ public:
+  explicit SpinBarrier(int T) : T_(T) {}
+  void wait() {
+    const int g = gen_.load(std::memory_order_acquire);
+    if (count_.fetch_add(1, std::memory_order_acq_rel) == T_ - 1) {
+      count_.store(0, std::memory_order_relaxed);
+      gen_.fetch_add(1, std::memory_order_release);
+      return;
+    }
+    for (int spin = 0; gen_.load(std::memory_order_acquire) == g; ++spin)
+      if (spin > 1024) std::this_thread::yield();
+  }
+
+ private:
+  const int T_;
+  std::atomic<int> count_{0};
+  std::atomic<int> gen_{0};
+};
+}  // namespace
+
+// Inverse of a dense SPD matrix by Cholesky: A = L L^T, L^{-1} column by column, then
+// A^{-1} = L^{-T} L^{-1}. Every inner product runs in increasing k; independent rows and
+// columns are spread over host threads and interleaved, which leaves each sum's order alone.
+// The result is exactly symmetric.
 bool spd_inverse(std::vector<double>& A, int n) {
-  // Cholesky A = L L^T (lower, in place)
-  for (int j = 0; j < n; ++j) {
-    double s = A[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) s -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-    if (!(s > 0.0)) return false;
-    double ljj = std::sqrt(s);
-    A[(size_t)j * n + j] = ljj;
-    for (int i = j + 1; i < n; ++i) {
-      double t = A[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) t -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-      A[(size_t)i * n + j] = t / ljj;
+  const int T = host_threads(n);
+  // Cholesky, column j from columns < j (lower triangle, in place). The rows of one column
+  // are formed eight at a time, each with its own running sum; blocks of eight rows go to the
+  // threads in turn, and a barrier ends each column.
+  constexpr int R = 8;
+  std::atomic<bool> spd{true};
+  SpinBarrier bar(T);
+  run_threads(T, [&](int th) {
+    for (int j = 0; j < n; ++j) {
+      const double* Lj = &A[(size_t)j * n];
+      double s = Lj[j];
+      for (int k = 0; k < j; ++k) s -= Lj[k] * Lj[k];
+      if (!(s > 0.0)) {  // every thread sees the same s and leaves at the same column
+        spd.store(false);
+        return;
+      }
+      const double ljj = std::sqrt(s);
+      for (int i = j + 1 + th * R; i < n; i += T * R) {
+        const int m = std::min(R, n - i);
+        double t[R];
+        const double* Li[R];
+        for (int r = 0; r < R; ++r) {
+          Li[r] = &A[(size_t)(i + std::min(r, m - 1)) * n];
+          t[r] = Li[r][j];
+        }
+        for (int k = 0; k < j; ++k) {
+          const double l = Lj[k];
+          for (int r = 0; r < R; ++r) t[r] -= Li[r][k] * l;
+        }
+        for (int r = 0; r < m; ++r) A[(size_t)(i + r) * n + j] = t[r] / ljj;
+      }
+      bar.wait();
+      if (th == 0) A[(size_t)j * n + j] = ljj;  // no thread reads A[j][j] in later columns
     }
-  }
-  // invert L (lower) in place into Linv
-  std::vector<double> Li((size_t)n * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    Li[(size_t)j * n + j] = 1.0 / A[(size_t)j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double t = 0.0;
-      for (int k = j; k < i; ++k) t += A[(size_t)i * n + k] * Li[(size_t)k * n + j];
-      Li[(size_t)i * n + j] = -t / A[(size_t)i * n + i];
+  });
+  if (!spd.load()) return false;
+  // W = L^{-T} stored by rows: W[j][k] = (L^{-1})_{kj}, k >= j; the columns of L^{-1} are
+  // independent of each other
+  std::vector<double> W((size_t)n * n, 0.0);
+  run_threads(T, [&](int th) {
+    for (int j = th; j < n; j += T) {
+      double* Wj = &W[(size_t)j * n];
+      Wj[j] = 1.0 / A[(size_t)j * n + j];
+      for (int i = j + 1; i < n; ++i) {
+        const double* Li = &A[(size_t)i * n];
+        double t = 0.0;
+        for (int k = j; k < i; ++k) t += Li[k] * Wj[k];
+        Wj[i] = -t / Li[i];
+      }
     }
-  }
-  // A^{-1} = L^{-T} L^{-1}
+  });
+  // (A^{-1})_{ij} = sum over k >= i of (L^{-1})_{ki} (L^{-1})_{kj}, for j <= i
+  run_threads(T, [&](int th) {
+    for (int i = th; i < n; i += T) {
+      const double* Wi = &W[(size_t)i * n];
+      for (int j = 0; j <= i; ++j) {
+        const double* Wj = &W[(size_t)j * n];
+        double t = 0.0;
+        for (int k = i; k < n; ++k) t += Wi[k] * Wj[k];
+        A[(size_t)i * n + j] = t;
+      }
+    }
+  });
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double t = 0.0;
-      for (int k = i; k < n; ++k) t += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
-      A[(size_t)i * n + j] = t;
-      A[(size_t)j * n + i] = t;
-    }
+    for (int j = 0; j < i; ++j) A[(size_t)j * n + i] = A[(size_t)i * n + j];
   return true;
 }
 

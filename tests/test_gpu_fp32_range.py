@@ -1,0 +1,83 @@
+"""FP32 preconditioners inside FP64 solves with residuals far outside FP32's range (normal
+numbers from about 1.2e-38 to 3.4e38). The residual is scaled by a power of two to norm about 1
+before the cast and the result scaled back, so a right-hand side times 2^k (k = -140: every
+entry below FP32's smallest subnormal; k = +140: above its largest finite value) gives, on every
+solve path, bitwise 2^k times the iterates of the unscaled solve, where a plain cast would flush
+the residual to zero or overflow it (§3.3 mixed precision: the FP32 V-cycle as a
+preconditioner)."""
+
+import numpy as np
+import pytest
+
+from paper_1402_5938_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+K = (-140, 140)
+
+
+def _problem(dim, ne, p, hier="p", persistent=False, **kw):
+    from paper_1402_5938_amd import gllmg
+    cfg = gllmg.make_config(dim, ne, p, hier, vcycle_prec="f32", **kw)
+    P = gllmg.Problem(cfg, inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0))
+    P.set_persistent(persistent)
+    return P
+
+
+def _rhs(P, seed):
+    import torch
+    f = torch.from_numpy(np.random.default_rng(seed).uniform(-1, 1, P.nnodes(0))).cuda()
+    return P.rhs(f)
+
+
+def _same_scaled(r, x, r0, x0, k):
+    import torch
+    assert r.status == r0.status and r.iters == r0.iters, (k, r.iters, r0.iters)
+    assert r.converged
+    assert r.history == [h * 2.0 ** k for h in r0.history], k
+    assert torch.equal(x, x0 * 2.0 ** k), k
+    assert r.relres_true == r0.relres_true
+
+
+@pytest.mark.parametrize("mode", ["pcg", "mg"])
+@pytest.mark.parametrize("case", [
+    dict(dim=3, ne=(3, 3, 3), p=4),
+    dict(dim=2, ne=(6, 5), p=8),
+    dict(dim=3, ne=(2, 3, 2), p=4, hier="low", low_cycles=2),
+])
+def test_stream_solve_scales_exactly(mode, case):
+    import torch
+    if case.get("hier") == "low" and mode == "mg":
+        pytest.skip("the first-order preconditioner is used by PCG only")
+    P = _problem(**case)
+    b = _rhs(P, 7)
+    x0 = torch.zeros_like(b)
+    r0 = P.solve(b, x0, mode=mode, rtol=1e-10, maxit=200)
+    assert r0.converged
+    for k in K:
+        x = torch.zeros_like(b)
+        _same_scaled(P.solve(b * 2.0 ** k, x, mode=mode, rtol=1e-10, maxit=200), x, r0, x0, k)
+    P.close()
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_batch_solve_scales_exactly(persistent):
+    """Launch groups (problems of one shape in lockstep) and the one-workgroup persistent solver
+    (problems of distinct shapes, each alone)."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    if persistent:
+        probs = [_problem(3, (2, 2, 2), 4, persistent=True), _problem(3, (2, 2, 3), 3, persistent=True)]
+    else:
+        probs = [_problem(3, (3, 2, 2), 4) for _ in range(3)]
+    bs = [_rhs(P, 40 + i) for i, P in enumerate(probs)]
+    xs0 = [torch.zeros_like(b) for b in bs]
+    res0 = gllmg.batch_solve(probs, bs, xs0, rtol=1e-10, maxit=200)
+    for k in K:
+        xs = [torch.zeros_like(b) for b in bs]
+        res = gllmg.batch_solve(probs, [b * 2.0 ** k for b in bs], xs, rtol=1e-10, maxit=200)
+        torch.cuda.synchronize()
+        for r, x, r0, x0 in zip(res, xs, res0, xs0):
+            _same_scaled(r, x, r0, x0, k)
+    for P in probs:
+        P.close()

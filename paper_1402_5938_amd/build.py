@@ -59,6 +59,39 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
     return LIB
 
 
+# The library with AddressSanitizer and UndefinedBehaviorSanitizer on its host side (device
+# code unoptimized: the executable makes no GPU call), linked with a driver of host-side checks
+# into an executable.
+SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+       "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_host_check(driver: str, out_dir: str, jobs: int = 0) -> str:
+    """Compile the host side of every csrc/*.hip file and the driver source `driver` with the
+    sanitizers into out_dir; returns the executable's path."""
+    os.makedirs(out_dir, exist_ok=True)
+    flags = ["-x", "hip", f"--offload-arch={ARCH}", "-O1", "-Xarch_device", "-O0", "-g",
+             "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"] + SAN
+
+    def one(src):
+        obj = os.path.join(out_dir, os.path.basename(src).rsplit(".", 1)[0] + ".o")
+        r = subprocess.run([HIPCC] + flags + ["-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        return obj
+
+    srcs = sources() + [driver]
+    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 16)
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(one, srcs))
+    exe = os.path.join(out_dir, "host_check")
+    r = subprocess.run([HIPCC, f"--offload-arch={ARCH}"] + SAN + ["-o", exe] + objs + ["-lpthread"],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stderr}")
+    return exe
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=0)

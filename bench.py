@@ -131,8 +131,9 @@ def apply_beyond_cache(ne=32, p=8, reps=20):
 
 def cpu_baseline():
     """The oracle's PCG (FP64, assembled factored sparse operator, single thread) on a bounded
-    sample of the same workload: the same warp, coefficient, hierarchy and smoother on 4^3
-    hexes at p = 8 (35,937 nodes); setup excluded as on the GPU side."""
+    sample of the same workload: the same warp, coefficient, hierarchy (orders 8, 4, 2, 1, the
+    exact solve on the first-order level) and smoother on 4^3 hexes at p = 8 (35,937 nodes);
+    setup excluded as on the GPU side."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -140,7 +141,8 @@ def cpu_baseline():
     from paper_1402_5938_amd import inputs
     prob = inputs.warped_var3d(nelem=4, order=8)
     with threadpool_limits(limits=1):
-        H = mg.Hierarchy(3, prob.nelem, prob.order, prob.map, prob.mu, hierarchy="p", nu=4)
+        H = mg.Hierarchy(3, prob.nelem, prob.order, prob.map, prob.mu, hierarchy="p", nu=4,
+                         max_levels=4)
         b = fem.load_vector(H.fine.mesh, fem.nodal_field(H.fine.mesh, prob.f))
         reps = 0
         t0 = time.perf_counter()
@@ -181,7 +183,8 @@ def workload_mixed(a):
     out = {}
     sols = {}
     for prec in ("f64", "f32"):
-        prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0)
+        # order halving 16 -> 1, the exact solve on the first-order level (8^3: 343 unknowns)
+        prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0, max_levels=5)
         G = gllmg.Problem.from_inputs(prob)
         b = G.rhs(torch.from_numpy(prob.nodal_rhs()).cuda())
         t, r, x = _solve_timed(G, b, a.steps, a.warmup, 1e-10, 500)
@@ -194,11 +197,22 @@ def workload_mixed(a):
             sols["tight"] = xt
         G.close()
     u = sols["tight"]
+    # the oracle's tight (rtol 1e-13) FP64 solution at its seeded sample nodes, written by
+    # tests/golden/make_golden.py from the CPU oracle
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests",
+                                       "golden", "warped_8cubed_p16.json")))
+    idx = torch.tensor(gold["sample_nodes"], device="cuda")
+    xo = torch.tensor(gold["x_tight_sample"], dtype=torch.float64, device="cuda")
     for prec in ("f64", "f32"):
         out[prec]["rel_error_vs_fp64_tight"] = float(torch.linalg.norm(sols[prec] - u) /
                                                      torch.linalg.norm(u))
+        xs = sols[prec][idx]
+        out[prec]["rel_error_vs_oracle_samples"] = float(torch.linalg.norm(xs - xo) / torch.linalg.norm(xo))
+        out[prec]["rel_error_vs_oracle_norm2"] = abs(float(torch.linalg.norm(sols[prec])) -
+                                                     gold["x_tight_norm2"]) / gold["x_tight_norm2"]
     out["speedup_mixed_over_fp64"] = out["f64"]["time_to_solution_ms"] / out["f32"]["time_to_solution_ms"]
-    return {"workload": "mixed: 3D warped var 8^3 p=16, N=2146689, PCG to 1e-10", **out}
+    return {"workload": "mixed: 3D warped var 8^3 p=16, N=2146689, p-multigrid 16->8->4->2->1 "
+                        "with the exact solve on 8^3 at p=1, PCG to 1e-10", **out}
 
 
 def workload_batch(a):
@@ -490,6 +504,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--nelem", type=int, default=16)
     ap.add_argument("--order", type=int, default=8)
+    ap.add_argument("--levels", type=int, default=4,
+                    help="levels of the config2 hierarchy (0: order halving, then h-coarsening)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported: the solver and "
@@ -508,10 +524,11 @@ def main():
               "lowprec": workload_lowprec}[a.workload]
         print(json.dumps(fn(a)))
         return
-    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
-    cfg = gllmg.make_config(3, prob.nelem, prob.order, "p", "chebyshev", prob.nu)
+    # the configuration's order sequence 8 -> 4 -> 2 -> 1, the exact solve on the first-order
+    # level (16^3 hexes: 3375 unknowns)
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order, max_levels=a.levels)
     t_setup = time.perf_counter()
-    G = gllmg.Problem(cfg, prob.map, prob.mu)
+    G = gllmg.Problem.from_inputs(prob)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
     N = G.nnodes(0)
@@ -567,8 +584,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"3D warped var-coefficient Poisson, {a.nelem}^3 hexes, p={a.order}, "
-                               f"N={N}; FP64 p-multigrid Chebyshev(4,4) PCG to 1e-10; "
+                               f"N={N}; FP64 p-multigrid "
+                               + "->".join(str(lv.order) for lv in G.levels)
+                               + f" with the exact solve on {a.nelem}^3 at p={G.levels[-1].order} "
+                               f"({G.levels[-1].ninterior} unknowns), Chebyshev(4,4), PCG to 1e-10; "
                                "value = N / time-to-solution",
+                   "levels": G.nlevels,
                    "nodes": N, "pcg_iterations": iters[-1], "time_to_solution_ms": ms,
                    "solves_per_s": 1e3 / ms, "setup_s": t_setup,
                    "apply_gdof_s": N / t_apply / 1e9, "apply_us": t_apply * 1e6},

@@ -226,26 +226,29 @@ __device__ void b_prolong_add(const BatchCtx& c, int lf, const T* xc, T* xf) {
 // ------------------------------------------------------------------ coarse solve, vectors
 template <typename T>
 __device__ __attribute__((noinline)) void b_coarse(const BatchLevel& L, const T* b, T* x) {
+  // the stream path's k_coarse, row by row: each wave forms rows w, w + waves, ..., lane l
+  // summing the terms j = l, l + 64, ... and an xor butterfly adding the lanes (the same
+  // order, so the same values)
   const Grid& g = L.g;
   const T* Ainv = LvlT<T>::Ainv(L);
   const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
   const int mx = nx - 2, my = ny - 2;
   for (int64_t t = threadIdx.x; t < g.N; t += kBT) {
     const int gx = (int)(t % nx), gy = (int)((t / nx) % ny), gz = (int)(t / ((int64_t)nx * ny));
-    if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || gz == 0 || gz == nz - 1) {
-      x[t] = T(0);
-      continue;
-    }
-    const int64_t row = (gx - 1) + (int64_t)mx * ((gy - 1) + (int64_t)my * (gz - 1));
-    const T* a = Ainv + row;  // the symmetric inverse's column `row` (coalesced over lanes)
+    if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || gz == 0 || gz == nz - 1) x[t] = T(0);
+  }
+  auto node_of = [&](int64_t j) {
+    const int64_t q = j / mx;
+    const int jx = (int)(j - q * mx), jy = (int)(q % my), jz = (int)(q / my);
+    return (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (jz + 1));
+  };
+  const int lane = threadIdx.x & 63;
+  for (int64_t row = threadIdx.x >> 6; row < L.nint; row += kBT / 64) {
+    const T* a = Ainv + row * L.nint;
     T acc = T(0);
-    int64_t j = 0;
-    for (int jz = 0; jz < nz - 2; ++jz)
-      for (int jy = 0; jy < my; ++jy) {
-        const T* bl = b + 1 + (int64_t)nx * ((jy + 1) + (int64_t)ny * (jz + 1));
-        for (int jx = 0; jx < mx; ++jx, ++j) acc += a[j * L.nint] * bl[jx];
-      }
-    x[t] = acc;
+    for (int64_t j = lane; j < L.nint; j += 64) acc += a[j] * b[node_of(j)];
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) x[node_of(row)] = acc;
   }
   __syncthreads();
 }

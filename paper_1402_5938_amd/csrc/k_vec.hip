@@ -13,11 +13,19 @@ inline unsigned nb(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 
 // ------------------------------------------------------------------ coarsest level
 // x = A_II^{-1} b on the interior nodes (dense inverse, rows in lexicographic interior order),
-// 0 on the boundary.
+// 0 on the boundary. Blocks [0, nbn) zero the boundary nodes, one node per thread. Each block
+// after them first copies b's interior entries, in row order, into LDS (at most 4096 values);
+// then each of its waves forms one interior row: lane l sums the row's terms j = l, l + 64, ...
+// in increasing j (the lanes read consecutive entries of the row), and an xor butterfly adds
+// the 64 partial sums in a fixed order. The whole chip streams the inverse, however few nodes
+// the level has.
+constexpr int kCT = 512;
+constexpr int kRowsPerBlock = kCT / 64;
+
 template <typename T, bool GR>
-__global__ void __launch_bounds__(kT)
-k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* __restrict__ x,
-         Grid g, Grp gp) {
+__global__ void __launch_bounds__(kCT)
+k_coarse(const T* __restrict__ Ainv, int nint, const T* __restrict__ b, T* __restrict__ x,
+         Grid g, unsigned nbn, Grp gp) {
   if constexpr (GR) {
     int64_t dk;
     if (!grp_begin(gp, &dk)) return;
@@ -25,29 +33,35 @@ k_coarse(const T* __restrict__ Ainv, int64_t nint, const T* __restrict__ b, T* _
     b = shift(b, dk);
     x = shift(x, dk);
   }
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= g.N) return;
+  extern __shared__ char coarse_lds[];
+  T* sb = (T*)coarse_lds;
   const int nx = g.nn[0], ny = g.nn[1], nz = g.nn[2];
-  const int gx = (int)(t % nx), gy = (int)((t / nx) % ny), gz = (int)(t / ((int64_t)nx * ny));
-  bool bnd = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1;
-  if (g.dim == 3) bnd = bnd || gz == 0 || gz == nz - 1;
-  if (bnd) {
-    x[t] = T(0);
+  const bool d3 = g.dim == 3;
+  if (blockIdx.x < nbn) {
+    const int64_t t = (int64_t)blockIdx.x * kCT + threadIdx.x;
+    if (t >= g.N) return;
+    const int gx = (int)(t % nx), gy = (int)((t / nx) % ny), gz = (int)(t / ((int64_t)nx * ny));
+    const bool bnd = gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1 || (d3 && (gz == 0 || gz == nz - 1));
+    if (bnd) x[t] = T(0);
     return;
   }
-  const int mx = nx - 2, my = ny - 2, mz = g.dim == 3 ? nz - 2 : 1;
-  const int64_t row = (gx - 1) + (int64_t)mx * ((gy - 1) + (int64_t)my * (g.dim == 3 ? gz - 1 : 0));
-  // the inverse is exactly symmetric: row `row` is read as column `row`, so the lanes of a wave
-  // (consecutive interior nodes of a line) read consecutive addresses
-  const T* a = Ainv + row;
+  const int mx = nx - 2, my = ny - 2;
+  auto node_of = [&](int j) {
+    const int q = j / mx;
+    const int jx = j - q * mx, jy = q % my, jz = q / my;
+    return (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (d3 ? jz + 1 : 0));
+  };
+  for (int j = threadIdx.x; j < nint; j += kCT) sb[j] = b[node_of(j)];
+  __syncthreads();
+  const int row = (int)(blockIdx.x - nbn) * kRowsPerBlock + (int)(threadIdx.x >> 6);
+  if (row >= nint) return;  // the whole wave
+  const int lane = threadIdx.x & 63;
+  const T* a = Ainv + (int64_t)row * nint;
   T acc = T(0);
-  int64_t j = 0;
-  for (int jz = 0; jz < mz; ++jz)
-    for (int jy = 0; jy < my; ++jy) {
-      const T* bl = b + 1 + (int64_t)nx * ((jy + 1) + (int64_t)ny * (g.dim == 3 ? jz + 1 : 0));
-      for (int jx = 0; jx < mx; ++jx, ++j) acc += a[j * nint] * bl[jx];
-    }
-  x[t] = acc;
+#pragma unroll 8
+  for (int j = lane; j < nint; j += 64) acc += a[j] * sb[j];
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) x[node_of(row)] = acc;
 }
 
 // ------------------------------------------------------------------ elementwise
@@ -356,17 +370,21 @@ __global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, doubl
 
 
 void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s) {
+  GLLMG_CHECK(L.nint <= 4096, GLLMG_EUNSUPPORTED, "coarsest level above 4096 unknowns");
+  const int nint = (int)L.nint;
+  const unsigned nbn = (unsigned)((L.g.N + kCT - 1) / kCT);
+  const dim3 grid(nbn + (unsigned)((nint + kRowsPerBlock - 1) / kRowsPerBlock), grp_count());
   if (prec == 0)
     with_gr([&](auto gr) {
       constexpr bool GR = decltype(gr)::value;
-      hipLaunchKernelGGL((k_coarse<double, GR>), dim3(nb(L.g.N), grp_count()), dim3(kT), 0, s, L.Ainv64, L.nint,
-                       (const double*)b, (double*)x, L.g, cur_grp());
+      hipLaunchKernelGGL((k_coarse<double, GR>), grid, dim3(kCT), sizeof(double) * nint, s, L.Ainv64,
+                         nint, (const double*)b, (double*)x, L.g, nbn, cur_grp());
     });
   else
     with_gr([&](auto gr) {
       constexpr bool GR = decltype(gr)::value;
-      hipLaunchKernelGGL((k_coarse<float, GR>), dim3(nb(L.g.N), grp_count()), dim3(kT), 0, s, L.Ainv32, L.nint,
-                       (const float*)b, (float*)x, L.g, cur_grp());
+      hipLaunchKernelGGL((k_coarse<float, GR>), grid, dim3(kCT), sizeof(float) * nint, s, L.Ainv32,
+                         nint, (const float*)b, (float*)x, L.g, nbn, cur_grp());
     });
   GLLMG_HIP(hipGetLastError());
 }

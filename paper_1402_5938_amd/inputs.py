@@ -151,14 +151,17 @@ def poisson2d_manufactured(nelem=4, order=4) -> Problem:
                    smoother="chebyshev", nu=2, mode="mg", maxit=1000)
 
 
-def warped_var3d(nelem=16, order=8, vcycle_prec="f64", f_seed=None) -> Problem:
+def warped_var3d(nelem=16, order=8, vcycle_prec="f64", f_seed=None, max_levels=0) -> Problem:
     """3D unit cube under the cyclic sine warp (a = 0.05), mu = exp(4.6 sx sy sz), p-multigrid,
-    Chebyshev degree 4, PCG. f = 1, or nodal U[-1,1] from ``f_seed``."""
+    Chebyshev degree 4, PCG. f = 1, or nodal U[-1,1] from ``f_seed``. max_levels = 0: order
+    halving to 1, then h-coarsening; k > 0: the finest k levels, the last solved exactly (at
+    p = 8, k = 4 is the order sequence 8, 4, 2, 1 with the exact solve on the first-order level)."""
     ne = (nelem, nelem, nelem)
-    p = Problem(name=f"3d-var {nelem}^3 p={order}", dim=3, nelem=ne, order=order,
+    p = Problem(name=f"3d-var {nelem}^3 p={order}" + (f" levels={max_levels}" if max_levels else ""),
+                dim=3, nelem=ne, order=order,
                 map=map_warp_sine(0.05), mu=mu_exp_sine_product(4.6),
                 hierarchy="p", smoother="chebyshev", nu=4, mode="pcg",
-                vcycle_prec=vcycle_prec)
+                vcycle_prec=vcycle_prec, max_levels=max_levels)
     if f_seed is None:
         p.f = field_const(1.0)
     else:

@@ -1,6 +1,6 @@
 """Write the full-size expected values in tests/golden/ from the CPU oracle only.
 
-python tests/golden/make_golden.py [config2|config3|batch|serve|all]
+python tests/golden/make_golden.py [config2|config2lit|config3|batch|serve|all]
 
 For the 3D warped variable-coefficient problem at its two full sizes (16^3 hexes at p = 8 and
 8^3 hexes at p = 16, 2,146,689 nodes each), the oracle's FP64 p-multigrid PCG (Chebyshev
@@ -121,6 +121,9 @@ def main():
     which = sys.argv[1] if len(sys.argv) > 1 else "all"
     if which in ("config2", "all"):
         run("warped_16cubed_p8", inputs.warped_var3d(nelem=16, order=8))
+    if which in ("config2lit", "all"):
+        # the order sequence 8, 4, 2, 1 with the exact solve on 16^3 at p = 1 (3375 unknowns)
+        run("warped_16cubed_p8_levels4", inputs.warped_var3d(nelem=16, order=8, max_levels=4))
     if which in ("config3", "all"):
         run("warped_8cubed_p16", inputs.warped_var3d(nelem=8, order=16, f_seed=0), tight=True)
     if which in ("batch", "all"):

@@ -27,6 +27,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 CASES = {
     "warped_16cubed_p8": lambda: inputs.warped_var3d(nelem=16, order=8),
+    # the benchmark's hierarchy: orders 8, 4, 2, 1 with the exact solve on 16^3 at p = 1
+    "warped_16cubed_p8_levels4": lambda: inputs.warped_var3d(nelem=16, order=8, max_levels=4),
     "warped_8cubed_p16": lambda: inputs.warped_var3d(nelem=8, order=16, f_seed=0),
 }
 

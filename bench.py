@@ -461,10 +461,11 @@ def workload_apply(a):
     import torch
 
     from paper_1402_5938_amd import gllmg, inputs
-    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order)
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order, vcycle_prec=a.prec)
     G = gllmg.Problem.from_inputs(prob)
     N = G.nnodes(0)
-    xr = torch.from_numpy(inputs.uniform_nodal(99, N)).cuda()
+    dt = torch.float64 if a.prec == "f64" else torch.float32
+    xr = torch.from_numpy(inputs.uniform_nodal(99, N)).cuda().to(dt)
     y = torch.empty_like(xr)
     for _ in range(5):
         G.apply(xr, y)
@@ -480,9 +481,9 @@ def workload_apply(a):
     for _ in range(3):
         dst.copy_(src)
     torch.cuda.synchronize()
-    nbytes = apply_bytes(3, prob.nelem, prob.order, N, 8)
+    nbytes = apply_bytes(3, prob.nelem, prob.order, N, 8 if a.prec == "f64" else 4)
     G.close()
-    return {"workload": f"apply: 3D warped var {a.nelem}^3 hexes p={a.order}, N={N}, "
+    return {"workload": f"apply: 3D warped var {a.nelem}^3 hexes p={a.order} {a.prec}, N={N}, "
                         f"{a.apply_reps} timed products, then 3 copies of {CALIB_COPY_BYTES} bytes",
             "apply_us": t_apply * 1e6, "algorithmic_bytes": nbytes,
             "achieved_gbs": nbytes / t_apply / 1e9}
@@ -501,6 +502,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--prec", default="f64", choices=["f64", "f32"], help="apply workload: product precision")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--nelem", type=int, default=16)
     ap.add_argument("--order", type=int, default=8)

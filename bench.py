@@ -142,7 +142,7 @@ def cpu_baseline():
     prob = inputs.warped_var3d(nelem=4, order=8)
     with threadpool_limits(limits=1):
         H = mg.Hierarchy(3, prob.nelem, prob.order, prob.map, prob.mu, hierarchy="p", nu=4,
-                         max_levels=4)
+                         coarse_unknowns=inputs.COARSE_UNKNOWNS)
         b = fem.load_vector(H.fine.mesh, fem.nodal_field(H.fine.mesh, prob.f))
         reps = 0
         t0 = time.perf_counter()
@@ -184,7 +184,8 @@ def workload_mixed(a):
     sols = {}
     for prec in ("f64", "f32"):
         # order halving 16 -> 1, the exact solve on the first-order level (8^3: 343 unknowns)
-        prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0, max_levels=5)
+        prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0,
+                                   coarse_unknowns=inputs.COARSE_UNKNOWNS)
         G = gllmg.Problem.from_inputs(prob)
         b = G.rhs(torch.from_numpy(prob.nodal_rhs()).cuda())
         t, r, x = _solve_timed(G, b, a.steps, a.warmup, 1e-10, 500)
@@ -506,8 +507,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--nelem", type=int, default=16)
     ap.add_argument("--order", type=int, default=8)
-    ap.add_argument("--levels", type=int, default=4,
-                    help="levels of the config2 hierarchy (0: order halving, then h-coarsening)")
+    ap.add_argument("--levels", type=int, default=0, help="config2: keep the finest k levels (0: all)")
+    ap.add_argument("--coarse-unknowns", type=int, default=4096,
+                    help="config2: stop at the first first-order level with at most this many "
+                         "interior unknowns (0: coarsen to the bottom)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported: the solver and "
@@ -528,7 +531,8 @@ def main():
         return
     # the configuration's order sequence 8 -> 4 -> 2 -> 1, the exact solve on the first-order
     # level (16^3 hexes: 3375 unknowns)
-    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order, max_levels=a.levels)
+    prob = inputs.warped_var3d(nelem=a.nelem, order=a.order, max_levels=a.levels,
+                               coarse_unknowns=a.coarse_unknowns)
     t_setup = time.perf_counter()
     G = gllmg.Problem.from_inputs(prob)
     torch.cuda.synchronize()

@@ -62,6 +62,12 @@ typedef enum { GLLMG_F64 = 0, GLLMG_F32 = 1 } gllmg_prec;
  * operator A_1 and its V-cycle V_1 (levels 1 and below): an approximation of A_1^{-1} that tends
  * to it as the sweeps grow (the paper applies A_1^{-1} exactly). GLL quadrature only. */
 enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1, GLLMG_HIER_LOW = 2 };
+/* Coarsening rule: halving the elements goes on while every axis has an even count and the
+ * halved level keeps an interior node. With coarse_unknowns = k > 0 it also stops at the first
+ * first-order level (p = 1, reached by any of the hierarchies) that has at most k interior
+ * unknowns: that level is the coarsest and is solved exactly (§3, the coarse-grid direct solve;
+ * on the GPU one exact solve of a few thousand unknowns costs less than the V-cycle launches of
+ * the levels below it). max_levels then truncates the plan. */
 /* Smoothers (§3.2, §4.3, §4.4.3):
  *   JACOBI        nu sweeps x += omega D^{-1} (b - A x)                    (paper: omega = 2/3)
  *   CHEBYSHEV     one degree-nu Chebyshev polynomial in D^{-1} A on [cheb_lo lambda, lambda]
@@ -143,6 +149,7 @@ typedef struct {
   uint64_t eig_seed;      /* seed of the SplitMix64 start vector                           */
   int32_t quadrature;     /* GLLMG_QUAD_GLL (default) or GLLMG_QUAD_GAUSS                  */
   int32_t low_cycles;     /* GLLMG_HIER_LOW: first-order V-cycle sweeps per preconditioning  */
+  int32_t coarse_unknowns;/* 0, or k in [1, 4096]: see the coarsening rule above             */
 } gllmg_config;
 
 typedef struct gllmg_problem gllmg_problem;

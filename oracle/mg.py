@@ -39,9 +39,12 @@ from .splitmix import start_vector
 from .transfer import Transfer
 
 
-def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0):
+def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0, coarse_unknowns=0):
     """List of (nelem, p) from fine to coarse. hierarchy "low": the order-p level, then the
-    first-order level on the same nodes (n_e p cells of order 1 per axis), then h-coarsening."""
+    first-order level on the same nodes (n_e p cells of order 1 per axis), then h-coarsening.
+    Halving goes on while every axis is even and the halved level keeps an interior node; with
+    coarse_unknowns = k > 0 it stops at the first first-order level with at most k interior
+    unknowns, the level then solved exactly (§3)."""
     nelem = tuple(int(v) for v in nelem)
 
     def interior(ne, q):
@@ -60,6 +63,8 @@ def plan_levels(dim, nelem, p, hierarchy="p", max_levels=0):
     elif hierarchy != "h":
         raise ValueError("hierarchy must be 'h', 'p' or 'low'")
     while all(v % 2 == 0 for v in ne) and interior(tuple(v // 2 for v in ne), q) >= 1:
+        if coarse_unknowns and q == 1 and interior(ne, q) <= coarse_unknowns:
+            break
         ne = tuple(v // 2 for v in ne)
         levels.append((ne, q))
     if max_levels and max_levels > 0:
@@ -150,7 +155,7 @@ class Hierarchy:
     def __init__(self, dim, nelem, p, map_desc, mu_desc, hierarchy="p", max_levels=0,
                  smoother="chebyshev", nu=4, omega=None, cheb_lo=0.25, cheb_safety=1.0,
                  eig_steps=10, eig_seed=0, lmax_override=None, direct_transfer=False,
-                 nu_post=None, quadrature="gll", low_cycles=1):
+                 nu_post=None, quadrature="gll", low_cycles=1, coarse_unknowns=0):
         if smoother not in ("jacobi", "chebyshev", "ssor", "l1jacobi", "blockjacobi"):
             raise ValueError(f"unknown smoother {smoother!r}")
         if omega is None:
@@ -159,7 +164,7 @@ class Hierarchy:
         self.nu = self.nu_pre = nu
         self.nu_post = nu if nu_post is None else nu_post
         self.cheb_lo, self.cheb_safety = cheb_lo, cheb_safety
-        self.plan = plan_levels(dim, nelem, p, hierarchy, max_levels)
+        self.plan = plan_levels(dim, nelem, p, hierarchy, max_levels, coarse_unknowns)
         self.levels: List[Level] = []
         if quadrature != "gll" and smoother in ("ssor", "l1jacobi", "blockjacobi"):
             raise ValueError("the Gauss-Seidel, l1 and block smoothers are built for GLL collocation")
@@ -356,7 +361,8 @@ def build_problem(prob, **kw):
     H = Hierarchy(prob.dim, prob.nelem, prob.order, prob.map, prob.mu,
                   hierarchy=prob.hierarchy, max_levels=prob.max_levels,
                   smoother=prob.smoother, nu=prob.nu, nu_post=prob.nu_post,
-                  eig_seed=prob.eig_seed, quadrature=prob.quadrature, **kw)
+                  eig_seed=prob.eig_seed, quadrature=prob.quadrature,
+                  coarse_unknowns=prob.coarse_unknowns, **kw)
     fn = prob.nodal_rhs()
     if fn is None:
         fn = nodal_field(H.fine.mesh, prob.f)

@@ -6,7 +6,9 @@
 #include <cstddef>
 #include <cstring>
 #include <exception>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <thread>
 
 #include "batch_desc.h"
@@ -38,6 +40,8 @@ void validate(const gllmg_config& c) {
               GLLMG_EINVAL, "hierarchy must be GLLMG_HIER_H, GLLMG_HIER_P or GLLMG_HIER_LOW");
   GLLMG_CHECK(c.hierarchy != GLLMG_HIER_LOW || (c.low_cycles >= 1 && c.low_cycles <= 64),
               GLLMG_EINVAL, "low_cycles must be in [1, 64]");
+  GLLMG_CHECK(c.coarse_unknowns >= 0 && c.coarse_unknowns <= 4096, GLLMG_EINVAL,
+              "coarse_unknowns must be in [0, 4096]");
   GLLMG_CHECK(c.hierarchy != GLLMG_HIER_LOW || c.quadrature == GLLMG_QUAD_GLL, GLLMG_EUNSUPPORTED,
               "the first-order hierarchy is built for GLL collocation");
   GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
@@ -91,6 +95,8 @@ std::vector<LevelSpec> plan_levels(const gllmg_config& c) {
     L.push_back(s);
   }
   for (;;) {
+    if (c.coarse_unknowns > 0 && s.p == 1 && interior_count(c.dim, s.ne, s.p) <= c.coarse_unknowns)
+      break;  // the first first-order level small enough for the exact solve
     bool even = true;
     for (int a = 0; a < c.dim; ++a) even = even && (s.ne[a] % 2 == 0);
     if (!even) break;
@@ -1466,18 +1472,84 @@ gllmg_status guard(Fn&& fn) {
 }
 
 // Everything gllmg_setup made besides the host object itself.
+// Host-side resources of one problem: pinned scalar and descriptor images, two private
+// streams, three events. Freeing pinned memory synchronizes the whole device, so problems
+// return them to a per-device pool when destroyed and later setups on that device take them
+// from there: past the first problems of a process, setup and destroy neither allocate host
+// resources nor wait for other work on the device (a server creating and destroying
+// problems while others solve). The pool lives until the process ends.
+struct HostRes {
+  double* hbuf = nullptr;
+  BatchProblem* bhost = nullptr;
+  int* ghact = nullptr;
+  double* ghsc = nullptr;
+  hipStream_t xs = nullptr, cap = nullptr;
+  hipEvent_t ev = nullptr, bev = nullptr, gev = nullptr;
+};
+std::mutex g_host_pool_mu;
+std::map<int, std::vector<HostRes>> g_host_pool;
+
+HostRes take_host_res(int dev) {
+  {
+    std::lock_guard<std::mutex> lk(g_host_pool_mu);
+    std::vector<HostRes>& v = g_host_pool[dev];
+    if (!v.empty()) {
+      HostRes r = v.back();
+      v.pop_back();
+      return r;
+    }
+  }
+  HostRes r;
+  try {
+    GLLMG_HIP(hipHostMalloc((void**)&r.hbuf, sizeof(double) * 64, hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&r.bhost, sizeof(BatchProblem), hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&r.ghact, sizeof(int) * kGroupMax, hipHostMallocDefault));
+    GLLMG_HIP(hipHostMalloc((void**)&r.ghsc, sizeof(double) * 4 * kGroupMax, hipHostMallocDefault));
+    GLLMG_HIP(hipStreamCreateWithFlags(&r.xs, hipStreamNonBlocking));
+    GLLMG_HIP(hipStreamCreateWithFlags(&r.cap, hipStreamNonBlocking));
+    GLLMG_HIP(hipEventCreateWithFlags(&r.ev, hipEventDisableTiming));
+    GLLMG_HIP(hipEventCreateWithFlags(&r.bev, hipEventDisableTiming));
+    GLLMG_HIP(hipEventCreateWithFlags(&r.gev, hipEventDisableTiming));
+  } catch (...) {  // a partly made set is freed at once (setup's own failure path)
+    if (r.cap) (void)hipStreamDestroy(r.cap);
+    if (r.xs) (void)hipStreamDestroy(r.xs);
+    for (hipEvent_t e : {r.ev, r.bev, r.gev})
+      if (e) (void)hipEventDestroy(e);
+    for (void* h : {(void*)r.hbuf, (void*)r.bhost, (void*)r.ghact, (void*)r.ghsc})
+      if (h) (void)hipHostFree(h);
+    throw;
+  }
+  return r;
+}
+
+// Back to the pool once everything of the problem that uses them has finished: its own
+// streams and its last recorded events (a solve's scalar copies into hbuf, a batch's
+// descriptors and group scalars); waits on nothing else.
+void give_host_res(int dev, const HostRes& r) {
+  (void)hipStreamSynchronize(r.xs);
+  (void)hipStreamSynchronize(r.cap);
+  for (hipEvent_t e : {r.ev, r.bev, r.gev}) (void)hipEventSynchronize(e);
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> lk(g_host_pool_mu);
+  g_host_pool[dev].push_back(r);
+}
+
 void release_resources(gllmg_problem* P) {
   drop_graph(P);
-  if (P->cap) (void)hipStreamDestroy(P->cap);
-  if (P->xs) (void)hipStreamDestroy(P->xs);
-  if (P->sv.ev) (void)hipEventDestroy(P->sv.ev);
-  if (P->bev) (void)hipEventDestroy(P->bev);
-  if (P->gev) (void)hipEventDestroy(P->gev);
   if (P->owns_ws) (void)hipFree(P->ws);
-  if (P->hbuf) (void)hipHostFree(P->hbuf);
-  if (P->bhost) (void)hipHostFree(P->bhost);
-  if (P->ghact) (void)hipHostFree(P->ghact);
-  if (P->ghsc) (void)hipHostFree(P->ghsc);
+  if (P->hbuf) {
+    HostRes r;
+    r.hbuf = P->hbuf;
+    r.bhost = P->bhost;
+    r.ghact = P->ghact;
+    r.ghsc = P->ghsc;
+    r.xs = P->xs;
+    r.cap = P->cap;
+    r.ev = P->sv.ev;
+    r.bev = P->bev;
+    r.gev = P->gev;
+    give_host_res(P->dev, r);
+  }
   P->cap = P->xs = nullptr;
   P->sv.ev = P->bev = P->gev = nullptr;
   P->hbuf = nullptr;
@@ -1536,6 +1608,7 @@ void gllmg_config_default(gllmg_config* c) {
   c->eig_seed = 0;
   c->quadrature = GLLMG_QUAD_GLL;
   c->low_cycles = 1;
+  c->coarse_unknowns = 0;
 }
 
 gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* bytes) {
@@ -1594,17 +1667,20 @@ gllmg_status gllmg_setup(const gllmg_config* cfg, const gllmg_field* map, const 
     A.size = P->ws_bytes;
     layout(P.get(), specs, A);
     // every host-side resource of the problem's later calls (pinned images, internal streams,
-    // events) is made here: no later call allocates
-    GLLMG_HIP(hipHostMalloc((void**)&P->hbuf, sizeof(double) * 64, hipHostMallocDefault));
-    GLLMG_HIP(hipHostMalloc((void**)&P->bhost, sizeof(BatchProblem), hipHostMallocDefault));
-    GLLMG_HIP(hipHostMalloc((void**)&P->ghact, sizeof(int) * kGroupMax, hipHostMallocDefault));
-    GLLMG_HIP(hipHostMalloc((void**)&P->ghsc, sizeof(double) * 4 * kGroupMax, hipHostMallocDefault));
-    GLLMG_HIP(hipStreamCreateWithFlags(&P->xs, hipStreamNonBlocking));
-    GLLMG_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
-    GLLMG_HIP(hipEventCreateWithFlags(&P->sv.ev, hipEventDisableTiming));
-    GLLMG_HIP(hipEventCreateWithFlags(&P->bev, hipEventDisableTiming));
-    GLLMG_HIP(hipEventCreateWithFlags(&P->gev, hipEventDisableTiming));
+    // events) is taken here, from the device's pool or newly made: no later call allocates
     GLLMG_HIP(hipGetDevice(&P->dev));
+    {
+      const HostRes r = take_host_res(P->dev);
+      P->hbuf = r.hbuf;
+      P->bhost = r.bhost;
+      P->ghact = r.ghact;
+      P->ghsc = r.ghsc;
+      P->xs = r.xs;
+      P->cap = r.cap;
+      P->sv.ev = r.ev;
+      P->bev = r.bev;
+      P->gev = r.gev;
+    }
     P->sscratch = static_scratch(P->dev);
     setup_impl(P.get(), map, mu, s);
     fill_ctab(P.get(), s);

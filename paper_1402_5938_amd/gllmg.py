@@ -54,7 +54,7 @@ class Config(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("cheb_lo", C.c_double), ("cheb_safety", C.c_double), ("eig_steps", C.c_int32),
                 ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64), ("quadrature", C.c_int32),
-                ("low_cycles", C.c_int32)]
+                ("low_cycles", C.c_int32), ("coarse_unknowns", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -165,7 +165,7 @@ def _callback(fn, is_map):
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
                 vcycle_prec="f64", max_levels=0, omega=None, cheb_lo=0.25,
                 cheb_safety=1.0, eig_steps=10, eig_seed=0, quadrature="gll",
-                low_cycles=1) -> Config:
+                low_cycles=1, coarse_unknowns=0) -> Config:
     c = Config()
     lib().gllmg_config_default(C.byref(c))
     c.dim = dim
@@ -177,6 +177,7 @@ def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu
         raise ValueError(f"unknown hierarchy {hierarchy!r}")
     c.hierarchy = {"h": HIER_H, "p": HIER_P, "low": HIER_LOW}[hierarchy]
     c.low_cycles = low_cycles
+    c.coarse_unknowns = coarse_unknowns
     if smoother not in SMOOTHERS:
         raise ValueError(f"unknown smoother {smoother!r}")
     c.smoother = SMOOTHERS[smoother]
@@ -267,7 +268,7 @@ class Problem:
         cfg = make_config(prob.dim, prob.nelem, prob.order, prob.hierarchy, prob.smoother,
                           prob.nu, nu_post=prob.nu_post, vcycle_prec=prob.vcycle_prec,
                           max_levels=prob.max_levels, eig_seed=prob.eig_seed,
-                          quadrature=prob.quadrature, **kw)
+                          quadrature=prob.quadrature, coarse_unknowns=prob.coarse_unknowns, **kw)
         return cls(cfg, prob.map, prob.mu, stream=stream)
 
     def close(self):

@@ -79,6 +79,16 @@ def mu_cos2_sum(c0: float, c1: float, freq: float) -> dict:
     return {"kind": "cos2_sum", "param": [float(c0), float(c1), float(freq)], "modes": None}
 
 
+# The exact coarse solve takes up to 4096 unknowns; one dense solve of that size costs less on
+# the GPU than the launches of the levels below it. The single large solves of the benchmark
+# stop coarsening at the first first-order level that small. Batched and served problems stop
+# at 512: each request pays the host-side inverse (O(n^3)) and keeps the dense inverse
+# resident (O(n^2) bytes), which at 4096 unknowns would cost a served request seconds of setup
+# and 190 MB of device memory.
+COARSE_UNKNOWNS = 4096
+REQUEST_COARSE_UNKNOWNS = 512
+
+
 @dataclass
 class Problem:
     """One solve: mesh, order, fields, hierarchy and solver settings."""
@@ -101,6 +111,7 @@ class Problem:
     rtol: float = 1e-10
     maxit: int = 500
     max_levels: int = 0
+    coarse_unknowns: int = 0            # > 0: stop at the first first-order level this small
     eig_seed: int = 0
 
     @property
@@ -151,17 +162,21 @@ def poisson2d_manufactured(nelem=4, order=4) -> Problem:
                    smoother="chebyshev", nu=2, mode="mg", maxit=1000)
 
 
-def warped_var3d(nelem=16, order=8, vcycle_prec="f64", f_seed=None, max_levels=0) -> Problem:
+def warped_var3d(nelem=16, order=8, vcycle_prec="f64", f_seed=None, max_levels=0,
+                 coarse_unknowns=0) -> Problem:
     """3D unit cube under the cyclic sine warp (a = 0.05), mu = exp(4.6 sx sy sz), p-multigrid,
-    Chebyshev degree 4, PCG. f = 1, or nodal U[-1,1] from ``f_seed``. max_levels = 0: order
-    halving to 1, then h-coarsening; k > 0: the finest k levels, the last solved exactly (at
-    p = 8, k = 4 is the order sequence 8, 4, 2, 1 with the exact solve on the first-order level)."""
+    Chebyshev degree 4, PCG. f = 1, or nodal U[-1,1] from ``f_seed``. Order halving to 1, then
+    h-coarsening; coarse_unknowns = k > 0 stops at the first first-order level with at most k
+    interior unknowns, max_levels = k > 0 keeps the finest k levels (at p = 8 on 16^3 hexes
+    both k = 4096 and max_levels = 4 give the order sequence 8, 4, 2, 1 with the exact solve on
+    the first-order level)."""
     ne = (nelem, nelem, nelem)
-    p = Problem(name=f"3d-var {nelem}^3 p={order}" + (f" levels={max_levels}" if max_levels else ""),
+    p = Problem(name=f"3d-var {nelem}^3 p={order}" + (f" levels={max_levels}" if max_levels else "")
+                + (f" coarse<={coarse_unknowns}" if coarse_unknowns else ""),
                 dim=3, nelem=ne, order=order,
                 map=map_warp_sine(0.05), mu=mu_exp_sine_product(4.6),
                 hierarchy="p", smoother="chebyshev", nu=4, mode="pcg",
-                vcycle_prec=vcycle_prec, max_levels=max_levels)
+                vcycle_prec=vcycle_prec, max_levels=max_levels, coarse_unknowns=coarse_unknowns)
     if f_seed is None:
         p.f = field_const(1.0)
     else:
@@ -185,9 +200,11 @@ def fourier_modes(rng: np.random.Generator, J: int = 16, dim: int = 3) -> np.nda
 
 
 def batched_problems(seed: int = 0, count: int = 256, nelem: int = 4,
-                     orders=(2, 4, 8, 16)) -> List[Problem]:
+                     orders=(2, 4, 8, 16),
+                     coarse_unknowns: int = REQUEST_COARSE_UNKNOWNS) -> List[Problem]:
     """Independent 3D problems on 4^3 hex meshes, order uniform in ``orders``,
-    mu = exp(random-Fourier field) and f ~ U[-1,1], each from its own spawned seed."""
+    mu = exp(random-Fourier field) and f ~ U[-1,1], each from its own spawned seed; the exact
+    solve on the first first-order level with at most ``coarse_unknowns`` interior unknowns."""
     children = np.random.SeedSequence(seed).spawn(count)
     out = []
     for i, ss in enumerate(children):
@@ -196,7 +213,8 @@ def batched_problems(seed: int = 0, count: int = 256, nelem: int = 4,
         modes = fourier_modes(rng, 16, 3)
         prob = Problem(name=f"batch[{i}] 4^3 p={p}", dim=3, nelem=(nelem,) * 3, order=p,
                        map=map_identity(), mu=mu_exp_fourier(modes), hierarchy="p",
-                       smoother="chebyshev", nu=4, mode="pcg", vcycle_prec="f32")
+                       smoother="chebyshev", nu=4, mode="pcg", vcycle_prec="f32",
+                       coarse_unknowns=coarse_unknowns)
         prob.f_seed = int(rng.integers(0, 2**63 - 1))
         out.append(prob)
     return out
@@ -210,7 +228,8 @@ class Request:
 
 
 def serving_trace(seed: int = 0, rate: float = 200.0, duration_s: float = 60.0,
-                  max_requests: Optional[int] = None) -> List[Request]:
+                  max_requests: Optional[int] = None,
+                  coarse_unknowns: int = REQUEST_COARSE_UNKNOWNS) -> List[Request]:
     """Poisson arrivals (exponential gaps of mean 1/rate) of mixed 2D/3D solves.
     dim in {2,3} equally likely; 2D n_e in {8,...,64}, 3D n_e in {2,...,24}; p in {4,6,8,12,16};
     mu = exp((ln C / 2) prod sin(2 pi (x_i + phi_i))) with C log-uniform in [1e2, 1e4]."""
@@ -234,7 +253,7 @@ def serving_trace(seed: int = 0, rate: float = 200.0, duration_s: float = 60.0,
                        order=p, map=map_identity(),
                        mu=mu_exp_sine_product(math.log(C) / 2.0, tuple(phase[:dim])),
                        hierarchy="p", smoother="chebyshev", nu=4, mode="pcg",
-                       vcycle_prec="f32", rtol=1e-8)
+                       vcycle_prec="f32", rtol=1e-8, coarse_unknowns=coarse_unknowns)
         prob.f_seed = int(rng.integers(0, 2**63 - 1))
         out.append(Request(rid=rid, arrival_s=t, problem=prob))
         rid += 1

@@ -50,7 +50,7 @@ class HbmLedger:
 def request_config(prob: Problem) -> gllmg.Config:
     return gllmg.make_config(prob.dim, prob.nelem, prob.order, prob.hierarchy, prob.smoother,
                              prob.nu, vcycle_prec=prob.vcycle_prec, max_levels=prob.max_levels,
-                             eig_seed=prob.eig_seed)
+                             eig_seed=prob.eig_seed, coarse_unknowns=prob.coarse_unknowns)
 
 
 def request_footprint(prob: Problem) -> int:

@@ -66,17 +66,19 @@ def fp64_close(a, b, scale=None, tol=1e-12, tol_scale=1e-14):
 
 def build_pair(dim, nelem, p, map_desc=None, mu_desc=None, hierarchy="p", smoother="chebyshev",
                nu=4, max_levels=0, vcycle_prec="f64", eig_seed=0, nu_post=None,
-               quadrature="gll", low_cycles=1):
+               quadrature="gll", low_cycles=1, coarse_unknowns=0):
     from paper_1402_5938_amd import gllmg
     map_desc = map_desc or inputs.map_warp_sine(0.05)
     mu_desc = mu_desc or inputs.mu_exp_sine_product(2.0)
     cfg = gllmg.make_config(dim, nelem, p, hierarchy, smoother, nu, nu_post=nu_post,
                             vcycle_prec=vcycle_prec, max_levels=max_levels, eig_seed=eig_seed,
-                            quadrature=quadrature, low_cycles=low_cycles)
+                            quadrature=quadrature, low_cycles=low_cycles,
+                            coarse_unknowns=coarse_unknowns)
     G = gllmg.Problem(cfg, map_desc, mu_desc)
     H = mg.Hierarchy(dim, nelem, p, map_desc, mu_desc, hierarchy=hierarchy, max_levels=max_levels,
                      smoother=smoother, nu=nu, nu_post=nu_post, eig_seed=eig_seed,
-                     quadrature=quadrature, low_cycles=low_cycles)
+                     quadrature=quadrature, low_cycles=low_cycles,
+                     coarse_unknowns=coarse_unknowns)
     return G, H
 
 

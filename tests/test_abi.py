@@ -50,6 +50,24 @@ def test_plan_and_validation_on_host():
     assert gllmg.plan(gllmg.make_config(3, (16,) * 3, 8, "p", max_levels=4))[0] == 4
     # a single level beyond the dense-solve limit is allowed (products and smoothing only)
     assert gllmg.plan(gllmg.make_config(3, (16,) * 3, 8, "p", max_levels=1))[0] == 1
+    for bad_k in (-1, 4097):
+        with pytest.raises(gllmg.GllmgError) as e:
+            gllmg.plan(gllmg.make_config(3, (4,) * 3, 4, "p", coarse_unknowns=bad_k))
+        assert e.value.status == gllmg.EINVAL
+
+
+@pytest.mark.parametrize("dim,ne,p,hier,k,ml", [
+    (3, (16, 16, 16), 8, "p", 4096, 0), (3, (16, 16, 16), 8, "p", 3374, 0), (3, (16, 16, 16), 8, "p", 26, 0),
+    (3, (8, 8, 8), 16, "p", 4096, 0), (3, (4, 4, 4), 16, "p", 4096, 0), (3, (4, 4, 4), 16, "p", 4096, 3),
+    (2, (64, 64), 16, "p", 4096, 0), (2, (16, 16), 4, "h", 4096, 0), (2, (66, 66), 1, "h", 4096, 0),
+    (3, (2, 2, 2), 4, "low", 4096, 0), (3, (4, 4, 2), 6, "low", 100, 0), (2, (24, 40), 3, "p", 50, 0),
+])
+def test_plan_matches_oracle_with_coarse_limit(dim, ne, p, hier, k, ml):
+    """The library's level count equals the oracle's plan under the coarse-unknowns rule."""
+    from paper_1402_5938_amd import gllmg
+    from oracle import mg
+    n = gllmg.plan(gllmg.make_config(dim, ne, p, hier, coarse_unknowns=k, max_levels=ml))[0]
+    assert n == len(mg.plan_levels(dim, ne, p, hier, max_levels=ml, coarse_unknowns=k))
 
 
 def test_null_arguments_rejected():
@@ -86,15 +104,17 @@ def _function_bodies(src):
 
 
 def test_no_allocation_after_setup():
-    """Device or pinned memory, streams and events are made only by gllmg_setup; the V-cycle
-    graph is instantiated only by the capture helper (called at setup, by gllmg_set_lmax and
-    by gllmg_set_graphs). So gllmg_plan's footprint is exact and a batch allocates nothing."""
+    """Device memory is allocated only by gllmg_setup; pinned memory, streams and events only by
+    the host-resource pool's take_host_res, which only gllmg_setup calls (gllmg_destroy gives
+    them back to the pool); the V-cycle graph is instantiated only by the capture helper
+    (called at setup, by gllmg_set_lmax and by gllmg_set_graphs). So gllmg_plan's footprint is
+    exact and a batch allocates nothing."""
     csrc = os.path.join(ROOT, "paper_1402_5938_amd", "csrc")
-    allowed = {"hipMalloc": {"gllmg_setup"}, "hipHostMalloc": {"gllmg_setup"},
+    allowed = {"hipMalloc": {"gllmg_setup"}, "hipHostMalloc": {"take_host_res"},
                "hipExtMallocWithFlags": set(), "hipMallocAsync": set(), "hipMallocManaged": set(),
-               "hipStreamCreateWithFlags": {"gllmg_setup"}, "hipStreamCreate": set(),
-               "hipEventCreateWithFlags": {"gllmg_setup"}, "hipEventCreate": set(),
-               "hipGraphInstantiate": {"capture_vcycle"}}
+               "hipStreamCreateWithFlags": {"take_host_res"}, "hipStreamCreate": set(),
+               "hipEventCreateWithFlags": {"take_host_res"}, "hipEventCreate": set(),
+               "hipGraphInstantiate": {"capture_vcycle"}, "take_host_res": {"gllmg_setup"}}
     found = {}
     for fn in sorted(os.listdir(csrc)):
         if not fn.endswith((".hip", ".h")):
@@ -109,6 +129,8 @@ def test_no_allocation_after_setup():
                     start = src.find(body)
                     if start <= m.start() < start + len(body):
                         owner = name
+                if owner is None and re.match(r"%s\s*\([^;{]*\)\s*\{" % call, src[m.start():]):
+                    continue  # the function's own definition
                 found.setdefault(call, set()).add(owner)
     for call, owners in found.items():
         assert owners <= allowed[call], (call, owners)

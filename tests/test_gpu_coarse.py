@@ -52,3 +52,29 @@ def test_one_level_exact_solve(dim, ne, p, quad):
     Ax = to_np(G.apply(to_dev(x)))
     assert rel_err(Ax * m.interior, r) <= 1e-10
     G.close()
+
+
+@pytest.mark.parametrize("dim,ne,p,hier,k", [
+    (3, (4, 4, 4), 4, "p", 64),      # 4^3 at p = 4, 2, 1: the exact solve on 27 unknowns
+    (2, (16, 16), 2, "p", 300),      # 16^2 at p = 2, 1: 225 unknowns
+    (3, (2, 2, 2), 4, "low", 4096),  # the order-4 level and its first-order level, solved exactly
+    (3, (4, 4, 4), 2, "h", 4096),    # order 2 throughout: no level is cut
+])
+def test_coarse_unknowns_rule_against_oracle(dim, ne, p, hier, k):
+    """Stopping at the first first-order level with at most k interior unknowns: the same plan,
+    V-cycle (1e-10) and PCG iteration counts as the oracle."""
+    from oracle import mg
+    G, H = build_pair(dim, ne, p, hierarchy=hier, coarse_unknowns=k)
+    assert [[list(lv.nelem)[:dim], lv.order] for lv in G.levels] == \
+        [[list(n), q] for n, q in H.plan]
+    m = H.fine.mesh
+    b = random_vec(m.N, 13) * m.interior
+    if hier != "low":
+        for l, lv in enumerate(H.levels[:-1]):
+            G.set_lmax(l, lv.lmax)
+        assert rel_err(to_np(G.vcycle(to_dev(b))), H.vcycle(b)) <= 1e-10
+    ro = mg.pcg(H, b, rtol=1e-10)
+    rg = G.solve(to_dev(b), rtol=1e-10)
+    assert rg.converged and rg.iters == ro.iters, (rg.iters, ro.iters)
+    assert rel_err(rg.history, ro.history) <= 1e-9
+    G.close()

@@ -426,6 +426,23 @@ def test_plan_levels():
     assert mg.plan_levels(3, (16,) * 3, 8, "p", max_levels=4)[-1] == ((16,) * 3, 1)
 
 
+def test_plan_levels_coarse_unknowns():
+    """Halving stops at the first first-order level with at most k interior unknowns."""
+    full = mg.plan_levels(3, (16,) * 3, 8, "p")
+    assert mg.plan_levels(3, (16,) * 3, 8, "p", coarse_unknowns=4096) == full[:4]   # 15^3 = 3375
+    assert mg.plan_levels(3, (16,) * 3, 8, "p", coarse_unknowns=3375) == full[:4]
+    assert mg.plan_levels(3, (16,) * 3, 8, "p", coarse_unknowns=3374) == full[:5]   # 7^3 = 343
+    assert mg.plan_levels(3, (16,) * 3, 8, "p", coarse_unknowns=26) == full         # 1^3 at 2^3
+    assert mg.plan_levels(3, (16,) * 3, 8, "p", coarse_unknowns=1) == full
+    assert mg.plan_levels(3, (8,) * 3, 16, "p", coarse_unknowns=4096)[-1] == ((8,) * 3, 1)
+    # levels of order > 1 are never cut short: the h-hierarchy at p = 4 keeps every level
+    assert mg.plan_levels(2, (16, 16), 4, "h", coarse_unknowns=4096) == mg.plan_levels(2, (16, 16), 4, "h")
+    # the first-order hierarchy: its first first-order level (on the order-p nodes) when small
+    assert mg.plan_levels(3, (2, 2, 2), 4, "low", coarse_unknowns=4096) == [((2,) * 3, 4), ((8,) * 3, 1)]
+    assert mg.plan_levels(2, (64, 64), 16, "p", coarse_unknowns=4096)[-1] == ((64, 64), 1)  # 63^2
+    assert mg.plan_levels(2, (66, 66), 1, "h", coarse_unknowns=4096)[-1] == ((33, 33), 1)
+
+
 # ---------------------------------------------------------------------------- smoothers
 def _gen_eig(dim=2, ne=2, p=3):
     H = mg.Hierarchy(dim, (ne,) * dim, p, inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0),

@@ -122,27 +122,29 @@ static void check_plans() {
         for (int hier : {GLLMG_HIER_H, GLLMG_HIER_P, GLLMG_HIER_LOW})
           for (int sm = GLLMG_SMOOTH_JACOBI; sm <= GLLMG_SMOOTH_BLOCK_JACOBI; ++sm)
             for (int quad : {GLLMG_QUAD_GLL, GLLMG_QUAD_GAUSS})
-              for (int ml : {0, 1, 3}) {
-                if (dim == 3 && ne == 8 && p > 8) continue;  // plan sizes only; keep it quick
-                gllmg_config c = base(dim, ne, p);
-                c.hierarchy = hier;
-                c.smoother = sm;
-                c.quadrature = quad;
-                c.max_levels = ml;
-                c.vcycle_prec = (p + ne) % 2 ? GLLMG_F32 : GLLMG_F64;
-                int32_t nl = -1;
-                size_t bytes = 0;
-                const gllmg_status st = gllmg_plan(&c, &nl, &bytes);
-                if (st == GLLMG_OK) {
-                  ++ok;
-                  EXPECT(nl >= 1 && bytes > 0);
-                  if (ml > 0) EXPECT(nl <= ml);
-                } else {
-                  ++rejected;
-                  EXPECT(st == GLLMG_EINVAL || st == GLLMG_EUNSUPPORTED);  // combinations not built
-                  EXPECT(std::strlen(gllmg_last_error()) > 0);
+              for (int ml : {0, 1, 3})
+                for (int cu : {0, 512}) {
+                  if (dim == 3 && ne == 8 && p > 8) continue;  // plan sizes only; keep it quick
+                  gllmg_config c = base(dim, ne, p);
+                  c.hierarchy = hier;
+                  c.smoother = sm;
+                  c.quadrature = quad;
+                  c.max_levels = ml;
+                  c.coarse_unknowns = cu;
+                  c.vcycle_prec = (p + ne) % 2 ? GLLMG_F32 : GLLMG_F64;
+                  int32_t nl = -1;
+                  size_t bytes = 0;
+                  const gllmg_status st = gllmg_plan(&c, &nl, &bytes);
+                  if (st == GLLMG_OK) {
+                    ++ok;
+                    EXPECT(nl >= 1 && bytes > 0);
+                    if (ml > 0) EXPECT(nl <= ml);
+                  } else {
+                    ++rejected;
+                    EXPECT(st == GLLMG_EINVAL || st == GLLMG_EUNSUPPORTED);  // combinations not built
+                    EXPECT(std::strlen(gllmg_last_error()) > 0);
+                  }
                 }
-              }
   EXPECT(ok > 1000 && rejected > 0);
   // invalid configurations, each with its own error
   gllmg_config c = base(3, 2, 4);
@@ -167,9 +169,18 @@ static void check_plans() {
   c.hierarchy = GLLMG_HIER_LOW;
   c.low_cycles = 0;
   EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
-  // the literal reading of the 16^3 p = 8 hierarchy: four levels down to 16^3 at p = 1
+  c = base(3, 2, 4);
+  c.coarse_unknowns = -1;
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
+  c.coarse_unknowns = 4097;
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
+  // the literal reading of the 16^3 p = 8 hierarchy: four levels down to 16^3 at p = 1, by
+  // truncation or by the coarse-unknowns limit
   c = base(3, 16, 8);
   c.max_levels = 4;
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_OK && nl == 4);
+  c = base(3, 16, 8);
+  c.coarse_unknowns = 4096;
   EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_OK && nl == 4);
 }
 

@@ -6,12 +6,16 @@ thread builds each admitted request's hierarchy, which then stays resident in HB
 solve finishes. The serving loop keeps every active solve moving iteration by iteration
 (gllmg_solve_begin / _poll / _end): requests that arrive while others are on the GPU join as
 soon as memory and a slot are free, and their iterations overlap on the device's queues.
-Nothing here computes any part of the method: every step runs in libgllmg.
+Requests of one shape that are ready at the same moment are solved together as a launch group
+(gllmg_batch_solve on a worker thread: every kernel launched once for all of them, each result
+bit for bit the one it gets alone), the others one by one. Nothing here computes any part of
+the method: every step runs in libgllmg.
 """
 
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
 import queue
 import threading
@@ -53,6 +57,14 @@ def request_config(prob: Problem) -> gllmg.Config:
                              eig_seed=prob.eig_seed, coarse_unknowns=prob.coarse_unknowns)
 
 
+def shape_key(prob: Problem):
+    """Requests with equal keys can share a launch group: the same level plan, smoother and
+    precision (coefficients, maps and right-hand sides may differ) and the same stopping rule."""
+    return (prob.dim, tuple(prob.nelem), prob.order, prob.hierarchy, prob.smoother, prob.nu,
+            prob.nu_post, prob.quadrature, prob.vcycle_prec, prob.max_levels,
+            prob.coarse_unknowns, prob.mode, prob.rtol, prob.maxit)
+
+
 def request_footprint(prob: Problem) -> int:
     """Device bytes of one request: the library workspace plus f, b and x (FP64)."""
     _, ws = gllmg.plan(request_config(prob))
@@ -71,6 +83,7 @@ class Record:
     started: float = float("nan")
     finished: float = float("nan")
     iters: int = -1
+    grouped: int = 1        # requests in the launch group that solved this one (1: alone)
     converged: bool = False
     relres_true: float = float("nan")
     status: int = -1
@@ -83,9 +96,14 @@ class Record:
 
 class Server:
     def __init__(self, hbm_budget: int, max_active: int = 64, nstreams: int = 8,
-                 keep_solutions: bool = False, setup_threads: int = 6, host_rhs: bool = False):
+                 keep_solutions: bool = False, setup_threads: int = 6, host_rhs: bool = False,
+                 group_requests: bool = True, group_threads: int = 2,
+                 group_window_s: float = 0.002):
         """host_rhs: a request's nodal f is drawn on the host (numpy, the same values as
-        Problem.nodal_rhs) and uploaded, instead of drawn on the device."""
+        Problem.nodal_rhs) and uploaded, instead of drawn on the device. group_requests: solve
+        same-shape requests that are ready together as launch groups (group_threads worker
+        threads drive them); a ready request whose shape has other requests still in setup
+        waits for them up to group_window_s."""
         import torch
         self.host_rhs = host_rhs
         self.ledger = HbmLedger(hbm_budget)
@@ -101,6 +119,10 @@ class Server:
         for t in self._setup_threads:
             t.start()
         self._t0 = 0.0
+        self.group_requests = group_requests
+        self.group_window_s = group_window_s
+        self._groups = concurrent.futures.ThreadPoolExecutor(max_workers=group_threads)
+        self._group_streams = [torch.cuda.Stream() for _ in range(group_threads)]
 
     def now(self) -> float:
         return time.perf_counter() - self._t0
@@ -134,6 +156,19 @@ class Server:
                 rec.error = str(e)
                 self._ready.put((req, rec, None, None, None))
 
+    def _solve_group(self, items, k):
+        """One launch group: every request of `items` (same shape) in one gllmg_batch_solve on
+        group stream k."""
+        import torch
+        s = self._group_streams[k % len(self._group_streams)]
+        probs = [it[2] for it in items]
+        req0 = items[0][0]
+        with torch.cuda.stream(s):
+            res = gllmg.batch_solve(probs, [it[3] for it in items], [it[4] for it in items],
+                                    rtol=req0.problem.rtol, maxit=req0.problem.maxit, stream=s)
+        s.synchronize()
+        return res
+
     # ----------------------------------------------------------------- serving loop
     def run(self, trace: List[Request], time_scale: float = 1.0,
             max_wall_s: Optional[float] = None) -> dict:
@@ -142,6 +177,12 @@ class Server:
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival_s))
         waiting: collections.deque = collections.deque()
         active = []  # (req, rec, P, b, x, async)
+        groups = []  # (items, future)
+        in_groups = 0
+        ngroup = 0
+        held = collections.OrderedDict()  # shape -> ready requests waiting for partners
+        held_since = {}
+        setup_keys = collections.Counter()  # shapes of the requests in setup
         in_setup = 0
         rr = 0
         self._t0 = time.perf_counter()
@@ -149,7 +190,7 @@ class Server:
             self.records[req.rid] = Record(req.rid, req.problem.name, req.problem.nnodes,
                                            request_footprint(req.problem),
                                            req.arrival_s * time_scale)
-        while pending or waiting or active or in_setup:
+        while pending or waiting or active or groups or held or in_setup:
             now = self.now()
             if max_wall_s is not None and now > max_wall_s:
                 break
@@ -157,7 +198,7 @@ class Server:
             while pending and pending[0].arrival_s * time_scale <= now:
                 waiting.append(pending.popleft())
             # FIFO admission by footprint and slots
-            while waiting and len(active) + in_setup < self.max_active:
+            while waiting and len(active) + in_groups + in_setup + sum(map(len, held.values())) < self.max_active:
                 req = waiting[0]
                 rec = self.records[req.rid]
                 if rec.footprint > self.ledger.budget:
@@ -170,25 +211,75 @@ class Server:
                 waiting.popleft()
                 rec.admitted = now
                 in_setup += 1
+                setup_keys[shape_key(req.problem)] += 1
                 self._todo.put((req, rec))
                 progressed = True
-            # hierarchies that finished setting up start solving
+            # hierarchies that finished setting up start solving: same-shape requests ready
+            # together as one launch group, the others alone
             while True:
                 try:
                     req, rec, P, b, x = self._ready.get_nowait()
                 except queue.Empty:
                     break
                 in_setup -= 1
+                setup_keys[shape_key(req.problem)] -= 1
                 progressed = True
                 if P is None:
                     rec.finished = self.now()
                     self.ledger.release(rec.footprint)
                     continue
+                key = shape_key(req.problem) if self.group_requests and req.problem.mode == "pcg" \
+                    else ("alone", req.rid)
+                held.setdefault(key, []).append((req, rec, P, b, x))
+                held_since.setdefault(key, self.now())
+            ready = []
+            for key in list(held):
+                if setup_keys.get(key, 0) > 0 and self.now() - held_since[key] < self.group_window_s:
+                    continue  # partners of this shape are still in setup
+                ready.append(held.pop(key))
+                del held_since[key]
+            for items in ready:
+                if len(items) >= 2:
+                    t = self.now()
+                    for it in items:
+                        it[1].started = t
+                        it[1].grouped = len(items)
+                    groups.append((items, self._groups.submit(self._solve_group, items, ngroup)))
+                    ngroup += 1
+                    in_groups += len(items)
+                    continue
+                req, rec, P, b, x = items[0]
                 st = self.streams[rr % len(self.streams)]  # setup already synchronized
                 rr += 1
                 a = P.solve_async(b, x, rtol=req.problem.rtol, maxit=req.problem.maxit, stream=st)
                 rec.started = self.now()
                 active.append((req, rec, P, b, x, a))
+            # launch groups that have finished
+            still_g = []
+            for items, fut in groups:
+                if not fut.done():
+                    still_g.append((items, fut))
+                    continue
+                t = self.now()
+                try:
+                    results = fut.result()
+                    err = ""
+                except Exception as e:  # reported per request
+                    results, err = [None] * len(items), str(e)
+                for (req, rec, P, b, x), res in zip(items, results):
+                    rec.finished = t
+                    if res is not None:
+                        rec.iters, rec.converged = res.iters, res.converged
+                        rec.relres_true, rec.status = res.relres_true, res.status
+                    else:
+                        rec.error = err
+                    if self.keep:
+                        self.solutions[req.rid] = x.clone()
+                    P.close()
+                    self.ledger.release(rec.footprint)
+                in_groups -= len(items)
+                progressed = True
+            groups = still_g
             # advance every active solve without blocking
             still = []
             for item in active:
@@ -216,6 +307,7 @@ class Server:
             self._todo.put(None)
         for t in self._setup_threads:
             t.join(timeout=60)
+        self._groups.shutdown(wait=True)
 
     def report(self) -> dict:
         done = [r for r in self.records.values() if r.converged and np.isfinite(r.finished)]
@@ -233,6 +325,7 @@ class Server:
             "mean_admission_wait_s": float(np.nanmean([r.admitted - r.arrival for r in done])) if done else float("nan"),
             "mean_setup_s": float(np.nanmean([r.ready - r.admitted for r in done])) if done else float("nan"),
             "mean_solve_s": float(np.nanmean([r.finished - r.started for r in done])) if done else float("nan"),
+            "grouped_requests": sum(1 for r in done if r.grouped > 1),
             "hbm_budget": self.ledger.budget, "hbm_peak_reserved": self.ledger.peak,
             "span_s": span,
         }

@@ -662,7 +662,9 @@ __device__ inline int axis_cands(int c, int p, int ne, int* ce, int* cl) {
 // Sum over the elements containing node (gx, gy, gz) of F[e][local index of the node], in the
 // order z, y, x with the lower element first. Along y and z the candidates are the same for a
 // whole grid row, so those branches are uniform where a wave covers one row; along x a missing
-// second candidate re-reads the first (all loads are issued before the sum).
+// second candidate re-reads the first (all loads are issued before the sum). Offsets into F
+// are 32-bit (the launchers require E n^d < 2^32): 64-bit index arithmetic made the kernel
+// bound by its integer instructions.
 template <int N, int DIM, typename T>
 __device__ __forceinline__ T gather_sum(const T* __restrict__ F, const Grid& g, int gx, int gy,
                                         int gz) {
@@ -677,12 +679,13 @@ __device__ __forceinline__ T gather_sum(const T* __restrict__ F, const Grid& g, 
 #pragma unroll
     for (int ky = 0; ky < 2; ++ky)
       if (kz < cz && ky < cy) {
-        const int64_t eyz = (int64_t)g.ne[0] * (cey[ky] + (int64_t)g.ne[1] * cez[kz]);
-        const int lyz = N * (cly[ky] + N * clz[kz]);
+        const uint32_t eyz =
+            (uint32_t)g.ne[0] * ((uint32_t)cey[ky] + (uint32_t)g.ne[1] * (uint32_t)cez[kz]);
+        const uint32_t lyz = (uint32_t)(N * (cly[ky] + N * clz[kz]));
 #pragma unroll
         for (int kx = 0; kx < 2; ++kx) {
           const int ax = kx < cx ? kx : 0;
-          v[kz][ky][kx] = F[(cex[ax] + eyz) * NL + clx[ax] + lyz];
+          v[kz][ky][kx] = F[((uint32_t)cex[ax] + eyz) * (uint32_t)NL + ((uint32_t)clx[ax] + lyz)];
         }
       }
   T acc = T(0);
@@ -719,9 +722,9 @@ template <int N, int DIM, typename T>
 __device__ __forceinline__ void gather_node(const T* __restrict__ F, const T* __restrict__ xin,
                                             const Grid& g, int neumann, const EpiT<T>& ep,
                                             uint32_t t) {
-  const uint32_t row = t / (uint32_t)g.nn[0];
+  const uint32_t row = div_by_recip(t, (uint32_t)g.nn[0], g.rnn[0]);
   const int gx = (int)(t - row * (uint32_t)g.nn[0]);
-  const int gz = DIM == 3 ? (int)(row / (uint32_t)g.nn[1]) : 0;
+  const int gz = DIM == 3 ? (int)div_by_recip(row, (uint32_t)g.nn[1], g.rnn[1]) : 0;
   const int gy = DIM == 3 ? (int)(row - (uint32_t)gz * (uint32_t)g.nn[1]) : (int)row;
   gather_at<N, DIM, T>(F, xin, g, neumann, ep, (int64_t)t, gx, gy, gz);
 }

@@ -60,7 +60,21 @@ struct Grid {
   int nn[3];         // nodes per axis = ne * p + 1 (nn[2] = 1 in 2D)
   int64_t E;         // elements
   int64_t N;         // nodes
+  double rnn[2];     // 1 / nn[0], 1 / nn[1] (node index -> grid row -> plane without integer division)
 };
+
+// floor(n / d) for n < 2^32, 0 < d < 2^30, with r = 1.0 / d: the FP64 product is within one of
+// the quotient (its rounding error is below 2^32 * 2^-52), and one step corrects it.
+__host__ __device__ inline uint32_t div_by_recip(uint32_t n, uint32_t d, double r) {
+  uint32_t q = (uint32_t)((double)n * r);
+  int32_t rem = (int32_t)(n - q * d);
+  if (rem < 0) {
+    --q;
+    rem += (int32_t)d;
+  }
+  if (rem >= (int32_t)d) ++q;
+  return q;
+}
 
 // Transfer from a level to the next coarser one: the 1D matrix Pl[child][i][c] (child < nch;
 // nch = 1 under p-coarsening, 2 under h-coarsening) evaluating coarse element basis function c

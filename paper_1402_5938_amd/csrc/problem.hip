@@ -122,6 +122,8 @@ Grid make_grid(int dim, const LevelSpec& s) {
     g.E *= g.ne[a];
     g.N *= g.nn[a];
   }
+  g.rnn[0] = 1.0 / g.nn[0];
+  g.rnn[1] = 1.0 / g.nn[1];
   return g;
 }
 

@@ -158,41 +158,49 @@ def cpu_baseline():
                       f"{reps} solves in {el:.1f} s, setup excluded"}
 
 
-def _solve_timed(G, b, steps, warmup, rtol, maxit):
+def _solve_timed(G, b, steps, warmup, rtol, maxit, mode="pcg"):
     import torch
     x = torch.zeros_like(b)
     for _ in range(warmup):
         x.zero_()
-        G.solve(b, x, rtol=rtol, maxit=maxit)
+        G.solve(b, x, mode=mode, rtol=rtol, maxit=maxit)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         x.zero_()
-        r = G.solve(b, x, rtol=rtol, maxit=maxit)
+        r = G.solve(b, x, mode=mode, rtol=rtol, maxit=maxit)
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, r, x
 
 
+IR_INNER = 12   # FP32 CG steps per refinement step of the iterative-refinement mode
+
+
 def workload_mixed(a):
     """Mixed precision on the 3D warped problem with 8^3 hexes at p = 16 (2,146,689 nodes),
-    f ~ U[-1,1] (seed 0): FP32 V-cycle inside FP64 PCG versus the all-FP64 solve, both to
-    1e-10; the FP32 solution's error is measured against a tight (1e-13) FP64 solve."""
+    f ~ U[-1,1] (seed 0), all to 1e-10: the all-FP64 PCG, the FP32 V-cycle inside FP64 PCG, and
+    iterative refinement (FP64 residuals, IR_INNER steps of FP32 CG with the FP32 V-cycle per
+    refinement step). Errors against a tight (1e-13) FP64 solve on the GPU and against the
+    oracle's tight solution at its sample nodes."""
     import torch
 
     from paper_1402_5938_amd import gllmg, inputs
     out = {}
     sols = {}
-    for prec in ("f64", "f32"):
+    for name, prec, mode in (("f64", "f64", "pcg"), ("f32", "f32", "pcg"), ("f32_ir", "f32", "ir")):
         # order halving 16 -> 1, the exact solve on the first-order level (8^3: 343 unknowns)
         prob = inputs.warped_var3d(nelem=8, order=16, vcycle_prec=prec, f_seed=0,
                                    coarse_unknowns=inputs.COARSE_UNKNOWNS)
-        G = gllmg.Problem.from_inputs(prob)
+        G = gllmg.Problem.from_inputs(prob, ir_inner=IR_INNER if mode == "ir" else 0)
         b = G.rhs(torch.from_numpy(prob.nodal_rhs()).cuda())
-        t, r, x = _solve_timed(G, b, a.steps, a.warmup, 1e-10, 500)
-        out[prec] = {"time_to_solution_ms": t * 1e3, "pcg_iterations": r.iters,
+        t, r, x = _solve_timed(G, b, a.steps, a.warmup, 1e-10, 500, mode)
+        out[name] = {"time_to_solution_ms": t * 1e3, "pcg_iterations": r.iters,
                      "relres_true": r.relres_true}
-        sols[prec] = x.clone()
-        if prec == "f64":
+        if mode == "ir":
+            out[name]["refinement_steps"] = len(r.history) - 1
+            out[name]["inner_cg_steps_per_refinement"] = IR_INNER
+        sols[name] = x.clone()
+        if name == "f64":
             xt = torch.zeros_like(b)
             G.solve(b, xt, rtol=1e-13, maxit=500)
             sols["tight"] = xt
@@ -204,16 +212,17 @@ def workload_mixed(a):
                                        "golden", "warped_8cubed_p16.json")))
     idx = torch.tensor(gold["sample_nodes"], device="cuda")
     xo = torch.tensor(gold["x_tight_sample"], dtype=torch.float64, device="cuda")
-    for prec in ("f64", "f32"):
-        out[prec]["rel_error_vs_fp64_tight"] = float(torch.linalg.norm(sols[prec] - u) /
+    for name in ("f64", "f32", "f32_ir"):
+        out[name]["rel_error_vs_fp64_tight"] = float(torch.linalg.norm(sols[name] - u) /
                                                      torch.linalg.norm(u))
-        xs = sols[prec][idx]
-        out[prec]["rel_error_vs_oracle_samples"] = float(torch.linalg.norm(xs - xo) / torch.linalg.norm(xo))
-        out[prec]["rel_error_vs_oracle_norm2"] = abs(float(torch.linalg.norm(sols[prec])) -
+        xs = sols[name][idx]
+        out[name]["rel_error_vs_oracle_samples"] = float(torch.linalg.norm(xs - xo) / torch.linalg.norm(xo))
+        out[name]["rel_error_vs_oracle_norm2"] = abs(float(torch.linalg.norm(sols[name])) -
                                                      gold["x_tight_norm2"]) / gold["x_tight_norm2"]
     out["speedup_mixed_over_fp64"] = out["f64"]["time_to_solution_ms"] / out["f32"]["time_to_solution_ms"]
+    out["speedup_ir_over_fp64"] = out["f64"]["time_to_solution_ms"] / out["f32_ir"]["time_to_solution_ms"]
     return {"workload": "mixed: 3D warped var 8^3 p=16, N=2146689, p-multigrid 16->8->4->2->1 "
-                        "with the exact solve on 8^3 at p=1, PCG to 1e-10", **out}
+                        "with the exact solve on 8^3 at p=1, to 1e-10", **out}
 
 
 def workload_batch(a):

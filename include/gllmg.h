@@ -83,7 +83,7 @@ enum { GLLMG_HIER_H = 0, GLLMG_HIER_P = 1, GLLMG_HIER_LOW = 2 };
  *                 (paper: omega = 2/3). */
 enum { GLLMG_SMOOTH_JACOBI = 0, GLLMG_SMOOTH_CHEBYSHEV = 1, GLLMG_SMOOTH_SSOR = 2,
        GLLMG_SMOOTH_L1_JACOBI = 3, GLLMG_SMOOTH_BLOCK_JACOBI = 4 };
-enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1 };
+enum { GLLMG_MODE_PCG = 0, GLLMG_MODE_MG = 1, GLLMG_MODE_IR = 2 };
 /* Quadrature (§2.3): GLL collocation (the nodes are the (p+1)^d quadrature points: diagonal mass,
  * the stiffness couples a node with the coordinate planes through it) or the paper's Gauss rule
  * with p+1 Gauss-Legendre points per axis (geometry and mu at the Gauss points, dense element
@@ -150,6 +150,7 @@ typedef struct {
   int32_t quadrature;     /* GLLMG_QUAD_GLL (default) or GLLMG_QUAD_GAUSS                  */
   int32_t low_cycles;     /* GLLMG_HIER_LOW: first-order V-cycle sweeps per preconditioning  */
   int32_t coarse_unknowns;/* 0, or k in [1, 4096]: see the coarsening rule above             */
+  int32_t ir_inner;       /* 0, or k in [1, 100]: GLLMG_MODE_IR's FP32 CG steps per refinement */
 } gllmg_config;
 
 typedef struct gllmg_problem gllmg_problem;
@@ -278,7 +279,14 @@ gllmg_status gllmg_vcycle(const gllmg_problem* prob, gllmg_prec prec, const void
  * when ||r|| <= rtol ||r_0|| (§4.3). b, x: FP64 device vectors; x is the initial guess on
  * entry. stats may be NULL. Synchronous. ENOTCONV: maxit reached (x = last iterate, stats
  * filled). EBREAKDOWN: non-finite residual or p^T A p <= 0. EUNSUPPORTED: the coarsest level
- * has more than 4096 interior nodes, so no exact coarse solve was set up. */
+ * has more than 4096 interior nodes, so no exact coarse solve was set up.
+ * GLLMG_MODE_IR (problems set up with vcycle_prec = GLLMG_F32 and ir_inner = k > 0): iterative
+ * refinement. Each step forms r = b - A x in FP64, scales it by a power of two to norm about 1,
+ * runs k steps of CG in FP32 on A e = r from e = 0 (FP32 products, FP32 V-cycle as the
+ * preconditioner, FP32 vector updates, FP64 dot products), and adds e, scaled back, to x in
+ * FP64; it stops when the FP64 residual meets rtol. stats: iters counts the inner CG steps (one
+ * V-cycle each; maxit bounds them), history holds ||b - A x|| after every refinement step,
+ * relres = relres_true. gllmg_solve only (solve_begin and batch solves: EUNSUPPORTED). */
 gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* b, double* x,
                          double rtol, int32_t maxit, gllmg_solve_stats* stats, void* stream);
 

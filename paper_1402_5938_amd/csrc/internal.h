@@ -360,6 +360,14 @@ void vec_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y, 
 // dst[k cnt + i] = scal[i] (src = the first problem's scalars) for every active problem k of
 // the current launch group (dst is not shifted: one buffer for the group)
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s);
+// iterative refinement: e += a p, r -= a h with a = scal[num] / scal[den] (FP32 vectors);
+// p = z + b p with b = scal[num] / scal[den]; x += e times the power of two that undoes the
+// scaling of the residual whose (r, r) is *rr
+void ir_update_er(int64_t n, const double* scal, int i_num, int i_den, float* e, float* r,
+                  const float* p, const float* h, hipStream_t s);
+void ir_update_p(int64_t n, const double* scal, int i_num, int i_den, float* p, const float* z,
+                 hipStream_t s);
+void ir_add(int64_t n, const float* e, const double* rr, double* x, hipStream_t s);
 void pcg_update_p(int64_t n, const double* scal, int i_num, int i_den, double* p,
                   const double* z, hipStream_t s);
 void start_vector(const Grid& g, uint64_t seed, int level, double* v, hipStream_t s);

@@ -366,8 +366,52 @@ __global__ void k_pcg_p(int64_t n, const double* scal, int inum, int iden, doubl
   p[i] = z[i] + be * p[i];
 }
 
+// Inner FP32 CG of the iterative refinement. alpha = scal[num] / scal[den] (FP64 dots of the
+// FP32 vectors), applied in FP32: e += alpha p; r -= alpha h.
+__global__ void __launch_bounds__(kT) k_ir_er(int64_t n, const double* scal, int inum, int iden,
+                                              float* e, float* r, const float* p, const float* h) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const float al = (float)(scal[inum] / scal[iden]);
+  e[i] = e[i] + al * p[i];
+  r[i] = r[i] - al * h[i];
+}
+// beta = scal[num] / scal[den]; p = z + beta p (FP32 vectors)
+__global__ void __launch_bounds__(kT) k_ir_p(int64_t n, const double* scal, int inum, int iden,
+                                             float* p, const float* z) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const float be = (float)(scal[inum] / scal[iden]);
+  p[i] = z[i] + be * p[i];
+}
+// x += e 2^k: the correction of the scaled residual back at the residual's scale (the power of
+// two pow2_inv_norm(*rr) that scaled it), added in FP64
+__global__ void __launch_bounds__(kT) k_ir_add(int64_t n, const float* e, const double* rr, double* x) {
+  const int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+  if (i >= n) return;
+  const double sc = 1.0 / pow2_inv_norm(*rr);
+  x[i] = x[i] + (double)e[i] * sc;
+}
+
 }  // namespace
 
+void ir_update_er(int64_t n, const double* scal, int inum, int iden, float* e, float* r,
+                  const float* p, const float* h, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_ir_er, dim3(nb(n)), dim3(kT), 0, s, n, scal, inum, iden, e, r, p, h);
+  GLLMG_HIP(hipGetLastError());
+}
+void ir_update_p(int64_t n, const double* scal, int inum, int iden, float* p, const float* z,
+                 hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_ir_p, dim3(nb(n)), dim3(kT), 0, s, n, scal, inum, iden, p, z);
+  GLLMG_HIP(hipGetLastError());
+}
+void ir_add(int64_t n, const float* e, const double* rr, double* x, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_ir_add, dim3(nb(n)), dim3(kT), 0, s, n, e, rr, x);
+  GLLMG_HIP(hipGetLastError());
+}
 
 void launch_coarse_solve(const Level& L, int prec, const void* b, void* x, hipStream_t s) {
   GLLMG_CHECK(L.nint <= 4096, GLLMG_EUNSUPPORTED, "coarsest level above 4096 unknowns");

@@ -42,6 +42,9 @@ void validate(const gllmg_config& c) {
               GLLMG_EINVAL, "low_cycles must be in [1, 64]");
   GLLMG_CHECK(c.coarse_unknowns >= 0 && c.coarse_unknowns <= 4096, GLLMG_EINVAL,
               "coarse_unknowns must be in [0, 4096]");
+  GLLMG_CHECK(c.ir_inner >= 0 && c.ir_inner <= 100, GLLMG_EINVAL, "ir_inner must be in [0, 100]");
+  GLLMG_CHECK(c.ir_inner == 0 || c.vcycle_prec == GLLMG_F32, GLLMG_EINVAL,
+              "iterative refinement (ir_inner > 0) runs the FP32 V-cycle: vcycle_prec must be F32");
   GLLMG_CHECK(c.hierarchy != GLLMG_HIER_LOW || c.quadrature == GLLMG_QUAD_GLL, GLLMG_EUNSUPPORTED,
               "the first-order hierarchy is built for GLL collocation");
   GLLMG_CHECK(c.smoother == GLLMG_SMOOTH_JACOBI || c.smoother == GLLMG_SMOOTH_CHEBYSHEV ||
@@ -163,6 +166,7 @@ struct gllmg_problem {
   double* pp = nullptr;
   double* ph = nullptr;
   double* pt = nullptr;
+  float* ir32 = nullptr;     // iterative refinement: FP32 r, z, p, h, e (N0 each), or null
   char* scratch = nullptr;   // start of the region shared by setup temporaries and solve vectors
   size_t scratch_bytes = 0;
   double* hbuf = nullptr;    // pinned host scalars
@@ -296,6 +300,8 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
   P->pp = (double*)A.take(sizeof(double) * N0);
   P->ph = (double*)A.take(sizeof(double) * N0);
   P->pt = (double*)A.take(sizeof(double) * N0);
+  // iterative refinement's FP32 r, z, p, h, e
+  if (P->cfg.ir_inner > 0 && P->cfg.vcycle_prec == GLLMG_F32) P->ir32 = (float*)A.take(sizeof(float) * 5 * N0);
   for (auto& L : P->L) {
     const int64_t N = L.g.N;
     for (int pr = 0; pr < (f32 ? 2 : 1); ++pr) {
@@ -924,8 +930,9 @@ void precond_level0(gllmg_problem* P, int pr, const void* r, void* z, hipStream_
     vcycle_level(P, 0, pr, r, z, s);
 }
 
-// device scalars of a solve in P->scal: (r, r), (p, A p), the two (z, r), (b - A x, b - A x)
-enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4 };
+// device scalars of a solve in P->scal: (r, r), (p, A p), the two (z, r), (b - A x, b - A x);
+// the inner CG of the iterative refinement: its two (z, r) and (p, A p)
+enum { S_RR = 0, S_PH = 1, S_G0 = 2, S_G1 = 3, S_B = 4, S_IG0 = 10, S_IG1 = 11, S_IPH = 12 };
 
 // z = V r for the solve's FP64 residual r = P->pr, with (r, r) in scal[S_RR], into z on the
 // finest level, in the problem's V-cycle precision. An FP32 preconditioner sees r scaled by a
@@ -1187,8 +1194,81 @@ gllmg_status solve_end(gllmg_problem* P, gllmg_solve_stats* st) {
   return GLLMG_OK;
 }
 
+// Iterative refinement (GLLMG_MODE_IR): FP64 residuals outside, cfg.ir_inner steps of FP32 CG
+// preconditioned by the FP32 V-cycle inside, on the residual scaled by a power of two; the inner
+// steps run on the device without host round trips (their scalars stay in P->scal), one
+// read-back per refinement step.
+gllmg_status ir_solve(gllmg_problem* P, const double* b, double* x, double rtol, int maxit,
+                      gllmg_solve_stats* st, hipStream_t s) {
+  GLLMG_CHECK(P->ir32 != nullptr, GLLMG_EUNSUPPORTED,
+              "iterative refinement needs ir_inner > 0 and the FP32 V-cycle at setup");
+  GLLMG_CHECK(!P->sv.active, GLLMG_EINVAL, "a solve is already in progress on this problem");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<int64_t> a0;
+  for (auto& L : P->L) a0.push_back(L.applies);
+  const int64_t N = P->L[0].g.N;
+  float* r32 = P->ir32;
+  float* z32 = r32 + N;
+  float* p32 = z32 + N;
+  float* h32 = p32 + N;
+  float* e32 = h32 + N;
+  auto residual_norm = [&]() {
+    residual(P, 0, 0, b, x, P->pr, s);
+    dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, s);
+    GLLMG_HIP(hipMemcpyAsync(P->hbuf, P->scal + S_RR, sizeof(double), hipMemcpyDeviceToHost, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+    return std::sqrt(P->hbuf[0]);
+  };
+  const double n0 = residual_norm();
+  std::vector<double> hist{n0};
+  double nr = n0;
+  int iters = 0;
+  bool conv = n0 == 0.0, breakdown = !std::isfinite(n0);
+  while (!conv && !breakdown && iters < maxit) {
+    const int m = std::min(P->cfg.ir_inner, maxit - iters);
+    cast_64_32(N, P->pr, r32, s, P->scal + S_RR);
+    vec_zero(1, N, e32, s);
+    precond_level0(P, 1, r32, z32, s);
+    dot(1, N, z32, r32, P->part, P->scal + S_IG0, s);
+    vec_copy(1, N, z32, p32, s);
+    int g = S_IG0;
+    for (int it = 0; it < m; ++it) {
+      apply_level(P, 0, 1, 0, p32, h32, s);
+      dot(1, N, p32, h32, P->part, P->scal + S_IPH, s);
+      ir_update_er(N, P->scal, g, S_IPH, e32, r32, p32, h32, s);
+      if (it + 1 == m) break;
+      precond_level0(P, 1, r32, z32, s);
+      const int gn = g == S_IG0 ? S_IG1 : S_IG0;
+      dot(1, N, z32, r32, P->part, P->scal + gn, s);
+      ir_update_p(N, P->scal, gn, g, p32, z32, s);
+      g = gn;
+    }
+    iters += m;
+    ir_add(N, e32, P->scal + S_RR, x, s);  // S_RR still holds the scaled residual's (r, r)
+    nr = residual_norm();
+    hist.push_back(nr);
+    breakdown = !std::isfinite(nr);
+    conv = !breakdown && nr <= rtol * n0;
+  }
+  if (st) {
+    st->iters = iters;
+    st->converged = conv ? 1 : 0;
+    st->relres = n0 > 0.0 ? nr / n0 : 0.0;
+    st->relres_true = st->relres;
+    for (int i = 0; i < 16; ++i) st->applies[i] = 0;
+    for (size_t i = 0; i < P->L.size() && i < 16; ++i) st->applies[i] = P->L[i].applies - a0[i];
+    if (st->history)
+      for (size_t i = 0; i < hist.size() && i <= (size_t)maxit; ++i) st->history[i] = hist[i];
+    st->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (breakdown) throw Error(GLLMG_EBREAKDOWN, "breakdown: non-finite residual");
+  if (!conv) return GLLMG_ENOTCONV;
+  return GLLMG_OK;
+}
+
 gllmg_status solve_impl(gllmg_problem* P, int mode, const double* b, double* x, double rtol,
                         int maxit, gllmg_solve_stats* st, hipStream_t s) {
+  if (mode == GLLMG_MODE_IR) return ir_solve(P, b, x, rtol, maxit, st, s);
   solve_begin(P, mode, b, x, rtol, maxit, s);
   return solve_end(P, st);
 }
@@ -1611,6 +1691,7 @@ void gllmg_config_default(gllmg_config* c) {
   c->quadrature = GLLMG_QUAD_GLL;
   c->low_cycles = 1;
   c->coarse_unknowns = 0;
+  c->ir_inner = 0;
 }
 
 gllmg_status gllmg_plan(const gllmg_config* cfg, int32_t* nlevels, size_t* bytes) {
@@ -1932,7 +2013,8 @@ gllmg_status gllmg_solve(const gllmg_problem* P, int32_t mode, const double* b, 
                          double rtol, int32_t maxit, gllmg_solve_stats* st, void* stream) {
   return guard([&]() {
     level_of(P, 0);
-    GLLMG_CHECK(mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG, GLLMG_EINVAL, "unknown mode");
+    GLLMG_CHECK(mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG || mode == GLLMG_MODE_IR,
+                GLLMG_EINVAL, "unknown mode");
     check_ptr(b, 8, "b");
     check_ptr(x, 8, "x");
     GLLMG_CHECK(rtol > 0.0 && maxit >= 1, GLLMG_EINVAL, "rtol must be > 0 and maxit >= 1");
@@ -1949,6 +2031,8 @@ gllmg_status gllmg_solve_begin(gllmg_problem* P, int32_t mode, const double* b, 
                                double rtol, int32_t maxit, void* stream) {
   return guard([&]() {
     level_of(P, 0);
+    GLLMG_CHECK(mode != GLLMG_MODE_IR, GLLMG_EUNSUPPORTED,
+                "iterative refinement runs through gllmg_solve only");
     GLLMG_CHECK(mode == GLLMG_MODE_PCG || mode == GLLMG_MODE_MG, GLLMG_EINVAL, "unknown mode");
     check_ptr(b, 8, "b");
     check_ptr(x, 8, "x");

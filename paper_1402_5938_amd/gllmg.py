@@ -23,7 +23,8 @@ HIER_H, HIER_P, HIER_LOW = 0, 1, 2
 SMOOTH_JACOBI, SMOOTH_CHEBYSHEV, SMOOTH_SSOR, SMOOTH_L1_JACOBI, SMOOTH_BLOCK_JACOBI = 0, 1, 2, 3, 4
 SMOOTHERS = {"jacobi": SMOOTH_JACOBI, "chebyshev": SMOOTH_CHEBYSHEV, "ssor": SMOOTH_SSOR,
              "l1jacobi": SMOOTH_L1_JACOBI, "blockjacobi": SMOOTH_BLOCK_JACOBI}
-MODE_PCG, MODE_MG = 0, 1
+MODE_PCG, MODE_MG, MODE_IR = 0, 1, 2
+MODES = {"pcg": MODE_PCG, "mg": MODE_MG, "ir": MODE_IR}
 
 KINDS = {"identity": 0, "warp_sine": 1, "affine": 2, "map_callback": 3, "const": 10,
          "exp_sine_product": 11, "exp_fourier": 12, "sin_product": 13, "cos2_sum": 14,
@@ -54,7 +55,7 @@ class Config(C.Structure):
                 ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("cheb_lo", C.c_double), ("cheb_safety", C.c_double), ("eig_steps", C.c_int32),
                 ("vcycle_prec", C.c_int32), ("eig_seed", C.c_uint64), ("quadrature", C.c_int32),
-                ("low_cycles", C.c_int32), ("coarse_unknowns", C.c_int32)]
+                ("low_cycles", C.c_int32), ("coarse_unknowns", C.c_int32), ("ir_inner", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -165,7 +166,7 @@ def _callback(fn, is_map):
 def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu_post=None,
                 vcycle_prec="f64", max_levels=0, omega=None, cheb_lo=0.25,
                 cheb_safety=1.0, eig_steps=10, eig_seed=0, quadrature="gll",
-                low_cycles=1, coarse_unknowns=0) -> Config:
+                low_cycles=1, coarse_unknowns=0, ir_inner=0) -> Config:
     c = Config()
     lib().gllmg_config_default(C.byref(c))
     c.dim = dim
@@ -178,6 +179,7 @@ def make_config(dim, nelem, order, hierarchy="p", smoother="chebyshev", nu=4, nu
     c.hierarchy = {"h": HIER_H, "p": HIER_P, "low": HIER_LOW}[hierarchy]
     c.low_cycles = low_cycles
     c.coarse_unknowns = coarse_unknowns
+    c.ir_inner = ir_inner
     if smoother not in SMOOTHERS:
         raise ValueError(f"unknown smoother {smoother!r}")
     c.smoother = SMOOTHERS[smoother]
@@ -381,12 +383,16 @@ class Problem:
         hist = (C.c_double * (maxit + 1))()
         st = SolveStats()
         st.history = C.cast(hist, C.POINTER(C.c_double))
-        m = MODE_PCG if mode == "pcg" else MODE_MG
+        m = MODES[mode]
         status = lib().gllmg_solve(self.h, m, _ptr(b), _ptr(x), float(rtol), int(maxit),
                                    C.byref(st), _stream(stream))
         if status not in (OK, ENOTCONV) or (status == ENOTCONV and raise_on_notconv):
             _check(status)
-        return _result(status, st, hist, self.nlevels)
+        res = _result(status, st, hist, self.nlevels)
+        if m == MODE_IR:  # one residual norm per refinement step of cfg.ir_inner CG steps
+            k = max(1, self.cfg.ir_inner)
+            res.history = list(hist[:(st.iters + k - 1) // k + 1])
+        return res
 
     def solve_async(self, b, x, mode="pcg", rtol=1e-10, maxit=500, stream=None) -> AsyncSolve:
         return AsyncSolve(self, b, x, mode, rtol, maxit, stream)
@@ -398,7 +404,7 @@ class AsyncSolve:
     def __init__(self, prob: "Problem", b, x, mode="pcg", rtol=1e-10, maxit=500, stream=None):
         self.prob, self.b, self.x, self.maxit = prob, b, x, maxit
         self.hist = (C.c_double * (maxit + 1))()
-        m = MODE_PCG if mode == "pcg" else MODE_MG
+        m = MODES[mode]
         _check(lib().gllmg_solve_begin(prob.h, m, _ptr(b), _ptr(x), float(rtol), int(maxit),
                                        _stream(stream)))
         self.result = None
@@ -440,7 +446,7 @@ def batch_solve(problems, bs, xs, mode="pcg", rtol=1e-10, maxit=500, stream=None
     for i in range(n):
         stats[i].history = C.cast(hists[i], C.POINTER(C.c_double))
     status = (C.c_int * n)()
-    m = MODE_PCG if mode == "pcg" else MODE_MG
+    m = MODES[mode]
     st = lib().gllmg_batch_solve(P, B, X, n, m, float(rtol), int(maxit), stats, status,
                                  _stream(stream))
     if st not in (OK, ENOTCONV):

@@ -170,6 +170,13 @@ static void check_plans() {
   c.low_cycles = 0;
   EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
   c = base(3, 2, 4);
+  c.ir_inner = 4;  // refinement needs the FP32 V-cycle
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
+  c.vcycle_prec = GLLMG_F32;
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_OK);
+  c.ir_inner = 101;
+  EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
+  c = base(3, 2, 4);
   c.coarse_unknowns = -1;
   EXPECT(gllmg_plan(&c, &nl, &bytes) == GLLMG_EINVAL);
   c.coarse_unknowns = 4097;

@@ -39,7 +39,7 @@ def _same_scaled(r, x, r0, x0, k):
     assert r.relres_true == r0.relres_true
 
 
-@pytest.mark.parametrize("mode", ["pcg", "mg"])
+@pytest.mark.parametrize("mode", ["pcg", "mg", "ir"])
 @pytest.mark.parametrize("case", [
     dict(dim=3, ne=(3, 3, 3), p=4),
     dict(dim=2, ne=(6, 5), p=8),
@@ -49,6 +49,8 @@ def test_stream_solve_scales_exactly(mode, case):
     import torch
     if case.get("hier") == "low" and mode == "mg":
         pytest.skip("the first-order preconditioner is used by PCG only")
+    if mode == "ir":
+        case = dict(case, ir_inner=5)
     P = _problem(**case)
     b = _rhs(P, 7)
     x0 = torch.zeros_like(b)

@@ -65,6 +65,57 @@ __device__ inline double b_sum(double v, double* red) {
   return s;
 }
 
+// The stream path's order of the solve's FP64 reductions (k_dot_partial and k_pcg_xr, then
+// k_sum_final): dot_grid(n) blocks of kDotThreads threads, thread t of block v adding the
+// terms of entries v kDotThreads + t + m g kDotThreads in increasing m, each block's values
+// added by the LDS tree of block_sum, then the block sums added the same way by one block. The
+// workgroup runs two such blocks at a time (its halves), so that every scalar of the solve, and
+// so every iterate, equals the stream path's bit for bit. term(i) gives entry i's term (and may
+// update vectors at i: each entry is visited once). sh: kBT doubles; part: dot_grid(n) doubles.
+constexpr int kHalves = kBT / kDotThreads;
+static_assert(kBT % kDotThreads == 0, "the workgroup emulates whole reduction blocks");
+static_assert((kBatchMaxNodes + kDotThreads - 1) / kDotThreads <= 64, "partials fit the LDS array");
+
+__device__ inline void s_tree(double* sh) {  // each half: sh[h..h+255] -> sh[h]
+  const int h = threadIdx.x / kDotThreads * kDotThreads, t = threadIdx.x % kDotThreads;
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if (t < w) sh[h + t] += sh[h + t + w];
+    __syncthreads();
+  }
+}
+
+template <class Term>
+__device__ double s_reduce(int64_t n, double* sh, double* part, Term term) {
+  const int g = dot_grid(n);
+  const int t = threadIdx.x % kDotThreads;
+  for (int v0 = 0; v0 < g; v0 += kHalves) {
+    const int v = v0 + (int)threadIdx.x / kDotThreads;
+    double acc = 0.0;
+    if (v < g)
+      for (int64_t i = (int64_t)v * kDotThreads + t; i < n; i += (int64_t)g * kDotThreads)
+        acc += term(i);
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    s_tree(sh);
+    if (t == 0 && v < g) part[v] = sh[threadIdx.x];
+    __syncthreads();
+  }
+  double acc = 0.0;
+  if ((int)threadIdx.x < kDotThreads)
+    for (int i = t; i < g; i += kDotThreads) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  s_tree(sh);
+  const double s = sh[0];
+  __syncthreads();
+  return s;
+}
+
+template <typename T>
+__device__ double s_dot(const T* a, const T* b, int64_t n, double* sh, double* part) {
+  return s_reduce(n, sh, part, [&](int64_t i) { return (double)a[i] * (double)b[i]; });
+}
+
 template <typename T>
 __device__ double b_dot(const T* a, const T* b, int64_t n, double* red) {
   double acc = 0.0;
@@ -412,8 +463,8 @@ __device__ void b_precond(const BatchCtx& c, const double* r, double* z, double 
 
 // ------------------------------------------------------------------ the solve
 template <int N0, typename T>
-__device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL,
-                        long long* sApp) {
+__device__ void b_solve(BatchProblem* Pg, char* lds, double* red, double* sh, double* spart,
+                        BatchLevel* sL, long long* sApp) {
   const int nl = Pg->nlev;
   for (int i = threadIdx.x; i < nl * (int)sizeof(BatchLevel) / 4; i += kBT)
     ((int*)sL)[i] = ((const int*)Pg->L)[i];
@@ -433,7 +484,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
     rs.r = r;
     b_apply0<N0>(c, x, rs);
   }
-  const double n0 = sqrt(b_dot<double>(r, r, N, red));
+  const double n0 = sqrt(s_dot<double>(r, r, N, sh, spart));
   if (threadIdx.x == 0) Pg->hist[0] = n0;
   int iters = 0, status = 1;
   double nr = n0;
@@ -443,7 +494,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
     double g = 0.0;
     if (mode == GLLMG_MODE_PCG) {
       b_precond<N0, T>(c, r, z, n0);
-      g = b_dot<double>(z, r, N, red);
+      g = s_dot<double>(z, r, N, sh, spart);
       for (int64_t i = threadIdx.x; i < N; i += kBT) p[i] = z[i];
       __syncthreads();
     }
@@ -453,16 +504,14 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
         Epi st;
         st.y = h;
         b_apply0<N0>(c, p, st);
-        ph = b_dot<double>(p, h, N, red);
+        ph = s_dot<double>(p, h, N, sh, spart);
         const double al = g / ph;
-        double acc = 0.0;
-        for (int64_t i = threadIdx.x; i < N; i += kBT) {
+        nr = sqrt(s_reduce(N, sh, spart, [&](int64_t i) {
           x[i] = x[i] + al * p[i];
           const double ri = r[i] - al * h[i];
           r[i] = ri;
-          acc += ri * ri;
-        }
-        nr = sqrt(b_sum(acc, red));
+          return ri * ri;
+        }));
       } else {
         b_precond<N0, T>(c, r, z, nr);
         for (int64_t i = threadIdx.x; i < N; i += kBT) x[i] = x[i] + z[i];
@@ -472,7 +521,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
         rs.b = b;
         rs.r = r;
         b_apply0<N0>(c, x, rs);
-        nr = sqrt(b_dot<double>(r, r, N, red));
+        nr = sqrt(s_dot<double>(r, r, N, sh, spart));
       }
       ++iters;
       if (threadIdx.x == 0 && iters < kBatchHist) Pg->hist[iters] = nr;
@@ -487,7 +536,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
       if (iters >= maxit) break;
       if (mode == GLLMG_MODE_PCG) {
         b_precond<N0, T>(c, r, z, nr);
-        const double gn = b_dot<double>(z, r, N, red);
+        const double gn = s_dot<double>(z, r, N, sh, spart);
         const double be = gn / g;
         for (int64_t i = threadIdx.x; i < N; i += kBT) p[i] = z[i] + be * p[i];
         __syncthreads();
@@ -502,7 +551,7 @@ __device__ void b_solve(BatchProblem* Pg, char* lds, double* red, BatchLevel* sL
     rs.b = b;
     rs.r = t;
     b_apply0<N0>(c, x, rs);
-    rt = sqrt(b_dot<double>(t, t, N, red)) / n0;
+    rt = sqrt(s_dot<double>(t, t, N, sh, spart)) / n0;
   }
   if (threadIdx.x == 0) {
     Pg->iters = iters;
@@ -522,9 +571,11 @@ template <int N0>
 __global__ void __launch_bounds__(kBatchThreads) k_batch(BatchArgs a) {
   __shared__ double lds[kBatchLdsBytes / 8];
   __shared__ double red[kBatchThreads / 64];
+  __shared__ double sh[kBatchThreads];
+  __shared__ double spart[64];
   __shared__ BatchLevel sL[kBatchMaxLevels];
   __shared__ long long sApp[kBatchMaxLevels];
-  b_solve<N0, float>(a.p[blockIdx.x], (char*)lds, red, sL, sApp);
+  b_solve<N0, float>(a.p[blockIdx.x], (char*)lds, red, sh, spart, sL, sApp);
 }
 
 }  // namespace gllmg

@@ -344,6 +344,13 @@ void jacobi_step(int prec, int64_t n, int x_from_zero, void* x, const void* b, c
                  const void* dinv, double omega, hipStream_t s);
 // deterministic dot products (FP64 result written to a device scalar)
 constexpr int kDotBlocks = 1024;
+constexpr int kDotThreads = 256;  // threads of the dot-product and CG-update blocks
+// blocks of the dot products and CG updates for vectors of n entries (a function of n alone, so
+// that every reduction over such a vector adds its entries in one fixed order)
+__host__ __device__ inline int dot_grid(int64_t n) {
+  const int64_t g = (n + kDotThreads - 1) / kDotThreads;
+  return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
+}
 void dot(int prec, int64_t n, const void* a, const void* b, double* partials, double* result,
          hipStream_t s);
 // scalar(s) in device memory for the PCG iteration

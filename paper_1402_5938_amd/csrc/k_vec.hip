@@ -8,7 +8,7 @@ namespace gllmg {
 
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = kDotThreads;  // 256
 inline unsigned nb(int64_t n) { return (unsigned)((n + kT - 1) / kT); }
 
 // ------------------------------------------------------------------ coarsest level
@@ -249,10 +249,6 @@ __global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, do
   if (threadIdx.x == 0) *out = s;
 }
 
-inline int dot_grid(int64_t n) {
-  int64_t g = (n + kT - 1) / kT;
-  return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
-}
 
 // ------------------------------------------------------------------ Lanczos building blocks
 // Block-Gram-Schmidt against the basis V_0..V_{c-1} (columns of V with leading dimension ld):

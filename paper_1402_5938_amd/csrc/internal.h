@@ -351,11 +351,13 @@ __host__ __device__ inline int dot_grid(int64_t n) {
   const int64_t g = (n + kDotThreads - 1) / kDotThreads;
   return (int)(g < kDotBlocks ? (g < 1 ? 1 : g) : kDotBlocks);
 }
+// hresult: also into this pinned host scalar (or nullptr; ignored in launch groups)
 void dot(int prec, int64_t n, const void* a, const void* b, double* partials, double* result,
-         hipStream_t s);
+         hipStream_t s, double* hresult = nullptr);
 // scalar(s) in device memory for the PCG iteration
 void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* x, double* r,
-                   const double* p, const double* h, double* partials, double* rr, hipStream_t s);
+                   const double* p, const double* h, double* partials, double* rr, hipStream_t s,
+                   double* hrr = nullptr);
 // Lanczos: w -= V (V^T w) against the c basis vectors V_v = V + v ld (one classical
 // Gram-Schmidt pass: all coefficients from the same w, fixed-order sums). part holds
 // c kMdBlocks doubles, coef c.

@@ -235,18 +235,25 @@ __global__ void __launch_bounds__(kT) k_dot_partial(int64_t n, const T* a, const
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// *out = the sum of the np partials; also to the pinned host scalar *hout if given (single
+// problems only: it saves a separate copy before the host reads the value)
 template <bool GR>
-__global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out, Grp gp) {
+__global__ void __launch_bounds__(kT) k_sum_final(const double* part, int np, double* out,
+                                                  double* hout, Grp gp) {
   if constexpr (GR) {
     int64_t dk;
     if (!grp_begin(gp, &dk)) return;
     part = shift(part, dk);
     out = shift(out, dk);
+    hout = nullptr;
   }
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += kT) acc += part[i];
   const double s = block_sum(acc);
-  if (threadIdx.x == 0) *out = s;
+  if (threadIdx.x == 0) {
+    *out = s;
+    if (hout) *hout = s;
+  }
 }
 
 
@@ -592,7 +599,7 @@ void jacobi_step(int prec, int64_t n, int from_zero, void* x, const void* b, con
   GLLMG_HIP(hipGetLastError());
 }
 void dot(int prec, int64_t n, const void* a, const void* b, double* part, double* res,
-         hipStream_t s) {
+         hipStream_t s, double* hres) {
   const int g = dot_grid(n);
   if (prec == 0)
     with_gr([&](auto gr) {
@@ -609,12 +616,14 @@ void dot(int prec, int64_t n, const void* a, const void* b, double* part, double
   GLLMG_HIP(hipGetLastError());
   with_gr([&](auto gr) {
     constexpr bool GR = decltype(gr)::value;
-    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, res, cur_grp());
+    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, res,
+                       hres, cur_grp());
   });
   GLLMG_HIP(hipGetLastError());
 }
 void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x, double* r,
-                   const double* p, const double* h, double* part, double* rr, hipStream_t s) {
+                   const double* p, const double* h, double* part, double* rr, hipStream_t s,
+                   double* hrr) {
   const int g = dot_grid(n);
   with_gr([&](auto gr) {
     constexpr bool GR = decltype(gr)::value;
@@ -623,7 +632,8 @@ void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x,
   GLLMG_HIP(hipGetLastError());
   with_gr([&](auto gr) {
     constexpr bool GR = decltype(gr)::value;
-    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, rr, cur_grp());
+    hipLaunchKernelGGL((k_sum_final<GR>), dim3(1, grp_count()), dim3(kT), 0, s, (const double*)part, g, rr, hrr,
+                       cur_grp());
   });
   GLLMG_HIP(hipGetLastError());
 }

@@ -1018,6 +1018,8 @@ void post_scalars(gllmg_problem* P, int src, int cnt, int dst) {
                            hipMemcpyDeviceToHost, v.s));
   GLLMG_HIP(hipEventRecord(v.ev, v.s));
 }
+// the reductions wrote their results to hbuf themselves: only the event
+void post_event(gllmg_problem* P) { GLLMG_HIP(hipEventRecord(P->sv.ev, P->sv.s)); }
 
 // One PCG iteration up to its convergence data: h = A p; (p, h); x += alpha p; r -= alpha h;
 // (r, r). One MG iteration: z = V r; x += z; r = b - A x; (r, r).
@@ -1026,15 +1028,16 @@ void enqueue_iteration(gllmg_problem* P) {
   const int64_t N = P->L[0].g.N;
   if (v.mode == GLLMG_MODE_PCG) {
     apply_level(P, 0, 0, 0, P->pp, P->ph, v.s);
-    dot(0, N, P->pp, P->ph, P->part, P->scal + S_PH, v.s);
-    pcg_update_xr(N, P->scal, v.g, S_PH, v.x, P->pr, P->pp, P->ph, P->part, P->scal + S_RR, v.s);
+    dot(0, N, P->pp, P->ph, P->part, P->scal + S_PH, v.s, P->hbuf + 1);
+    pcg_update_xr(N, P->scal, v.g, S_PH, v.x, P->pr, P->pp, P->ph, P->part, P->scal + S_RR, v.s,
+                  P->hbuf);
   } else {
     precond(P, P->pr, P->pz, v.s);
     vec_axpy(0, N, 1.0, P->pz, v.x, v.s);
     residual(P, 0, 0, v.b, v.x, P->pr, v.s);
-    dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, v.s);
+    dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, v.s, P->hbuf);
   }
-  post_scalars(P, S_RR, 2, 0);
+  post_event(P);
   v.phase = PH_ITER;
   // PCG: unless this iteration may well be the last (its residual norm, extrapolated from the
   // last two, within 10x of the target, or maxit next), the next V-cycle is enqueued now, so
@@ -1067,9 +1070,11 @@ void enqueue_final(gllmg_problem* P) {
   const int64_t N = P->L[0].g.N;
   if (v.n0 > 0.0 && std::isfinite(v.n0)) {
     residual(P, 0, 0, v.b, v.x, P->pt, v.s);
-    dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, v.s);
+    dot(0, N, P->pt, P->pt, P->part, P->scal + S_B, v.s, P->hbuf + 2);
+    post_event(P);
+  } else {
+    post_scalars(P, S_B, 1, 2);
   }
-  post_scalars(P, S_B, 1, 2);
   v.phase = PH_FINAL;
 }
 
@@ -1091,8 +1096,8 @@ void solve_begin(gllmg_problem* P, int mode, const double* b, double* x, double 
   for (auto& lv : P->L) v.a0.push_back(lv.applies);
   const int64_t N = P->L[0].g.N;
   residual(P, 0, 0, b, x, P->pr, s);
-  dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, s);
-  post_scalars(P, S_RR, 1, 0);
+  dot(0, N, P->pr, P->pr, P->part, P->scal + S_RR, s, P->hbuf);
+  post_event(P);
   v.phase = PH_INIT;
 }
 

@@ -26,6 +26,28 @@ __device__ __forceinline__ void pin(T& v) {
   asm volatile("" : "+v"(v));
 }
 
+// Row r of the n x n matrix M (D or its transpose, stored one after the other), the same for
+// every lane, read by scalar loads into scalar registers: the FMAs of a contraction then take
+// their D operand from a scalar register instead of an LDS broadcast per term. M (the same
+// for every lane, also where the compiler cannot tell, as in a device function's argument) is
+// constant while a kernel runs. The empty asm hides the row's address from the optimizer, so
+// each row is loaded where it is requested and not every row at the kernel's start, which
+// would need more scalar registers than a wave has.
+template <int N, typename T>
+__device__ __forceinline__ void uniform_row(const T* M, int r, T (&out)[N]) {
+  const uint64_t a = (uint64_t)(M + r * N);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const T* p = (const T*)(((uint64_t)hi << 32) | lo);
+#if defined(__OPTIMIZE__)  // (unoptimized builds keep p in a vector register: no such hint)
+  asm volatile("" : "+s"(p));
+#endif
+  using CT = const __attribute__((address_space(4))) T;
+  CT* q = (CT*)p;
+#pragma unroll
+  for (int l = 0; l < N; ++l) out[l] = q[l];
+}
+
 // ------------------------------------------------------------------ 3D element kernel
 // Thread (i, j) of an element keeps the column k = 0..p in registers; the x- and
 // y-contractions read the element tile from LDS, the z-contraction works in registers.
@@ -66,8 +88,10 @@ struct EBox {
 // One pass of the 3D element kernel over EPB elements (those of `map`, by default ebase..) by
 // the threads t of a workgroup: t < EPB n^2 own a column, others only join the barriers. sA and
 // sB hold EPB n^3 values, sD n^2. Consecutive calls that share the LDS must be separated by a
-// barrier.
-template <int N, typename T, int EPB, class Map = ERange>
+// barrier. With SR the z-contractions take D's rows and columns (the same for every lane) from
+// scalar registers (uniform_row) instead of LDS broadcasts: measured 7-13% faster at n = 7 in
+// FP64, 2-3% at n = 9, within +-2% below (kept on LDS there).
+template <int N, typename T, int EPB, class Map = ERange, bool SR = (N >= 7)>
 __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ F,
                                        const T* __restrict__ G, const T* __restrict__ Dm,
                                        const Grid& g, int neumann, uint32_t ebase, int t,
@@ -131,11 +155,13 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T ux = T(0), uy = T(0), uz = T(0);
+    T dk[N];
+    if constexpr (SR) uniform_row<N>(Dm, k, dk);
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       ux += Di[l] * A[k * NN + j * N + l];
       uy += Dj[l] * A[k * NN + l * N + i];
-      uz += sD[k * N + l] * xr[l];
+      uz += (SR ? dk[l] : sD[k * N + l]) * xr[l];
     }
     T g0, g1, g2, g3, g4, g5;
     if (k < PF) {
@@ -185,24 +211,27 @@ __device__ __forceinline__ void elem3d(const T* __restrict__ x, T* __restrict__ 
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     T acc = T(0);
+    T dk[N];
+    if constexpr (SR) uniform_row<N>(Dm + NN, k, dk);  // column k of D
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       acc += DiT[l] * A[k * NN + j * N + l];
       acc += DjT[l] * B[k * NN + l * N + i];
-      acc += sD[l * N + k] * wz[l];
+      acc += (SR ? dk[l] : sD[l * N + k]) * wz[l];
     }
     Fe[k * NN] = acc;
   }
 }
 
-// v of wave lane l (l a compile-time constant after unrolling), in a scalar register
-__device__ __forceinline__ float lane_value(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+// One row of the pointwise product w = G u, g0 u0 + g1 u1 + g2 u2, with its rounding fixed
+// (two fused multiply-adds in this order) rather than left to the compiler's choice of which
+// product to fuse, which can differ between two kernels that inline the same pass.
+__device__ __forceinline__ double flux(double g0, double g1, double g2, double u0, double u1,
+                                       double u2) {
+  return __builtin_fma(g2, u2, __builtin_fma(g1, u1, g0 * u0));
 }
-__device__ __forceinline__ double lane_value(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
+__device__ __forceinline__ float flux(float g0, float g1, float g2, float u0, float u1, float u2) {
+  return __builtin_fmaf(g2, u2, __builtin_fmaf(g1, u1, g0 * u0));
 }
 
 // High orders: the same element pass arranged for a register budget of two waves per SIMD
@@ -215,7 +244,12 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 // * the contractions run in chunks of C terms, software-pipelined: the LDS reads of
 //   chunk s+1 are issued before the products of chunk s, with a scheduling barrier between
 //   chunks so that the compiler does not hoist all reads of a plane (which is what fills the
-//   registers otherwise).
+//   registers otherwise);
+// * D's rows and columns for the z-contractions (the same for every lane) come from scalar
+//   loads one plane ahead into scalar registers (uniform_row), not from LDS: a third fewer
+//   LDS reads than one LDS broadcast per term, and fewer instructions than one LDS read per
+//   plane passed to the lanes by cross-lane reads; measured 5-13% faster at n = 13 and 17 on
+//   8^3 to 20^3 hexes, FP32 and FP64, except FP64 n = 17 on 8^3 hexes (2% slower).
 // The sums are formed in the same order as in elem3d.
 // chunk length: measured best 1 in FP64 and 2 in FP32 (n = 13, 15, 17; FP64 with 1 against 3:
 // 12-19% faster)
@@ -285,15 +319,9 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
   }
 
   // phase 1: u = D-contractions of the tile along x, y, z; flux w = G u per node
-  T bx[2][C], by[2][C], bz[2][C], bd[2][C];
-  // FP32: D's row k (the same for the whole wave) arrives in one LDS read, lane l holding
-  // D[k][l], and reaches every lane by a cross-lane read instead of one LDS read per term (a
-  // quarter fewer LDS reads; measured 3.5% faster at n = 13 and 17; in FP64 the two 32-bit
-  // cross-lane reads per value cost more than they save: 5% slower at n = 17)
-  constexpr bool DLANE = sizeof(T) == 4;
-  const int dl = (int)(threadIdx.x & 63u) < N ? (int)(threadIdx.x & 63u) : N - 1;
-  T drow[2] = {T(0), T(0)};
-  if constexpr (DLANE) drow[0] = sD[dl];
+  T bx[2][C], by[2][C], bz[2][C];
+  T srow[2][N];  // row k of D (phase 1) or column k (phase 2), one plane ahead
+  uniform_row<N>(Dm, 0, srow[0]);
   auto load1 = [&](int s, int buf) {
     const int k = s / NC, c = s - (s / NC) * NC;
 #pragma unroll
@@ -303,7 +331,6 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
         bx[buf][q] = A[k * NN + j * N + l];
         by[buf][q] = A[k * NN + l * N + i];
         if constexpr (!XREG) bz[buf][q] = A[l * NN + ij];
-        if constexpr (!DLANE) bd[buf][q] = sD[k * N + l];
       }
     }
   };
@@ -315,16 +342,14 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
     const int k = s / NC, c = s - (s / NC) * NC;
     if (s + 1 < S) load1(s + 1 < S ? s + 1 : 0, (s + 1) & 1);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DLANE)
-      if (c == 0 && k + 1 < N) drow[(k + 1) & 1] = sD[(k + 1 < N ? k + 1 : 0) * N + dl];
+    if (c == 0 && k + 1 < N) uniform_row<N>(Dm, k + 1 < N ? k + 1 : 0, srow[(k + 1) & 1]);
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int l = c * C + q;
       if (l < N) {
         ux += Di[l] * bx[s & 1][q];
         uy += Dj[l] * by[s & 1][q];
-        const T dkl = DLANE ? lane_value(drow[k & 1], l) : bd[s & 1][q];
-        uz += dkl * (XREG ? xr[l] : bz[s & 1][q]);
+        uz += srow[k & 1][l] * (XREG ? xr[l] : bz[s & 1][q]);
       }
     }
     if (c == NC - 1) {
@@ -335,9 +360,9 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
 #pragma unroll
         for (int cc = 0; cc < 6; ++cc) gp[k % PF][cc] = Ge[cc * NNN + (k + PF < N ? k + PF : 0) * NN];
       }
-      const T wx = gk[0] * ux + gk[1] * uy + gk[2] * uz;
-      wy[k] = gk[1] * ux + gk[3] * uy + gk[4] * uz;
-      wz[k] = gk[2] * ux + gk[4] * uy + gk[5] * uz;
+      const T wx = flux(gk[0], gk[1], gk[2], ux, uy, uz);
+      wy[k] = flux(gk[1], gk[3], gk[4], ux, uy, uz);
+      wz[k] = flux(gk[2], gk[4], gk[5], ux, uy, uz);
       // form the fluxes here: otherwise the compiler sinks them to their uses after the
       // barrier and keeps u and the six factors of every plane alive instead
       pin(wy[k]);
@@ -352,9 +377,7 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
     for (int k = 0; k < N; ++k) A[k * NN + ij] = wy[k];
   }
   __syncthreads();
-  // (with DLANE every lane stays active through phase 2 for the cross-lane reads: the block
-  // is whole waves, and invalid threads only skip their stores)
-  if (!DLANE && !valid) return;
+  if (!valid) return;
   T DiT[N], DjT[N];
 #pragma unroll
   for (int l = 0; l < N; ++l) {
@@ -363,9 +386,8 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
   }
 
   // phase 2: transposed contractions of the fluxes (x-flux in B, y-flux in A, z in registers)
-  T cx[2][C], cy[2][C], cd[2][C];
-  T dcol[2] = {T(0), T(0)};  // column k of D, as the rows above
-  if constexpr (DLANE) dcol[0] = sD[dl * N];
+  T cx[2][C], cy[2][C];
+  uniform_row<N>(Dm + NN, 0, srow[0]);
   auto load2 = [&](int s, int buf) {
     const int k = s / NC, c = s - (s / NC) * NC;
 #pragma unroll
@@ -374,7 +396,6 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
       if (l < N) {
         cx[buf][q] = B[k * NN + j * N + l];
         cy[buf][q] = A[k * NN + l * N + i];
-        if constexpr (!DLANE) cd[buf][q] = sD[l * N + k];
       }
     }
   };
@@ -386,16 +407,14 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
     const int k = s / NC, c = s - (s / NC) * NC;
     if (s + 1 < S) load2(s + 1 < S ? s + 1 : 0, (s + 1) & 1);
     __builtin_amdgcn_sched_barrier(0);
-    if constexpr (DLANE)
-      if (c == 0 && k + 1 < N) dcol[(k + 1) & 1] = sD[dl * N + (k + 1 < N ? k + 1 : 0)];
+    if (c == 0 && k + 1 < N) uniform_row<N>(Dm + NN, k + 1 < N ? k + 1 : 0, srow[(k + 1) & 1]);
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int l = c * C + q;
       if (l < N) {
         acc += DiT[l] * cx[s & 1][q];
         acc += DjT[l] * cy[s & 1][q];
-        const T dlk = DLANE ? lane_value(dcol[k & 1], l) : cd[s & 1][q];
-        acc += dlk * wz[l];
+        acc += srow[k & 1][l] * wz[l];
       }
     }
     if (c == NC - 1) {
@@ -425,12 +444,14 @@ __device__ __forceinline__ void elem3d_any(const T* __restrict__ x, T* __restric
 // are the same for the whole wave (LDS broadcasts) and only the x-contractions read other
 // threads' values from LDS. (One thread per node instead reads D per lane for every term:
 // measured 1.7x slower at p = 8 and 2.5x at p = 16.) sA and sB hold EPB n^2 values, sD n^2.
+// With SR the y-contractions take D's rows and columns from scalar registers (uniform_row):
+// 3-21% faster at n = 17; at n = 5 and 9 between 7% faster and 7% slower (kept on LDS).
 template <int N>
 struct Epb2 {
   static constexpr int v = 256 / N;
 };
 
-template <int N, typename T, int EPB>
+template <int N, typename T, int EPB, bool SR = (N >= 13)>
 __device__ __forceinline__ void elem2d_col(const T* __restrict__ x, T* __restrict__ F,
                                            const T* __restrict__ G, const T* __restrict__ Dm,
                                            const Grid& g, int neumann, uint32_t ebase, int t,
@@ -479,10 +500,12 @@ __device__ __forceinline__ void elem2d_col(const T* __restrict__ x, T* __restric
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     T ux = T(0), uy = T(0);
+    T dj[N];
+    if constexpr (SR) uniform_row<N>(Dm, j, dj);
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       ux += Di[l] * A[j * N + l];
-      uy += sD[j * N + l] * xr[l];
+      uy += (SR ? dj[l] : sD[j * N + l]) * xr[l];
     }
     T g0, g1, g2;
     if (j < PF) {
@@ -507,10 +530,12 @@ __device__ __forceinline__ void elem2d_col(const T* __restrict__ x, T* __restric
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     T acc = T(0);
+    T dj[N];
+    if constexpr (SR) uniform_row<N>(Dm + NN, j, dj);  // column j of D
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       acc += DiT[l] * B[j * N + l];
-      acc += sD[l * N + j] * wy[l];
+      acc += (SR ? dj[l] : sD[l * N + j]) * wy[l];
     }
     Fe[j * N] = acc;
   }

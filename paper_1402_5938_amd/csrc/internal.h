@@ -94,7 +94,7 @@ struct Level {
   int ncomp;              // unique G entries per point (3 in 2D, 6 in 3D)
   double* G64 = nullptr;  // [E][ncomp][n^d]
   float* G32 = nullptr;
-  double* D64 = nullptr;  // n x n derivative matrix, D[i*n + l] = l_l'(xi_i)
+  double* D64 = nullptr;  // n x n derivative matrix, D[i*n + l] = l_l'(xi_i), then its transpose
   float* D32 = nullptr;
   double* xi64 = nullptr; // GLL nodes and weights of the level's order
   double* w64 = nullptr;

@@ -21,12 +21,10 @@ namespace gllmg {
 
 namespace {
 
-// threads of the 3D element kernel: EPB n^2, rounded up to whole waves for the FP32 high-order
-// pass (whose cross-lane reads need every lane of a wave present)
+// threads of the 3D element kernel: EPB n^2
 template <int N, typename T, int EPB>
 struct Threads3d {
-  static constexpr int v =
-      (N >= kHighpN && sizeof(T) == 4) ? (EPB * N * N + 63) / 64 * 64 : EPB * N * N;
+  static constexpr int v = EPB * N * N;
 };
 
 template <int N, typename T, int EPB, bool GR>

@@ -233,8 +233,8 @@ size_t layout(gllmg_problem* P, const std::vector<LevelSpec>& specs, Arena& A) {
     L.npts = L.g.E * (c.dim == 3 ? (int64_t)L.n * L.n * L.n : (int64_t)L.n * L.n);
     L.has_coarse = l + 1 < specs.size();
     const int n = L.n;
-    L.D64 = (double*)A.take(sizeof(double) * n * n);
-    L.D32 = (float*)A.take(sizeof(float) * n * n);
+    L.D64 = (double*)A.take(sizeof(double) * 2 * n * n);
+    L.D32 = (float*)A.take(sizeof(float) * 2 * n * n);
     L.xi64 = (double*)A.take(sizeof(double) * n);
     L.w64 = (double*)A.take(sizeof(double) * n);
     if (L.gauss) {
@@ -612,12 +612,17 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
       GLLMG_HIP(hipMemcpyAsync(L.wg64, r.wg.data(), sizeof(double) * r.wg.size(), hipMemcpyHostToDevice, s));
       GLLMG_HIP(hipStreamSynchronize(s));
     }
-    std::vector<float> D32(r.D.begin(), r.D.end());
-    GLLMG_HIP(hipMemcpyAsync(L.D64, r.D.data(), sizeof(double) * r.D.size(), hipMemcpyHostToDevice, s));
+    const int n = L.n;
+    std::vector<double> DDt(r.D);  // D, then its transpose
+    DDt.resize((size_t)2 * n * n);
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) DDt[(size_t)n * n + a * n + b] = r.D[(size_t)b * n + a];
+    std::vector<float> D32(DDt.begin(), DDt.end());
+    GLLMG_HIP(hipMemcpyAsync(L.D64, DDt.data(), sizeof(double) * DDt.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.xi64, r.xi.data(), sizeof(double) * r.xi.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.w64, r.w.data(), sizeof(double) * r.w.size(), hipMemcpyHostToDevice, s));
-    GLLMG_HIP(hipStreamSynchronize(s));  // D32 goes out of scope
+    GLLMG_HIP(hipStreamSynchronize(s));  // DDt and D32 go out of scope
   }
   for (size_t l = 0; l < P->L.size(); ++l) {
     Level& L = P->L[l];

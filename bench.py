@@ -499,6 +499,32 @@ def workload_apply(a):
             "achieved_gbs": nbytes / t_apply / 1e9}
 
 
+def extra_workloads(a):
+    """The other workloads measured in the same run, in summary: the 8^3 p = 16 solve in FP64,
+    mixed precision and iterative refinement (errors against the oracle's samples), the batch
+    of 256 problems, and the Poisson-arrival server at 200 req/s. A workload that fails is
+    reported with its error instead of its figures."""
+    import torch
+    out = {}
+    for name, fn, keep in (
+            ("mixed_8cubed_p16", workload_mixed,
+             lambda r: {k: r[k] for k in ("f64", "f32", "f32_ir", "speedup_mixed_over_fp64",
+                                          "speedup_ir_over_fp64") if k in r}),
+            ("batch_256_4cubed", workload_batch,
+             lambda r: {k: r[k] for k in ("batch_time_ms", "solves_per_s", "converged", "max_iters")}),
+            ("serve_200rps", workload_serve,
+             lambda r: {k: r[k] for k in r if k != "workload"})):
+        t0 = time.perf_counter()
+        try:
+            out[name] = keep(fn(a))
+        except Exception as e:  # reported, not raised: the headline line is printed regardless
+            out[name] = {"error": f"{type(e).__name__}: {e}"}
+        out[name]["wall_s"] = time.perf_counter() - t0
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep",
@@ -514,6 +540,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--prec", default="f64", choices=["f64", "f32"], help="apply workload: product precision")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="config2: leave out the mixed-precision, batched and serving workloads")
     ap.add_argument("--nelem", type=int, default=16)
     ap.add_argument("--order", type=int, default=8)
     ap.add_argument("--levels", type=int, default=0, help="config2: keep the finest k levels (0: all)")
@@ -619,6 +647,8 @@ def main():
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     G.close()
+    if not a.no_extra:
+        out["workloads"] = extra_workloads(a)
     print(json.dumps(out))
 
 

@@ -238,7 +238,7 @@ __device__ __forceinline__ float flux(float g0, float g1, float g2, float u0, fl
 // (at most 256 registers per thread), where the low-order form needs more and runs one
 // workgroup per CU, with no overlap of one element's loads and another's arithmetic:
 // * the z-contraction reads the thread's own column back from LDS where registers are short
-//   (FP32 n = 17, FP64 n = 12, 13), else from a register copy of x;
+//   (FP64 n = 12, 13), else from a register copy of x;
 // * the x-flux goes to the second LDS tile, still unused, as soon as it is formed, the
 //   y-flux once every thread has finished reading the input tile;
 // * the contractions run in chunks of C terms, software-pipelined: the LDS reads of
@@ -290,12 +290,11 @@ __device__ __forceinline__ void elem3d_hp(const T* __restrict__ x, T* __restrict
   for (int k = 0; k < PF; ++k)
 #pragma unroll
     for (int c = 0; c < 6; ++c) gp[k][c] = Ge[c * NNN + k * NN];
-  // FP32 up to n = 16: the x column stays in registers for the z-contraction (a quarter of the
-  // first phase's LDS reads; measured 4-6% faster at n = 13 and 15). At n = 17 the extra
-  // registers cost a wave per SIMD (5% slower). FP64 from n = 14 on, where the pass runs two
-  // waves per SIMD with or without them: 2% faster at n = 17 (at n = 12, 13 they would take
-  // the third wave).
-  constexpr bool XREG = (sizeof(T) == 4 && N <= 16) || (sizeof(T) == 8 && N >= 14);
+  // The x column stays in registers for the z-contraction in FP32 (a quarter of the first
+  // phase's LDS reads; measured 4-10% faster at n = 13, 15 and 17) and in FP64 from n = 14 on
+  // (3-4% at n = 17); in FP64 at n = 12, 13 the registers would take the third wave per SIMD
+  // (13-19% slower on 12^3 to 20^3 hexes).
+  constexpr bool XREG = sizeof(T) == 4 || N >= 14;
   T xr[N];
   {
 #pragma unroll

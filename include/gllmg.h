@@ -54,8 +54,8 @@ typedef enum {
 typedef enum { GLLMG_F64 = 0, GLLMG_F32 = 1 } gllmg_prec;
 
 /* Hierarchies (§3.1): H keeps p and halves the elements per axis; P takes p -> ceil(p/2) down to
- * 1, then halves the elements; LOW (§3.1.3, the first-order approximation built on the nodes of
- * the high-order discretization) keeps the order-p level, then a level of first-order cells
+ * 1, then halves the elements; LOW (§3.1.3, a first-order operator whose cells have the order-p
+ * nodes as vertices) keeps the order-p level, then a level of first-order cells
  * whose vertices are exactly the order-p nodes (n_e p cells per axis, same node numbering), then
  * halves that first-order grid (each coarser level on every other node). With LOW the solvers'
  * preconditioner is low_cycles sweeps x <- x + V_1 (r - A_1 x) from x = 0 of the first-order

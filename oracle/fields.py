@@ -3,7 +3,7 @@
 Test infrastructure only (see the package docstring).
 
 The paper's domains are images of the unit square/cube under a diffeomorphism (§2.3), and the
-coefficient mu is a given function evaluated wherever it is needed (§2.3, §4.1). The field
+coefficient mu is a known function, evaluated at whatever points need it (§2.3, §4.1). The field
 families and their parameters are described (without arithmetic) in
 ``paper_1402_5938_amd.inputs``; this module gives them meaning for the oracle.
 """

@@ -1,5 +1,5 @@
-"""The first-order preconditioner hierarchy (§3.1.3: first-order cells on the nodes of the
-high-order discretization, here with geometric h-coarsening of that structured grid) on the GPU
+"""The first-order preconditioner hierarchy (§3.1.3: first-order cells whose vertices are the
+order-p nodes, here with geometric h-coarsening of that structured grid) on the GPU
 through the C ABI against the oracle: the level structure, the preconditioner (k sweeps of the
 first-order V-cycle) to 1e-10, PCG and MG iteration counts, FP32 first-order sweeps."""
 

@@ -595,8 +595,8 @@ def test_pcg_equals_textbook_cg_with_materialized_vcycle():
 
 
 def test_cost_model_seven_fine_applies_per_iteration():
-    """§4.3: with 3 pre- and 3 post-smoothing steps each PCG iteration costs one residual-type
-    product plus six smoothing products on the finest level (7 N g_p)."""
+    """§4.3: with three smoothing steps before and three after, each PCG iteration costs one
+    residual-type product plus six smoothing products on the finest level (7 N g_p)."""
     for smoother in ("chebyshev", "jacobi"):
         H = _small_h(smoother=smoother, nu=3, ne=4, p=2, hierarchy="p")
         b = np.zeros(H.fine.mesh.N)

@@ -173,7 +173,7 @@ def _solve_timed(G, b, steps, warmup, rtol, maxit, mode="pcg"):
     return (time.perf_counter() - t0) / steps, r, x
 
 
-IR_INNER = 12   # FP32 CG steps per refinement step of the iterative-refinement mode
+IR_INNER = 12   # FP32 CG steps of the first refinement step (at most, in later ones)
 
 
 def workload_mixed(a):
@@ -198,7 +198,7 @@ def workload_mixed(a):
                      "relres_true": r.relres_true}
         if mode == "ir":
             out[name]["refinement_steps"] = len(r.history) - 1
-            out[name]["inner_cg_steps_per_refinement"] = IR_INNER
+            out[name]["inner_cg_steps_first_refinement"] = IR_INNER
         sols[name] = x.clone()
         if name == "f64":
             xt = torch.zeros_like(b)

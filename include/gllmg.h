@@ -282,10 +282,13 @@ gllmg_status gllmg_vcycle(const gllmg_problem* prob, gllmg_prec prec, const void
  * has more than 4096 interior nodes, so no exact coarse solve was set up.
  * GLLMG_MODE_IR (problems set up with vcycle_prec = GLLMG_F32 and ir_inner = k > 0): iterative
  * refinement. Each step forms r = b - A x in FP64, scales it by a power of two to norm about 1,
- * runs k steps of CG in FP32 on A e = r from e = 0 (FP32 products, FP32 V-cycle as the
+ * runs m steps of CG in FP32 on A e = r from e = 0 (FP32 products, FP32 V-cycle as the
  * preconditioner, FP32 vector updates, FP64 dot products), and adds e, scaled back, to x in
- * FP64; it stops when the FP64 residual meets rtol. stats: iters counts the inner CG steps (one
- * V-cycle each; maxit bounds them), history holds ||b - A x|| after every refinement step,
+ * FP64; it stops when the FP64 residual meets rtol. m = k in the first step; later, the
+ * smallest count that the previous step's mean reduction per CG step predicts to reach rtol,
+ * at most k (a step that falls short is followed by another). stats: iters counts the inner CG steps (one
+ * V-cycle each; maxit bounds them), history holds ||b - A x|| before the first and after every
+ * refinement step, followed by -1 where the array has room,
  * relres = relres_true. gllmg_solve only (solve_begin and batch solves: EUNSUPPORTED). */
 gllmg_status gllmg_solve(const gllmg_problem* prob, int32_t mode, const double* b, double* x,
                          double rtol, int32_t maxit, gllmg_solve_stats* stats, void* stream);

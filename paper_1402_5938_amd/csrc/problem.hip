@@ -1234,8 +1234,16 @@ gllmg_status ir_solve(gllmg_problem* P, const double* b, double* x, double rtol,
   double nr = n0;
   int iters = 0;
   bool conv = n0 == 0.0, breakdown = !std::isfinite(n0);
+  // inner length: k for the first step; after it, the mean rate per CG step of the previous
+  // refinement step (its residual reduction to the power 1/length) predicts how many steps
+  // reach the tolerance, and a step runs that many (at most k) instead of k
+  double rate = 0.0;
   while (!conv && !breakdown && iters < maxit) {
-    const int m = std::min(P->cfg.ir_inner, maxit - iters);
+    int m = std::min(P->cfg.ir_inner, maxit - iters);
+    if (rate > 0.0 && rate < 1.0) {
+      const double need = rtol * n0 / nr;
+      if (need < 1.0) m = std::min(m, std::max(1, (int)std::ceil(std::log(need) / std::log(rate))));
+    }
     cast_64_32(N, P->pr, r32, s, P->scal + S_RR);
     vec_zero(1, N, e32, s);
     precond_level0(P, 1, r32, z32, s);
@@ -1255,8 +1263,10 @@ gllmg_status ir_solve(gllmg_problem* P, const double* b, double* x, double rtol,
     }
     iters += m;
     ir_add(N, e32, P->scal + S_RR, x, s);  // S_RR still holds the scaled residual's (r, r)
+    const double before = nr;
     nr = residual_norm();
     hist.push_back(nr);
+    rate = nr > 0.0 && nr < before ? std::pow(nr / before, 1.0 / m) : 0.0;
     breakdown = !std::isfinite(nr);
     conv = !breakdown && nr <= rtol * n0;
   }
@@ -1267,8 +1277,10 @@ gllmg_status ir_solve(gllmg_problem* P, const double* b, double* x, double rtol,
     st->relres_true = st->relres;
     for (int i = 0; i < 16; ++i) st->applies[i] = 0;
     for (size_t i = 0; i < P->L.size() && i < 16; ++i) st->applies[i] = P->L[i].applies - a0[i];
-    if (st->history)
+    if (st->history) {
       for (size_t i = 0; i < hist.size() && i <= (size_t)maxit; ++i) st->history[i] = hist[i];
+      if (hist.size() <= (size_t)maxit) st->history[hist.size()] = -1.0;  // end of the list
+    }
     st->t_solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   if (breakdown) throw Error(GLLMG_EBREAKDOWN, "breakdown: non-finite residual");

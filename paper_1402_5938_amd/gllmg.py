@@ -389,9 +389,9 @@ class Problem:
         if status not in (OK, ENOTCONV) or (status == ENOTCONV and raise_on_notconv):
             _check(status)
         res = _result(status, st, hist, self.nlevels)
-        if m == MODE_IR:  # one residual norm per refinement step of cfg.ir_inner CG steps
-            k = max(1, self.cfg.ir_inner)
-            res.history = list(hist[:(st.iters + k - 1) // k + 1])
+        if m == MODE_IR:  # one residual norm per refinement step, then -1 (if there is room)
+            n = next((i for i in range(maxit + 1) if hist[i] < 0.0), maxit + 1)
+            res.history = list(hist[:n])
         return res
 
     def solve_async(self, b, x, mode="pcg", rtol=1e-10, maxit=500, stream=None) -> AsyncSolve:

@@ -1242,7 +1242,8 @@ gllmg_status ir_solve(gllmg_problem* P, const double* b, double* x, double rtol,
     int m = std::min(P->cfg.ir_inner, maxit - iters);
     if (rate > 0.0 && rate < 1.0) {
       const double need = rtol * n0 / nr;
-      if (need < 1.0) m = std::min(m, std::max(1, (int)std::ceil(std::log(need) / std::log(rate))));
+      const double q = need < 1.0 ? std::ceil(std::log(need) / std::log(rate)) : 1.0;
+      if (q < (double)m) m = std::max(1, (int)q);  // compared as doubles: q may exceed int range
     }
     cast_64_32(N, P->pr, r32, s, P->scal + S_RR);
     vec_zero(1, N, e32, s);

@@ -413,8 +413,8 @@ void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
 }
 
 // lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
-// S = D^{-1/2} A D^{-1/2} with full reorthogonalization (two classical Gram-Schmidt passes,
-// each one multi-dot and one update against the whole basis),
+// S = D^{-1/2} A D^{-1/2} with full reorthogonalization (one classical Gram-Schmidt pass per
+// step: one multi-dot and one update against the whole basis),
 // m = min(eig_steps, interior unknowns) steps, SplitMix64 start vector; breakdown when
 // beta <= 1e-14 ||T||. Returns the largest eigenvalue of the tridiagonal T_m.
 double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
@@ -447,7 +447,7 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
     dot(0, N, V[j], w, P->part, alpha + j, s);
     vec_axpy_dev(N, alpha + j, -1.0, V[j], w, s);
     if (j > 0) vec_axpy_sqrt_dev(N, n2 + (j - 1), V[j - 1], w, s);
-    for (int pass = 0; pass < 2; ++pass) block_orthogonalize(N, V[0], N, j + 1, w, part, coef, s);
+    block_orthogonalize(N, V[0], N, j + 1, w, part, coef, s);
     dot(0, N, w, w, P->part, n2 + j, s);
     if (j + 1 < m) vec_div_sqrt_dev(N, w, n2 + j, V[j + 1], s);
   }

@@ -325,8 +325,6 @@ void vec_scale_mul(int prec, int64_t n, double alpha, const void* a, const void*
                    hipStream_t s);                                                          // alpha a*b
 void vec_div(int64_t n, const double* a, double den, double* out, hipStream_t s);       // a / den
 void vec_sqrt(int64_t n, const double* a, double* out, hipStream_t s);
-void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
-                  hipStream_t s);                                        // y += sign * (*coef) x
 void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s);     // v = v ? 1/v : 0
 // Casts between the FP64 and FP32 vectors; with rr (the device (r, r) of the FP64 vector that the
 // FP32 one stands for) both scale by pow2_inv_norm(*rr): out = float(a * 2^-e), then
@@ -359,13 +357,20 @@ void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* 
                    const double* p, const double* h, double* partials, double* rr, hipStream_t s,
                    double* hrr = nullptr);
 // Lanczos: w -= V (V^T w) against the c basis vectors V_v = V + v ld (one classical
-// Gram-Schmidt pass: all coefficients from the same w, fixed-order sums). part holds
-// c kMdBlocks doubles, coef c.
+// Gram-Schmidt pass: all coefficients from the same w, fixed-order sums), then *n2 = w . w.
+// part holds c kMdBlocks doubles, coef c, npart kDotBlocks (the norm's partials).
 constexpr int kMdBlocks = 256;
-void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
-                         double* coef, hipStream_t s);
-void vec_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* out, hipStream_t s);  // a / sqrt(*n2)
-void vec_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y, hipStream_t s);  // y -= sqrt(*n2) x
+void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, double* w,
+                              double* part, double* coef, double* npart, double* n2, hipStream_t s);
+// Fused vector passes of a Lanczos step (the same arithmetic and reduction order as the
+// separate calls): w = sqd w then *res = v . w (part: kDotBlocks doubles); w = w - *alpha vj
+// - sqrt(*n2) vjm1 (the last term only if vjm1); vn = w / sqrt(*n2) and t = sqd vn.
+void lanczos_scale_dot(int64_t n, const double* sqd, double* w, const double* v, double* part,
+                       double* res, hipStream_t s);
+void lanczos_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
+                   const double* vjm1, double* w, hipStream_t s);
+void lanczos_next(int64_t n, const double* w, const double* n2, const double* sqd, double* vn,
+                  double* t, hipStream_t s);
 // dst[k cnt + i] = scal[i] (src = the first problem's scalars) for every active problem k of
 // the current launch group (dst is not shifted: one buffer for the group)
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s);

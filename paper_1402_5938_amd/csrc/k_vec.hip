@@ -137,10 +137,6 @@ __global__ void k_sqrt(int64_t n, const double* a, double* o) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) o[i] = sqrt(a[i]);
 }
-__global__ void k_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = y[i] + (sign * coef[0]) * x[i];
-}
 template <typename T> __global__ void k_recip_masked(int64_t n, T* v) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = v[i] != T(0) ? T(1) / v[i] : T(0);
@@ -297,26 +293,60 @@ __global__ void __launch_bounds__(kT) k_md_final(const double* part, int np, dou
   if (threadIdx.x == 0) coef[blockIdx.x] = s;
 }
 
-// w -= sum_v coef[v] V_v (v ascending)
-__global__ void k_md_sub(int64_t n, const double* V, int64_t ld, int c, const double* coef, double* w) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+
+// ------------------------------------------------------------------ Lanczos step, fused
+// The vector passes of one Lanczos step, each doing what two of the kernels above do in turn,
+// per entry with the same operations in the same order; those that end in a dot product run on
+// the dot-product grid with its strided sums, so that every partial (and every result) is
+// bitwise the one the separate kernels give.
+// w = (1 sqd) w; partials of v . w
+__global__ void __launch_bounds__(kT) k_lz_scale_dot(int64_t n, const double* sqd, double* w,
+                                                     const double* v, double* part) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const double wi = 1.0 * sqd[i] * w[i];
+    w[i] = wi;
+    acc += v[i] * wi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// w = w - alpha vj, then (vjm1 != nullptr) w = w - sqrt(*n2) vjm1
+__global__ void k_lz_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
+                           const double* vjm1, double* w) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double wi = w[i];
-  for (int v = 0; v < c; ++v) wi = wi - coef[v] * V[(int64_t)v * ld + i];
+  double wi = w[i] + (-1.0 * alpha[0]) * vj[i];
+  if (vjm1) wi = wi + (-sqrt(n2[0])) * vjm1[i];
   w[i] = wi;
 }
 
-// o = a / sqrt(*n2)
-__global__ void k_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* o) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) o[i] = a[i] / sqrt(n2[0]);
+// w -= sum_v coef[v] V_v (v ascending); partials of w . w
+__global__ void __launch_bounds__(kT) k_md_sub_dot(int64_t n, const double* V, int64_t ld, int c,
+                                                   const double* coef, double* w, double* part) {
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    double wi = w[i];
+    for (int v = 0; v < c; ++v) wi = wi - coef[v] * V[(int64_t)v * ld + i];
+    w[i] = wi;
+    acc += wi * wi;
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// y -= sqrt(*n2) x
-__global__ void k_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = y[i] + (-sqrt(n2[0])) * x[i];
+// vn = w / sqrt(*n2); t = (1 sqd) vn (w and vn may be the same vector)
+__global__ void k_lz_next(int64_t n, const double* w, const double* n2, const double* sqd,
+                          double* vn, double* t) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = w[i] / sqrt(n2[0]);
+  vn[i] = v;
+  t[i] = 1.0 * sqd[i] * v;
 }
+
+
 
 // dst[k cnt + i] = src[i] of problem k (blockIdx.y): a launch group's scalars side by side
 __global__ void k_collect(const double* src, int cnt, double* dst, Grp gp) {
@@ -523,12 +553,6 @@ void vec_sqrt(int64_t n, const double* a, double* o, hipStream_t s) {
   hipLaunchKernelGGL(k_sqrt, dim3(nb(n)), dim3(kT), 0, s, n, a, o);
   GLLMG_HIP(hipGetLastError());
 }
-void vec_axpy_dev(int64_t n, const double* coef, double sign, const double* x, double* y,
-                  hipStream_t s) {
-  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_axpy_dev, dim3(nb(n)), dim3(kT), 0, s, n, coef, sign, x, y);
-  GLLMG_HIP(hipGetLastError());
-}
 void vec_recip_masked(int prec, int64_t n, void* v, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   if (prec == 0)
@@ -637,28 +661,43 @@ void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x,
   });
   GLLMG_HIP(hipGetLastError());
 }
-void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
-                         double* coef, hipStream_t s) {
+void lanczos_scale_dot(int64_t n, const double* sqd, double* w, const double* v, double* part,
+                       double* res, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  const int g = dot_grid(n);
+  hipLaunchKernelGGL(k_lz_scale_dot, dim3(g), dim3(kT), 0, s, n, sqd, w, v, part);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_sum_final<false>), dim3(1), dim3(kT), 0, s, (const double*)part, g, res,
+                     (double*)nullptr, Grp{nullptr, nullptr});
+  GLLMG_HIP(hipGetLastError());
+}
+void lanczos_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
+                   const double* vjm1, double* w, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL(k_lz_axpy2, dim3(nb(n)), dim3(kT), 0, s, n, alpha, vj, n2, vjm1, w);
+  GLLMG_HIP(hipGetLastError());
+}
+void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, double* w,
+                              double* part, double* coef, double* npart, double* n2, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   GLLMG_CHECK(c >= 1, GLLMG_EINVAL, "empty basis");
-  // as many blocks as the vector fills, at most kMdBlocks (a function of n alone: same sums)
   const int g = (int)std::min<int64_t>(kMdBlocks, std::max<int64_t>(1, (n + kT - 1) / kT));
   hipLaunchKernelGGL(k_multidot, dim3(g, (c + kMdChunk - 1) / kMdChunk), dim3(kT), 0, s, n, V, ld, c,
                      (const double*)w, part);
   GLLMG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_md_final, dim3(c), dim3(kT), 0, s, (const double*)part, g, coef);
   GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_md_sub, dim3(nb(n)), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w);
+  const int gd = dot_grid(n);
+  hipLaunchKernelGGL(k_md_sub_dot, dim3(gd), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w, npart);
+  GLLMG_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_sum_final<false>), dim3(1), dim3(kT), 0, s, (const double*)npart, gd, n2,
+                     (double*)nullptr, Grp{nullptr, nullptr});
   GLLMG_HIP(hipGetLastError());
 }
-void vec_div_sqrt_dev(int64_t n, const double* a, const double* n2, double* o, hipStream_t s) {
+void lanczos_next(int64_t n, const double* w, const double* n2, const double* sqd, double* vn,
+                  double* t, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_div_sqrt_dev, dim3(nb(n)), dim3(kT), 0, s, n, a, n2, o);
-  GLLMG_HIP(hipGetLastError());
-}
-void vec_axpy_sqrt_dev(int64_t n, const double* n2, const double* x, double* y, hipStream_t s) {
-  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_axpy_sqrt_dev, dim3(nb(n)), dim3(kT), 0, s, n, n2, x, y);
+  hipLaunchKernelGGL(k_lz_next, dim3(nb(n)), dim3(kT), 0, s, n, w, n2, sqd, vn, t);
   GLLMG_HIP(hipGetLastError());
 }
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s) {

@@ -436,20 +436,18 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
   vec_sqrt(N, L.dinv64, sqd, s);
   start_vector(L.g, P->cfg.eig_seed, l, V[0], s);
   dot(0, N, V[0], V[0], P->part, P->scal + 8, s);
-  vec_div_sqrt_dev(N, V[0], P->scal + 8, V[0], s);
+  lanczos_next(N, V[0], P->scal + 8, sqd, V[0], t, s);  // V_0 normalized, t = sqd V_0
   // The whole recurrence is enqueued without reading anything back: beta_j = |w_j| stays on
   // the device. A breakdown (|w_j| ~ 0) is found afterwards on the host, where the
-  // coefficients past it are discarded.
+  // coefficients past it are discarded. Per step: w = sqd A t, alpha_j = V_j . w,
+  // w -= alpha_j V_j + beta_{j-1} V_{j-1}, w -= V (V^T w), |w|^2, V_{j+1} = w / |w| and the
+  // next step's t = sqd V_{j+1}.
   for (int j = 0; j < m; ++j) {
-    vec_scale_mul(0, N, 1.0, sqd, V[j], t, s);
     apply_level(P, l, 0, 0, t, w, s);
-    vec_scale_mul(0, N, 1.0, sqd, w, w, s);
-    dot(0, N, V[j], w, P->part, alpha + j, s);
-    vec_axpy_dev(N, alpha + j, -1.0, V[j], w, s);
-    if (j > 0) vec_axpy_sqrt_dev(N, n2 + (j - 1), V[j - 1], w, s);
-    block_orthogonalize(N, V[0], N, j + 1, w, part, coef, s);
-    dot(0, N, w, w, P->part, n2 + j, s);
-    if (j + 1 < m) vec_div_sqrt_dev(N, w, n2 + j, V[j + 1], s);
+    lanczos_scale_dot(N, sqd, w, V[j], P->part, alpha + j, s);
+    lanczos_axpy2(N, alpha + j, V[j], j > 0 ? n2 + (j - 1) : nullptr, j > 0 ? V[j - 1] : nullptr, w, s);
+    block_orthogonalize_norm(N, V[0], N, j + 1, w, part, coef, P->part, n2 + j, s);
+    if (j + 1 < m) lanczos_next(N, w, n2 + j, sqd, V[j + 1], t, s);
   }
   std::vector<double> ha(m), hn(m);
   GLLMG_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));

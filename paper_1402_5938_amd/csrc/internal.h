@@ -384,6 +384,8 @@ void ir_update_p(int64_t n, const double* scal, int i_num, int i_den, float* p, 
 void ir_add(int64_t n, const float* e, const double* rr, double* x, hipStream_t s);
 void pcg_update_p(int64_t n, const double* scal, int i_num, int i_den, double* p,
                   const double* z, hipStream_t s);
+// e = 1 at the interior nodes whose interior indices are (ox, oy, oz) mod c, 0 elsewhere
+void color_unit_vector(const Grid& g, int c, int ox, int oy, int oz, double* e, hipStream_t s);
 void start_vector(const Grid& g, uint64_t seed, int level, double* v, hipStream_t s);
 
 }  // namespace gllmg

@@ -235,6 +235,22 @@ __global__ void k_start_vector(Grid g, uint64_t seed, int level, double* __restr
   v[t] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
 }
 
+// e = the sum of the unit vectors of the interior nodes whose interior indices (g_a - 1) are
+// o_a mod c along every axis (one color of the coarse operator's assembly)
+__global__ void k_color_unit(Grid g, int c, int ox, int oy, int oz, double* e) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= g.N) return;
+  const int64_t nx = g.nn[0], ny = g.nn[1];
+  const int gx = (int)(t % nx);
+  const int64_t r = t / nx;
+  const int gy = (int)(r % ny);
+  const int gz = g.dim == 3 ? (int)(r / ny) : 0;
+  bool hit = gx >= 1 && gx <= nx - 2 && gy >= 1 && gy <= ny - 2 && (gx - 1) % c == ox &&
+             (gy - 1) % c == oy;
+  if (g.dim == 3) hit = hit && gz >= 1 && gz <= g.nn[2] - 2 && (gz - 1) % c == oz;
+  e[t] = hit ? 1.0 : 0.0;
+}
+
 }  // namespace
 
 void launch_geometry(const Level& L, const double* xn, const double* mun, double* G64,
@@ -291,6 +307,11 @@ void launch_dinv(const Grid& g, const double* diag, double* d64, float* d32, int
 
 void start_vector(const Grid& g, uint64_t seed, int level, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_start_vector, dim3(nblocks(g.N)), dim3(kThreads), 0, s, g, seed, level, v);
+  GLLMG_HIP(hipGetLastError());
+}
+
+void color_unit_vector(const Grid& g, int c, int ox, int oy, int oz, double* e, hipStream_t s) {
+  hipLaunchKernelGGL(k_color_unit, dim3(nblocks(g.N)), dim3(kThreads), 0, s, g, c, ox, oy, oz, e);
   GLLMG_HIP(hipGetLastError());
 }
 

@@ -261,7 +261,7 @@ constexpr int kMdChunk = 8;
 // part[v kMdBlocks + b] = the strided partial of V_v . w of block b, v = kMdChunk blockIdx.y + q
 __global__ void __launch_bounds__(kT)
 k_multidot(int64_t n, const double* V, int64_t ld, int c, const double* w, double* part) {
-  __shared__ double sh[kT];
+  __shared__ double sh[kMdChunk][kT];
   const int v0 = blockIdx.y * kMdChunk;
   double acc[kMdChunk];
 #pragma unroll
@@ -272,17 +272,20 @@ k_multidot(int64_t n, const double* V, int64_t ld, int c, const double* w, doubl
     for (int q = 0; q < kMdChunk; ++q)
       if (v0 + q < c) acc[q] += V[(int64_t)(v0 + q) * ld + i] * wi;
   }
+  // the kMdChunk trees side by side (each the same tree as one at a time: bitwise the same
+  // sums, with one barrier per level of the tree instead of one per level and coefficient)
 #pragma unroll
-  for (int q = 0; q < kMdChunk; ++q) {
-    sh[threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int h = kT / 2; h > 0; h >>= 1) {
-      if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-      __syncthreads();
+  for (int q = 0; q < kMdChunk; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int h = kT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+#pragma unroll
+      for (int q = 0; q < kMdChunk; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + h];
     }
-    if (threadIdx.x == 0 && v0 + q < c) part[(int64_t)(v0 + q) * kMdBlocks + blockIdx.x] = sh[0];
     __syncthreads();
   }
+  if ((int)threadIdx.x < kMdChunk && v0 + (int)threadIdx.x < c)
+    part[(int64_t)(v0 + threadIdx.x) * kMdBlocks + blockIdx.x] = sh[threadIdx.x][0];
 }
 
 // coef[v] = sum over the np blocks of part[v kMdBlocks + b] (block v)

@@ -1,10 +1,12 @@
 // Host side of the library: hierarchy planning, workspace layout, setup, smoothers, V-cycle,
 // solvers and the C ABI declared in include/gllmg.h.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <deque>
 #include <exception>
 #include <map>
 #include <memory>
@@ -394,22 +396,23 @@ void residual(gllmg_problem* P, int l, int pr, const void* b, const void* x, voi
 // function c evaluated at fine node i of child `ch`, whose reference coordinate in the coarse
 // element is xi_i (p-coarsening: same element) or (xi_i + 2 ch - 1) / 2 (h-coarsening: the
 // fine element is half ch of the coarse one along the axis).
-void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s) {
+// (the host tables go into k64 and k32, which the caller keeps until the stream has copied them)
+void build_transfer_tables(gllmg_problem* P, int l, hipStream_t s, std::deque<std::vector<double>>& k64,
+                           std::deque<std::vector<float>>& k32) {
   Level& F = P->L[l];
   Level& C = P->L[l + 1];
   const RefElem& rf = P->re[l];
   const RefElem& rc = P->re[l + 1];
   const int nf = F.n, nc = C.n, nch = F.tp.nch;
-  std::vector<double> Pl((size_t)nch * nf * nc);
+  auto& Pl = k64.emplace_back((size_t)nch * nf * nc);
   for (int ch = 0; ch < nch; ++ch)
     for (int i = 0; i < nf; ++i) {
       const double xc = nch == 1 ? rf.xi[i] : (rf.xi[i] + 2.0 * ch - 1.0) / 2.0;
       lagrange_at(rc, xc, &Pl[((size_t)ch * nf + i) * nc]);
     }
-  std::vector<float> Pl32(Pl.begin(), Pl.end());
+  const auto& Pl32 = k32.emplace_back(Pl.begin(), Pl.end());
   GLLMG_HIP(hipMemcpyAsync(F.tp.P64, Pl.data(), sizeof(double) * Pl.size(), hipMemcpyHostToDevice, s));
   GLLMG_HIP(hipMemcpyAsync(F.tp.P32, Pl32.data(), sizeof(float) * Pl32.size(), hipMemcpyHostToDevice, s));
-  GLLMG_HIP(hipStreamSynchronize(s));  // the host tables go out of scope
 }
 
 // lambda_max of D^{-1} A (§3.2.2: a few Arnoldi steps in setup): Lanczos on the symmetric
@@ -477,36 +480,47 @@ void build_coarse_inverse(gllmg_problem* P, hipStream_t s) {
   Level& L = P->L.back();
   const int64_t N = L.g.N, ni = L.nint;
   const int dim = L.g.dim, p = L.g.p, c = 2 * p + 1;
-  double* e = (double*)P->scratch;
-  double* y = e + N;
   const int nx = L.g.nn[0], ny = L.g.nn[1];
   const int mx = nx - 2, my = ny - 2, mz = dim == 3 ? L.g.nn[2] - 2 : 1;
   auto node = [&](int jx, int jy, int jz) {
     return (jx + 1) + (int64_t)nx * ((jy + 1) + (int64_t)ny * (dim == 3 ? jz + 1 : 0));
   };
   auto row = [&](int jx, int jy, int jz) { return jx + (int64_t)mx * (jy + (int64_t)my * jz); };
-  std::vector<double> A((size_t)ni * ni, 0.0), eh(N), col(N);
+  // the colors (ox, oy, oz); their products go B at a time into the scratch region (the
+  // color vector e, then B product columns) and come back in one copy per batch
+  std::vector<std::array<int, 3>> colors;
   for (int oz = 0; oz < std::min(c, mz); ++oz)
     for (int oy = 0; oy < std::min(c, my); ++oy)
-      for (int ox = 0; ox < std::min(c, mx); ++ox) {
-        std::fill(eh.begin(), eh.end(), 0.0);
-        for (int jz = oz; jz < mz; jz += c)
-          for (int jy = oy; jy < my; jy += c)
-            for (int jx = ox; jx < mx; jx += c) eh[node(jx, jy, jz)] = 1.0;
-        GLLMG_HIP(hipMemcpyAsync(e, eh.data(), sizeof(double) * N, hipMemcpyHostToDevice, s));
-        apply_level(P, (int)P->L.size() - 1, 0, 0, e, y, s);
-        GLLMG_HIP(hipMemcpyAsync(col.data(), y, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-        GLLMG_HIP(hipStreamSynchronize(s));
-        for (int jz = oz; jz < mz; jz += c)
-          for (int jy = oy; jy < my; jy += c)
-            for (int jx = ox; jx < mx; jx += c) {
-              const int64_t j = row(jx, jy, jz);
-              for (int iz = std::max(0, jz - p); iz <= std::min(mz - 1, jz + p); ++iz)
-                for (int iy = std::max(0, jy - p); iy <= std::min(my - 1, jy + p); ++iy)
-                  for (int ix = std::max(0, jx - p); ix <= std::min(mx - 1, jx + p); ++ix)
-                    A[(size_t)row(ix, iy, iz) * ni + j] = col[node(ix, iy, iz)];
-            }
-      }
+      for (int ox = 0; ox < std::min(c, mx); ++ox) colors.push_back({ox, oy, oz});
+  const int64_t cap = (int64_t)(P->scratch_bytes / sizeof(double)) / N - 1;
+  GLLMG_CHECK(cap >= 1, GLLMG_ENOMEM, "scratch region too small for the coarse assembly");
+  const int B = (int)std::min<int64_t>(cap, (int64_t)colors.size());
+  double* e = (double*)P->scratch;
+  double* y = e + N;
+  std::vector<double> A((size_t)ni * ni, 0.0), cols((size_t)B * N);
+  for (size_t c0 = 0; c0 < colors.size(); c0 += B) {
+    const int nb = (int)std::min<size_t>(B, colors.size() - c0);
+    for (int b = 0; b < nb; ++b) {
+      const auto& o = colors[c0 + b];
+      color_unit_vector(L.g, c, o[0], o[1], o[2], e, s);
+      apply_level(P, (int)P->L.size() - 1, 0, 0, e, y + (size_t)b * N, s);
+    }
+    GLLMG_HIP(hipMemcpyAsync(cols.data(), y, sizeof(double) * N * nb, hipMemcpyDeviceToHost, s));
+    GLLMG_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b) {
+      const auto& o = colors[c0 + b];
+      const double* col = cols.data() + (size_t)b * N;
+      for (int jz = o[2]; jz < mz; jz += c)
+        for (int jy = o[1]; jy < my; jy += c)
+          for (int jx = o[0]; jx < mx; jx += c) {
+            const int64_t j = row(jx, jy, jz);
+            for (int iz = std::max(0, jz - p); iz <= std::min(mz - 1, jz + p); ++iz)
+              for (int iy = std::max(0, jy - p); iy <= std::min(my - 1, jy + p); ++iy)
+                for (int ix = std::max(0, jx - p); ix <= std::min(mx - 1, jx + p); ++ix)
+                  A[(size_t)row(ix, iy, iz) * ni + j] = col[node(ix, iy, iz)];
+          }
+    }
+  }
   // symmetrize the rounding of the matrix-free products
   for (int64_t i = 0; i < ni; ++i)
     for (int64_t j = 0; j < i; ++j) {
@@ -597,31 +611,40 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
   GLLMG_HIP(hipMemsetAsync(P->flag, 0, sizeof(int) * 4, s));
   GLLMG_HIP(hipMemsetAsync(P->zeros, 0, 64, s));
   P->re.clear();
+  P->re.reserve(P->L.size());
+  // host images of the per-level tables, alive until the stream has copied them (one
+  // synchronization after the loop)
+  std::deque<std::vector<double>> keep64;
+  std::deque<std::vector<float>> keep32;
+  struct SyncFirst {  // destroyed before the images, also when setup throws
+    hipStream_t s;
+    ~SyncFirst() { (void)hipStreamSynchronize(s); }
+  } sync_first{s};
   for (auto& L : P->L) {
     P->re.push_back(ref_element(L.g.p));
     RefElem& r = P->re.back();
     if (L.gauss) {
       gauss_rule(r);
-      std::vector<float> I32(r.Iq.begin(), r.Iq.end()), Dq32(r.Dq.begin(), r.Dq.end());
+      const auto& I32 = keep32.emplace_back(r.Iq.begin(), r.Iq.end());
+      const auto& Dq32 = keep32.emplace_back(r.Dq.begin(), r.Dq.end());
       GLLMG_HIP(hipMemcpyAsync(L.Iq64, r.Iq.data(), sizeof(double) * r.Iq.size(), hipMemcpyHostToDevice, s));
       GLLMG_HIP(hipMemcpyAsync(L.Iq32, I32.data(), sizeof(float) * I32.size(), hipMemcpyHostToDevice, s));
       GLLMG_HIP(hipMemcpyAsync(L.Dq64, r.Dq.data(), sizeof(double) * r.Dq.size(), hipMemcpyHostToDevice, s));
       GLLMG_HIP(hipMemcpyAsync(L.Dq32, Dq32.data(), sizeof(float) * Dq32.size(), hipMemcpyHostToDevice, s));
       GLLMG_HIP(hipMemcpyAsync(L.wg64, r.wg.data(), sizeof(double) * r.wg.size(), hipMemcpyHostToDevice, s));
-      GLLMG_HIP(hipStreamSynchronize(s));
     }
     const int n = L.n;
-    std::vector<double> DDt(r.D);  // D, then its transpose
+    auto& DDt = keep64.emplace_back(r.D);  // D, then its transpose
     DDt.resize((size_t)2 * n * n);
     for (int a = 0; a < n; ++a)
       for (int b = 0; b < n; ++b) DDt[(size_t)n * n + a * n + b] = r.D[(size_t)b * n + a];
-    std::vector<float> D32(DDt.begin(), DDt.end());
+    const auto& D32 = keep32.emplace_back(DDt.begin(), DDt.end());
     GLLMG_HIP(hipMemcpyAsync(L.D64, DDt.data(), sizeof(double) * DDt.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.D32, D32.data(), sizeof(float) * D32.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.xi64, r.xi.data(), sizeof(double) * r.xi.size(), hipMemcpyHostToDevice, s));
     GLLMG_HIP(hipMemcpyAsync(L.w64, r.w.data(), sizeof(double) * r.w.size(), hipMemcpyHostToDevice, s));
-    GLLMG_HIP(hipStreamSynchronize(s));  // DDt and D32 go out of scope
   }
+  GLLMG_HIP(hipStreamSynchronize(s));  // the per-level tables are on the device
   for (size_t l = 0; l < P->L.size(); ++l) {
     Level& L = P->L[l];
     double* wdet = l == 0 ? (double*)P->scratch : nullptr;
@@ -660,29 +683,29 @@ void setup_impl(gllmg_problem* P, const gllmg_field* map, const gllmg_field* mu,
                       P->flag, s);
       if (l == 0) launch_gather_full(L, wdet, P->mass, s);
     }
-    check_flag(P, s);
     double* diag = (double*)P->scratch;
     launch_diag(L, diag, (double*)P->F, s);
     launch_dinv(L.g, diag, L.dinv64, f32 ? L.dinv32 : nullptr, P->flag, s);
-    check_flag(P, s);
     if (c.smoother == GLLMG_SMOOTH_L1_JACOBI) {
       launch_l1_rowsum(L, diag, s);
       launch_dinv(L.g, diag, L.l1inv64, f32 ? L.l1inv32 : nullptr, P->flag, s);
-      check_flag(P, s);
     }
     if (c.smoother == GLLMG_SMOOTH_BLOCK_JACOBI) {
       launch_block_setup(L, L.Binv64, P->flag, s);
-      check_flag(P, s);
       if (f32) cast_64_32(L.g.E * (int64_t)block_slots(L) * block_slots(L), L.Binv64, L.Binv32, s);
     }
   }
-  for (size_t l = low_first(P) ? 1 : 0; l + 1 < P->L.size(); ++l) build_transfer_tables(P, (int)l, s);
+  // the checks of every level at once (the flag bits accumulate; the kernels above run to the
+  // end on invalid values without harm, and check_flag reports the first kind of failure)
+  check_flag(P, s);
+  for (size_t l = low_first(P) ? 1 : 0; l + 1 < P->L.size(); ++l)
+    build_transfer_tables(P, (int)l, s, keep64, keep32);
   for (size_t l = 0; l < P->L.size(); ++l)
     if (P->L[l].has_coarse || !P->L[l].Ainv64)
       P->L[l].lmax = c.cheb_safety * lanczos_lmax(P, (int)l, s);
   if (P->L.back().Ainv64) build_coarse_inverse(P, s);
   for (auto& L : P->L) L.applies = 0;
-  GLLMG_HIP(hipStreamSynchronize(s));
+  GLLMG_HIP(hipStreamSynchronize(s));  // (also the end of the transfer tables' copies)
 }
 
 // ------------------------------------------------------------------ smoothers and cycles

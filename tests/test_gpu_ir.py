@@ -75,3 +75,18 @@ def test_ir_argument_errors():
     _, w1 = gllmg.plan(gllmg.make_config(3, (2, 2, 2), 4, "p", vcycle_prec="f32", ir_inner=4))
     assert w0 <= w1 <= w0 + 5 * 4 * G.nnodes(0) + 256
     G.close()
+
+
+def test_ir_maxit_below_the_inner_length():
+    """maxit < k: one refinement step of maxit CG steps, ENOTCONV (not raised by default), the
+    history holding the two residual norms and the iteration count maxit."""
+    import torch
+    from paper_1402_5938_amd import gllmg
+    mp, mu = inputs.map_warp_sine(0.05), inputs.mu_exp_sine_product(2.0)
+    G = gllmg.Problem(gllmg.make_config(3, (2, 2, 2), 4, "p", vcycle_prec="f32", ir_inner=8), mp, mu)
+    b = G.rhs(torch.ones(G.nnodes(0), dtype=torch.float64, device="cuda"))
+    x = torch.zeros_like(b)
+    r = G.solve(b, x, mode="ir", rtol=1e-14, maxit=3)
+    assert r.status == gllmg.ENOTCONV and not r.converged
+    assert r.iters == 3 and len(r.history) == 2 and r.history[1] < r.history[0]
+    G.close()

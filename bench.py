@@ -265,7 +265,7 @@ def workload_batch(a):
 
 def workload_serve(a):
     """Poisson-arrival stream (mean a.serve_rate req/s; 200 by default, the serving workload's
-    rate, which is beyond the measured capacity of about 110 solves/s, so the queue grows) of
+    rate, which is beyond the measured capacity of about 150 solves/s, so the queue grows) of
     mixed 2D/3D solves to 1e-8 under an HBM budget; p50/p99 latency and solves/s over the first
     a.serve_s seconds of arrivals."""
     from paper_1402_5938_amd import inputs
@@ -283,6 +283,55 @@ def workload_serve(a):
     srv.close()
     return {"workload": f"serve: {len(trace)} requests over {a.serve_s} s at {a.serve_rate:g} req/s, "
                         f"budget {a.hbm_gb} GiB", **rep}
+
+
+def workload_requests(a):
+    """The serving stream's requests (seed 0, 200 req/s) one at a time, without the server: the
+    first a.requests of them set up, then solved alone (FP32 V-cycle in FP64 PCG to 1e-8), after
+    one untimed pass over the same requests (set up, solved, destroyed) so that every kernel's
+    code is loaded. Per-request setup (hierarchy, geometry, diagonal, Lanczos bounds, coarse
+    inverse) and solve times: the GPU work a served request costs when nothing overlaps it."""
+    import numpy as np
+    import torch
+
+    from paper_1402_5938_amd import gllmg, inputs
+    probs = [r.problem for r in inputs.serving_trace(seed=0, rate=200.0, duration_s=60.0,
+                                                     max_requests=a.requests)]
+
+    def rhs(G, p):
+        return G.rhs(torch.from_numpy(p.nodal_rhs()).cuda())
+
+    for p in probs:
+        G = gllmg.Problem.from_inputs(p)
+        G.solve(rhs(G, p), rtol=p.rtol, maxit=p.maxit)
+        G.close()
+    torch.cuda.synchronize()
+    Gs, t_set, t_sol, its = [], [], [], []
+    for p in probs:
+        t0 = time.perf_counter()
+        Gs.append(gllmg.Problem.from_inputs(p))
+        torch.cuda.synchronize()
+        t_set.append(time.perf_counter() - t0)
+    for G, p in zip(Gs, probs):
+        b = rhs(G, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = G.solve(b, rtol=p.rtol, maxit=p.maxit)
+        torch.cuda.synchronize()
+        t_sol.append(time.perf_counter() - t0)
+        its.append(r.iters)
+        assert r.converged, (p.name, r)
+    nodes = [G.nnodes(0) for G in Gs]
+    for G in Gs:
+        G.close()
+    ms = lambda v: round(1e3 * float(v), 3)  # noqa: E731
+    return {"workload": f"requests: the first {len(probs)} requests of the serving stream, set up "
+                        "and solved one at a time", "requests": len(probs),
+            "total_nodes": int(sum(nodes)), "setup_total_s": float(sum(t_set)),
+            "solve_total_s": float(sum(t_sol)), "setup_mean_ms": ms(np.mean(t_set)),
+            "setup_median_ms": ms(np.median(t_set)), "setup_max_ms": ms(np.max(t_set)),
+            "solve_mean_ms": ms(np.mean(t_sol)), "solve_median_ms": ms(np.median(t_sol)),
+            "solve_max_ms": ms(np.max(t_sol)), "mean_iters": float(np.mean(its))}
 
 
 SMOOTHER_CASES = {"chebyshev": (4, 4), "jacobi": (3, 3), "ssor": (2, 1), "l1jacobi": (3, 3),
@@ -528,11 +577,12 @@ def extra_workloads(a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="config2", choices=["config2", "mixed", "batch", "serve", "apply", "sweep",
-                                                          "smoothers", "gauss", "lowprec"])
+                                                          "smoothers", "gauss", "lowprec", "requests"])
     ap.add_argument("--smoothers", default="chebyshev,jacobi,ssor")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--serve-s", type=float, default=2.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--requests", type=int, default=150, help="requests workload: how many requests")
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -563,7 +613,7 @@ def main():
         fn = {"mixed": workload_mixed, "batch": workload_batch, "serve": workload_serve,
               "apply": workload_apply, "sweep": workload_sweep,
               "smoothers": workload_smoothers, "gauss": workload_gauss,
-              "lowprec": workload_lowprec}[a.workload]
+              "lowprec": workload_lowprec, "requests": workload_requests}[a.workload]
         print(json.dumps(fn(a)))
         return
     # the configuration's order sequence 8 -> 4 -> 2 -> 1, the exact solve on the first-order

@@ -358,8 +358,10 @@ void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* 
                    double* hrr = nullptr);
 // Lanczos: w -= V (V^T w) against the c basis vectors V_v = V + v ld (one classical
 // Gram-Schmidt pass: all coefficients from the same w, fixed-order sums), then *n2 = w . w.
-// part holds c kMdBlocks doubles, coef c, npart kDotBlocks (the norm's partials).
-constexpr int kMdBlocks = 256;
+// part holds c kMdBlocks doubles, coef c, npart kDotBlocks (the norm's partials). The
+// multi-dot takes as many workgroups as a dot product (four per compute unit at most sizes):
+// with one per compute unit it read a 7M-node basis at 0.2 TB/s.
+constexpr int kMdBlocks = kDotBlocks;
 void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, double* w,
                               double* part, double* coef, double* npart, double* n2, hipStream_t s);
 // Fused vector passes of a Lanczos step (the same arithmetic and reduction order as the

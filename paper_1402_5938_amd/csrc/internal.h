@@ -357,22 +357,26 @@ void pcg_update_xr(int64_t n, const double* scal, int i_num, int i_den, double* 
                    const double* p, const double* h, double* partials, double* rr, hipStream_t s,
                    double* hrr = nullptr);
 // Lanczos: w -= V (V^T w) against the c basis vectors V_v = V + v ld (one classical
-// Gram-Schmidt pass: all coefficients from the same w, fixed-order sums), then *n2 = w . w.
-// part holds c kMdBlocks doubles, coef c, npart kDotBlocks (the norm's partials). The
-// multi-dot takes as many workgroups as a dot product (four per compute unit at most sizes):
-// with one per compute unit it read a 7M-node basis at 0.2 TB/s.
+// Gram-Schmidt pass: all coefficients from the same w, fixed-order sums), leaving the dot
+// product's partials of w . w in npart (dot_grid(n) of them). part holds c kMdBlocks doubles,
+// coef c. The multi-dot takes as many workgroups as a dot product: with one per compute unit
+// it read a 57M-node basis at 1.6 TB/s.
 constexpr int kMdBlocks = kDotBlocks;
-void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, double* w,
-                              double* part, double* coef, double* npart, double* n2, hipStream_t s);
-// Fused vector passes of a Lanczos step (the same arithmetic and reduction order as the
-// separate calls): w = sqd w then *res = v . w (part: kDotBlocks doubles); w = w - *alpha vj
-// - sqrt(*n2) vjm1 (the last term only if vjm1); vn = w / sqrt(*n2) and t = sqd vn.
+void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
+                         double* coef, double* npart, hipStream_t s);
+// Fused vector passes of a Lanczos step (the same arithmetic and reduction order as separate
+// dot, sum and update kernels; each sum of np partials is formed by every workgroup that needs
+// it, in the final-sum kernel's order, and stored by the first): w = sqd w with the partials of
+// v . w in part (dot_grid(n) of them); *alpha = the sum of np partials, then w = w - *alpha vj
+// - sqrt(*n2) vjm1 (the last term only if vjm1); *n2 = the sum of np partials (np = 0: *n2 is
+// given), then vn = w / sqrt(*n2) and t = sqd vn; *out = the sum of np partials.
 void lanczos_scale_dot(int64_t n, const double* sqd, double* w, const double* v, double* part,
-                       double* res, hipStream_t s);
-void lanczos_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
-                   const double* vjm1, double* w, hipStream_t s);
-void lanczos_next(int64_t n, const double* w, const double* n2, const double* sqd, double* vn,
-                  double* t, hipStream_t s);
+                       hipStream_t s);
+void lanczos_axpy2(int64_t n, const double* part, int np, double* alpha, const double* vj,
+                   const double* n2, const double* vjm1, double* w, hipStream_t s);
+void lanczos_next(int64_t n, const double* w, const double* part, int np, double* n2,
+                  const double* sqd, double* vn, double* t, hipStream_t s);
+void sum_partials(const double* part, int np, double* out, hipStream_t s);
 // dst[k cnt + i] = scal[i] (src = the first problem's scalars) for every active problem k of
 // the current launch group (dst is not shifted: one buffer for the group)
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s);

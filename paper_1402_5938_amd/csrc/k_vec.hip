@@ -315,14 +315,27 @@ __global__ void __launch_bounds__(kT) k_lz_scale_dot(int64_t n, const double* sq
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// w = w - alpha vj, then (vjm1 != nullptr) w = w - sqrt(*n2) vjm1
-__global__ void k_lz_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
-                           const double* vjm1, double* w) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double wi = w[i] + (-1.0 * alpha[0]) * vj[i];
-  if (vjm1) wi = wi + (-sqrt(n2[0])) * vjm1[i];
-  w[i] = wi;
+// The sum of np partials, formed by every workgroup in k_sum_final's order (bitwise its
+// result); the first workgroup also stores it to *out.
+__device__ inline double sum_in_block(const double* part, int np, double* out) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += kT) acc += part[i];
+  const double s = block_sum(acc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *out = s;
+  return s;
+}
+
+// alpha = the sum of the np partials; w = w - alpha vj, then (vjm1 != nullptr)
+// w = w - sqrt(*n2) vjm1
+__global__ void __launch_bounds__(kT) k_lz_axpy2(int64_t n, const double* part, int np,
+                                                 double* alpha, const double* vj, const double* n2,
+                                                 const double* vjm1, double* w) {
+  const double a = sum_in_block(part, np, alpha);
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    double wi = w[i] + (-1.0 * a) * vj[i];
+    if (vjm1) wi = wi + (-sqrt(n2[0])) * vjm1[i];
+    w[i] = wi;
+  }
 }
 
 // w -= sum_v coef[v] V_v (v ascending); partials of w . w
@@ -339,17 +352,17 @@ __global__ void __launch_bounds__(kT) k_md_sub_dot(int64_t n, const double* V, i
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// vn = w / sqrt(*n2); t = (1 sqd) vn (w and vn may be the same vector)
-__global__ void k_lz_next(int64_t n, const double* w, const double* n2, const double* sqd,
-                          double* vn, double* t) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const double v = w[i] / sqrt(n2[0]);
-  vn[i] = v;
-  t[i] = 1.0 * sqd[i] * v;
+// nn = the sum of the np partials (np = 0: nn = *n2); vn = w / sqrt(nn); t = (1 sqd) vn (w and
+// vn may be the same vector)
+__global__ void __launch_bounds__(kT) k_lz_next(int64_t n, const double* w, const double* part, int np,
+                                                double* n2, const double* sqd, double* vn, double* t) {
+  const double nn = np > 0 ? sum_in_block(part, np, n2) : n2[0];
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
+    const double v = w[i] / sqrt(nn);
+    vn[i] = v;
+    t[i] = 1.0 * sqd[i] * v;
+  }
 }
-
-
 
 // dst[k cnt + i] = src[i] of problem k (blockIdx.y): a launch group's scalars side by side
 __global__ void k_collect(const double* src, int cnt, double* dst, Grp gp) {
@@ -665,23 +678,20 @@ void pcg_update_xr(int64_t n, const double* scal, int inum, int iden, double* x,
   GLLMG_HIP(hipGetLastError());
 }
 void lanczos_scale_dot(int64_t n, const double* sqd, double* w, const double* v, double* part,
-                       double* res, hipStream_t s) {
+                       hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  const int g = dot_grid(n);
-  hipLaunchKernelGGL(k_lz_scale_dot, dim3(g), dim3(kT), 0, s, n, sqd, w, v, part);
-  GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_sum_final<false>), dim3(1), dim3(kT), 0, s, (const double*)part, g, res,
-                     (double*)nullptr, Grp{nullptr, nullptr});
+  hipLaunchKernelGGL(k_lz_scale_dot, dim3(dot_grid(n)), dim3(kT), 0, s, n, sqd, w, v, part);
   GLLMG_HIP(hipGetLastError());
 }
-void lanczos_axpy2(int64_t n, const double* alpha, const double* vj, const double* n2,
-                   const double* vjm1, double* w, hipStream_t s) {
+void lanczos_axpy2(int64_t n, const double* part, int np, double* alpha, const double* vj,
+                   const double* n2, const double* vjm1, double* w, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_lz_axpy2, dim3(nb(n)), dim3(kT), 0, s, n, alpha, vj, n2, vjm1, w);
+  GLLMG_CHECK(np >= 1 && np <= kDotBlocks, GLLMG_EINVAL, "partial count out of range");
+  hipLaunchKernelGGL(k_lz_axpy2, dim3(dot_grid(n)), dim3(kT), 0, s, n, part, np, alpha, vj, n2, vjm1, w);
   GLLMG_HIP(hipGetLastError());
 }
-void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, double* w,
-                              double* part, double* coef, double* npart, double* n2, hipStream_t s) {
+void block_orthogonalize(int64_t n, const double* V, int64_t ld, int c, double* w, double* part,
+                         double* coef, double* npart, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
   GLLMG_CHECK(c >= 1, GLLMG_EINVAL, "empty basis");
   const int g = (int)std::min<int64_t>(kMdBlocks, std::max<int64_t>(1, (n + kT - 1) / kT));
@@ -690,17 +700,21 @@ void block_orthogonalize_norm(int64_t n, const double* V, int64_t ld, int c, dou
   GLLMG_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_md_final, dim3(c), dim3(kT), 0, s, (const double*)part, g, coef);
   GLLMG_HIP(hipGetLastError());
-  const int gd = dot_grid(n);
-  hipLaunchKernelGGL(k_md_sub_dot, dim3(gd), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w, npart);
-  GLLMG_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_sum_final<false>), dim3(1), dim3(kT), 0, s, (const double*)npart, gd, n2,
-                     (double*)nullptr, Grp{nullptr, nullptr});
+  hipLaunchKernelGGL(k_md_sub_dot, dim3(dot_grid(n)), dim3(kT), 0, s, n, V, ld, c, (const double*)coef, w,
+                     npart);
   GLLMG_HIP(hipGetLastError());
 }
-void lanczos_next(int64_t n, const double* w, const double* n2, const double* sqd, double* vn,
-                  double* t, hipStream_t s) {
+void lanczos_next(int64_t n, const double* w, const double* part, int np, double* n2,
+                  const double* sqd, double* vn, double* t, hipStream_t s) {
   GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
-  hipLaunchKernelGGL(k_lz_next, dim3(nb(n)), dim3(kT), 0, s, n, w, n2, sqd, vn, t);
+  GLLMG_CHECK(np >= 0 && np <= kDotBlocks && (np == 0 || part), GLLMG_EINVAL, "partial count out of range");
+  hipLaunchKernelGGL(k_lz_next, dim3(dot_grid(n)), dim3(kT), 0, s, n, w, part, np, n2, sqd, vn, t);
+  GLLMG_HIP(hipGetLastError());
+}
+void sum_partials(const double* part, int np, double* out, hipStream_t s) {
+  GLLMG_CHECK(!launch_group(), GLLMG_EINVAL, "kernel without launch-group support");
+  hipLaunchKernelGGL((k_sum_final<false>), dim3(1), dim3(kT), 0, s, part, np, out, (double*)nullptr,
+                     Grp{nullptr, nullptr});
   GLLMG_HIP(hipGetLastError());
 }
 void collect_scalars(const double* src, int cnt, double* dst, hipStream_t s) {

@@ -439,7 +439,8 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
   vec_sqrt(N, L.dinv64, sqd, s);
   start_vector(L.g, P->cfg.eig_seed, l, V[0], s);
   dot(0, N, V[0], V[0], P->part, P->scal + 8, s);
-  lanczos_next(N, V[0], P->scal + 8, sqd, V[0], t, s);  // V_0 normalized, t = sqd V_0
+  lanczos_next(N, V[0], nullptr, 0, P->scal + 8, sqd, V[0], t, s);  // V_0 normalized, t = sqd V_0
+  const int np = dot_grid(N);  // partial sums of each dot product (P->part holds them)
   // The whole recurrence is enqueued without reading anything back: beta_j = |w_j| stays on
   // the device. A breakdown (|w_j| ~ 0) is found afterwards on the host, where the
   // coefficients past it are discarded. Per step: w = sqd A t, alpha_j = V_j . w,
@@ -447,10 +448,14 @@ double lanczos_lmax(gllmg_problem* P, int l, hipStream_t s) {
   // next step's t = sqd V_{j+1}.
   for (int j = 0; j < m; ++j) {
     apply_level(P, l, 0, 0, t, w, s);
-    lanczos_scale_dot(N, sqd, w, V[j], P->part, alpha + j, s);
-    lanczos_axpy2(N, alpha + j, V[j], j > 0 ? n2 + (j - 1) : nullptr, j > 0 ? V[j - 1] : nullptr, w, s);
-    block_orthogonalize_norm(N, V[0], N, j + 1, w, part, coef, P->part, n2 + j, s);
-    if (j + 1 < m) lanczos_next(N, w, n2 + j, sqd, V[j + 1], t, s);
+    lanczos_scale_dot(N, sqd, w, V[j], P->part, s);
+    lanczos_axpy2(N, P->part, np, alpha + j, V[j], j > 0 ? n2 + (j - 1) : nullptr,
+                  j > 0 ? V[j - 1] : nullptr, w, s);
+    block_orthogonalize(N, V[0], N, j + 1, w, part, coef, P->part, s);
+    if (j + 1 < m)
+      lanczos_next(N, w, P->part, np, n2 + j, sqd, V[j + 1], t, s);
+    else
+      sum_partials(P->part, np, n2 + j, s);
   }
   std::vector<double> ha(m), hn(m);
   GLLMG_HIP(hipMemcpyAsync(ha.data(), alpha, sizeof(double) * m, hipMemcpyDeviceToHost, s));
